@@ -33,6 +33,8 @@
  *   - 10 Ruiz passes (inf-norm) then one Pock-Chambolle pass with alpha = 1;
  *   - KKT_omega weights omega^2 and 1/omega^2 as printed;
  *   - at an epoch's first evaluation the previous candidate KKT is KKT(z^{n,0});
+ *   - the candidate comparison KKT(current) < KKT(average) treats a relative
+ *     difference below 1e-12 as a tie, which goes to the average;
  *   - the start is proj_X(0), y = 0.
  * Sums are taken in a fixed blocked order (blocks of 4096, serial within and
  * across blocks) so that results do not depend on the thread count.  Built
@@ -649,7 +651,10 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
     /* restart candidate and restart criteria */
     double kc_cur = kkt_omega(ec.scaled, omega, o.kkt_omega_power);
     double kc_avg = kkt_omega(ea.scaled, omega, o.kkt_omega_power);
-    int cand_avg = !(kc_cur < kc_avg);
+    /* the current iterate only when clearly better; a relative difference below
+     * 1e-12 is a rounding-level tie (one step into an epoch the average equals
+     * the iterate) and goes to the average, the "otherwise" branch */
+    int cand_avg = !(kc_cur < kc_avg - 1e-12 * kc_avg);
     double kc = cand_avg ? kc_avg : kc_cur;
     int reason = orc_restart_reason(kc, kkt0, kkt_prev, t, k, o.beta_suff, o.beta_nec, o.beta_art);
     if (reason) {
