@@ -1,0 +1,180 @@
+"""Benchmark of the restarted-PDHG LP solver on one MI355X.
+
+Workload: the large skewed random LP (m = 1e6 rows, half EQ and half LE,
+n = 2e6 variables in [0, 10], nnz = 2e7 with power-law row lengths capped at
+10,000, N(0,1) values, constructed optimum), FP64 matrix.
+
+A "step" is one accepted PDHG iteration of Algorithm 1 (both fused SpMV step
+kernels plus the amortised restart/termination evaluation every 64 steps),
+timed inside pdlp_solve with the iterate already resident in HBM.  The line
+also carries:
+  roofline     -- the dominant step kernel's algorithmic bytes per launch over
+                  its mean launch duration (HIP events on the solver's stream),
+                  against 8 TB/s;
+  cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same LP
+                  (its first iterations), on the host cores;
+  time_to_tol  -- wall time to rel KKT 1e-4 with the FP64 and the FP32 matrix.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/*_traffic.txt: lines 'kernel <name> fetch_bytes <F>
+    write_bytes <W>'), or None."""
+    path = os.path.join(ROOT, "profiles", "step_kernels_skewed_1e6x2e6_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 6 and parts[0] == "kernel" and parts[1] == kernel:
+            return float(parts[3]) + float(parts[5])
+    return None
+
+
+def cpu_baseline(prob, iters: int):
+    import oracle
+    oracle.build()
+    cores = len(os.sched_getaffinity(0))
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    threads = min(cores, int(env_threads)) if env_threads and env_threads.isdigit() else cores
+    t0 = time.time()
+    r = oracle.solve(prob, eps_rel=0.0, max_iter=iters, threads=threads)
+    wall = time.time() - t0
+    info = r.info
+    return {"value": info["iterations"] / info["solve_s"], "unit": "PDHG iters/sec", "cores": info["threads_used"],
+            "kind": "oracle",
+            "sample": (f"first {info['iterations']} accepted PDHG iterations ({info['attempts']} attempts, "
+                       f"{info['evaluations']} evaluations) of the same 1e6x2e6 LP, FP64; "
+                       f"setup {info['setup_s']:.1f}s excluded, total {wall:.1f}s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--ttt-limit", type=float, default=90.0)
+    ap.add_argument("--profile-attempts", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver does not shard "
+              "an LP over several GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lpgen
+    from paper_2311_12180_amd import pdlp as P
+
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+    t = time.time()
+    prob = lpgen.config1(0)
+    log(f"generated {prob.name} in {time.time() - t:.1f}s")
+
+    # device copy bandwidth (context for the roofline)
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a); torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record(); torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+
+    stream = torch.cuda.current_stream().cuda_stream
+    h = P.pdlp_create(prob, stream=stream, eps_rel=0.0, max_iter=args.warmup, time_limit_s=600.0)
+    _, _, _, info0 = None, None, None, None
+    P.pdlp_solve(h)            # warm-up: graph capture, first launches
+    log(f"setup {P.pdlp_get_solution(h)[3]['setup_s']:.2f}s; warm-up {args.warmup} steps done")
+    P.pdlp_set_termination(h, 0.0, args.steps, 600.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.pdlp_solve(h)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, _, _, info = P.pdlp_get_solution(h)
+    steps = int(info["iterations"])
+    assert steps == args.steps, info
+    ms_step = dt / steps * 1e3
+    log(f"timed {steps} steps in {dt:.3f}s: {steps / dt:.1f} it/s ({info['attempts']} attempts, "
+        f"{info['restarts']} restarts)")
+
+    # per-kernel durations (HIP events on the solver's stream) and the roofline
+    ms_a, ms_b = P.pdlp_profile_attempts(h, args.profile_attempts)
+    by_a, by_b = P.pdlp_step_bytes(h)
+    kern = {"k_primal": (ms_a, by_a), "k_dual": (ms_b, by_b)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms_d, by_d = kern[dom]
+    achieved = by_d / (ms_d * 1e-3) / 1e9
+    traffic = _traffic_from_profiles(dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": by_d, "ms_per_launch": ms_d,
+                "other_kernel": {"name": [k for k in kern if k != dom][0],
+                                 "ms_per_launch": kern[[k for k in kern if k != dom][0]][0],
+                                 "GBps": round(kern[[k for k in kern if k != dom][0]][1] /
+                                               (kern[[k for k in kern if k != dom][0]][0] * 1e-3) / 1e9, 1)},
+                "copy_GBps": round(copy_gbps, 1)}
+    log(f"roofline: {roofline}")
+    P.pdlp_destroy(h)
+
+    ttt = None
+    if not args.no_ttt:
+        ttt = {}
+        import oracle
+        oracle.build()
+        for name, prec in (("fp64", 0), ("fp32_matrix", 1)):
+            h = P.pdlp_create(prob, stream=stream, eps_rel=1e-4, a_precision=prec, time_limit_s=args.ttt_limit)
+            P.pdlp_solve(h)
+            x, y, rc, inf = P.pdlp_get_solution(h)
+            ev = oracle.evaluate(prob, x, y)
+            obj_star = prob.obj_star()
+            ttt[name] = {"status": inf["status_name"], "iterations": inf["iterations"],
+                         "attempts": inf["attempts"], "restarts": inf["restarts"],
+                         "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
+                         "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
+                         "obj_rel_err_vs_known_optimum": abs(inf["primal_obj"] - obj_star) / (1 + abs(obj_star))}
+            log(f"time to 1e-4 ({name}): {ttt[name]}")
+            P.pdlp_destroy(h)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, args.cpu_iters)
+        log(f"cpu baseline: {cpu}")
+
+    line = {"metric": "PDHG iters/sec + wall time to rel KKT 1e-4/1e-8; SpMV HBM GB/s vs peak",
+            "value": round(steps / dt, 2), "unit": "PDHG iters/sec", "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "skewed random LP m=1e6 (half EQ, half LE) n=2e6 nnz=2e7, row lengths "
+                                   "power-law capped at 10,000, FP64 matrix",
+                       "m": prob.m, "n": prob.n, "nnz": prob.nnz, "eval_period": 64},
+            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

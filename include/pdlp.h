@@ -1,0 +1,195 @@
+/* pdlp.h -- restarted PDHG for linear programming on one AMD MI355X (gfx950).
+ *
+ * Method: Lu & Yang, "cuPDLP.jl: A GPU Implementation of Restarted
+ * Primal-Dual Hybrid Gradient for Linear Programming in Julia" (arXiv
+ * 2311.12180).  The solver runs Algorithm 1 (restarted PDHG) with Algorithm 2
+ * (adaptive step size), the diagonal preconditioning and primal-weight rules of
+ * Section 2.2, the KKT-error restart scheme of Section 3.4 (eq. (kkt)) and the
+ * relative-KKT termination test of Section 4.1, entirely on the GPU: the
+ * problem crosses to the device once and the solution comes back once
+ * (Section 3.2).
+ *
+ * The LP (Section 2, eq. (lp)), in the user orientation of this interface:
+ *     min  c'x
+ *     s.t. a_i x  = b_i   (row_type PDLP_ROW_EQ)
+ *          a_i x >= b_i   (row_type PDLP_ROW_GE)
+ *          a_i x <= b_i   (row_type PDLP_ROW_LE)
+ *          l <= x <= u    (l_j may be -INFINITY, u_j may be +INFINITY)
+ * A is m x n in CSR form (int32 row_ptr[m+1], int32 col_idx[nnz], double val[nnz]).
+ *
+ * Dual sign convention of the returned y and reduced costs lambda
+ * (stationarity c = A'y + lambda): y is free on EQ rows, y >= 0 on GE rows,
+ * y <= 0 on LE rows; lambda_j >= 0 where x_j sits at its lower bound and
+ * lambda_j <= 0 at its upper bound.
+ *
+ * Every function returns an int: 0 (PDLP_OK) on success, a negative PDLP_ERR_*
+ * code on failure; no function throws or aborts.  Non-convergence is not an
+ * error: pdlp_solve returns PDLP_OK and info.status tells why it stopped.
+ * A handle is not thread-safe; distinct handles on distinct streams may run
+ * concurrently.
+ */
+#ifndef PDLP_H
+#define PDLP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdlp_handle pdlp_handle;   /* opaque; owns every device buffer */
+
+enum { PDLP_ROW_EQ = 0, PDLP_ROW_GE = 1, PDLP_ROW_LE = 2 };       /* int8 row_type */
+enum { PDLP_MEM_HOST = 0, PDLP_MEM_DEVICE = 1 };                  /* where problem arrays live */
+enum { PDLP_A_FP64 = 0, PDLP_A_FP32 = 1 };                        /* matrix values in the steps */
+enum { PDLP_OPTIMAL = 1, PDLP_ITER_LIMIT = 2, PDLP_TIME_LIMIT = 3, PDLP_NUMERICAL_ERROR = 4 };
+enum {
+  PDLP_OK = 0,
+  PDLP_ERR_ARG = -1,          /* NULL pointer, bad size or option */
+  PDLP_ERR_DATA = -2,         /* malformed CSR, non-finite data, l > u, bad row type */
+  PDLP_ERR_HIP = -3,          /* a HIP runtime call failed (no device, launch failure) */
+  PDLP_ERR_OOM = -4,          /* device or pinned host allocation failed */
+  PDLP_ERR_STATE = -5,        /* call out of order (e.g. get_solution before solve) */
+  PDLP_ERR_UNSUPPORTED = -6
+};
+
+/* The LP.  All arrays are read during pdlp_create only (deep copy).
+ * mem = PDLP_MEM_HOST: host pointers.  mem = PDLP_MEM_DEVICE: device pointers
+ * of the current HIP device (e.g. torch tensor data_ptr()s), copied on the
+ * given stream.  Sizes: m >= 0, n >= 1, 0 <= nnz < 2^31.  Column indices of a
+ * row may come in any order but must be distinct and in [0, n). */
+typedef struct {
+  int32_t m, n;
+  int64_t nnz;
+  int32_t mem;
+  const int32_t* row_ptr;     /* [m+1], row_ptr[0] = 0, nondecreasing, row_ptr[m] = nnz */
+  const int32_t* col_idx;     /* [nnz] */
+  const double* val;          /* [nnz], finite */
+  const double* c;            /* [n], finite */
+  const double* b;            /* [m], finite */
+  const double* l;            /* [n], finite or -INFINITY */
+  const double* u;            /* [n], finite or +INFINITY, l <= u */
+  const int8_t* row_type;     /* [m], PDLP_ROW_* */
+} pdlp_problem;
+
+/* Options; pdlp_default_options fills the defaults shown. */
+typedef struct {
+  double eps_rel;             /* 1e-4: relative KKT tolerance of Section 4.1 */
+  int64_t max_iter;           /* 1000000: accepted PDHG steps (>= 0) */
+  double time_limit_s;        /* 3600 */
+  int32_t eval_period;        /* 64: restart/termination check every P accepted steps (>= 1) */
+  int32_t ruiz_iters;         /* 10: Ruiz inf-norm passes (Section 2.2) */
+  double pc_alpha;            /* 1.0: Pock-Chambolle alpha in [0, 2]; < 0 skips the pass */
+  double pw_theta;            /* 0.5: primal-weight smoothing in [0, 1] */
+  double eps_zero;            /* 1e-10: the "small nonzero tolerance" of the primal weight */
+  double beta_suff;           /* 0.2 restart criterion (i) */
+  double beta_nec;            /* 0.8 restart criterion (ii) */
+  double beta_art;            /* 0.36 restart criterion (iii) */
+  int32_t a_precision;        /* PDLP_A_FP64, or PDLP_A_FP32: the scaled matrix is rounded to
+                                 FP32 for the PDHG steps (products accumulate in FP64); the
+                                 restart / termination evaluations use the FP64 matrix */
+  int32_t kkt_omega_power;    /* 2: KKT_omega weights omega^2 and omega^-2 as in eq. (kkt); 1 */
+  int32_t trace;              /* capacity of the decision trace (attempts and evaluations), 0 = off */
+  int32_t poll_every;         /* 4: graph launches between two reads of the 8-byte status word */
+  int32_t graph;              /* 1: the inner loop is a captured hipGraph; 0: the same kernels
+                                 launched one by one (for callers that cannot use graphs) */
+} pdlp_options;
+
+typedef struct {
+  int32_t status;             /* PDLP_OPTIMAL / ITER_LIMIT / TIME_LIMIT / NUMERICAL_ERROR */
+  int32_t returned_avg;       /* 1 if the returned point is the epoch's weighted average */
+  int64_t iterations;         /* accepted PDHG steps */
+  int64_t attempts;           /* step attempts of Algorithm 2 (>= iterations) */
+  int64_t restarts;
+  int64_t evaluations;
+  double rel_kkt, rel_gap, rel_pres, rel_dres;   /* Section 4.1, on the original LP */
+  double primal_obj, dual_obj;
+  double omega, eta_hat;      /* primal weight and step size at exit */
+  double setup_s;             /* pdlp_create: upload, transpose, scaling */
+  double solve_s;             /* pdlp_solve wall time */
+} pdlp_info;
+
+/* Scaled-space state of the current iterate (for parity checks and resume). */
+typedef struct {
+  int64_t iterations, attempts, restarts, evaluations;
+  double eta_hat, omega, sum_eta, kkt0;
+} pdlp_iter_state;
+
+/* Fill *o with the defaults listed above.  PDLP_ERR_ARG if o is NULL. */
+int pdlp_default_options(pdlp_options* o);
+
+/* Validate and upload the LP, transpose it on the device (both K and K' are
+ * kept in CSR), negate LE rows into the >= form of eq. (primal-dual), and run
+ * the Section 2.2 preconditioning (ruiz_iters Ruiz passes, then one
+ * Pock-Chambolle pass) on the device.  o = NULL means defaults.  hip_stream is
+ * a hipStream_t (NULL: the default stream); every device operation of the
+ * handle runs on it, and create synchronizes it before returning.  On success
+ * *out owns all device memory; on failure *out is NULL and
+ * pdlp_last_error(NULL) describes the problem. */
+int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* hip_stream, pdlp_handle** out);
+
+/* Starting point for the next pdlp_solve (Section 4.1 uses the zero vector;
+ * this replaces it): x0[n] and y0[m] in the user orientation on the host, or
+ * NULL for the default (proj_X(0), 0); omega0 <= 0 keeps the default primal
+ * weight ||c~||/||q~||.  x0 is projected onto the bounds and y0 onto the sign
+ * constraints of its rows.  PDLP_ERR_DATA if a value is not finite. */
+int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const double* y0, double omega0);
+
+/* Run Algorithm 1 from the starting point until the Section 4.1 test holds
+ * (rel KKT <= eps_rel for the current or the average iterate) or a limit is
+ * hit.  Each call starts afresh from the starting point.  The inner loop is a
+ * captured hipGraph of attempt slots plus the restart/termination evaluation;
+ * the host reads only an 8-byte status word between graph launches. */
+int pdlp_solve(pdlp_handle* h);
+
+/* Change the termination test of later solves: eps_rel >= 0, max_iter >= 0
+ * accepted steps, time_limit_s > 0 (same meaning as in pdlp_options).
+ * PDLP_ERR_ARG for values out of range; the handle keeps its old values then. */
+int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s);
+
+/* Copy the solution of the last pdlp_solve to host buffers: x[n], y[m]
+ * (user orientation) and reduced_cost[n] (lambda = proj_Lambda(c - A'y)); any
+ * of them and info may be NULL.  PDLP_ERR_STATE before the first solve. */
+int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* reduced_cost, pdlp_info* info);
+
+/* The current iterate in the scaled >= form (x~[n], y~[m]; NULL to skip) and
+ * the step state.  Valid after pdlp_solve. */
+int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pdlp_iter_state* st);
+
+/* The preconditioner D1[m], D2[n] and the scaled >=-form values D1 K D2 in the
+ * CSR order of the input (val_scaled[nnz]); NULL to skip any. */
+int pdlp_get_scaling(pdlp_handle* h, double* D1, double* D2, double* val_scaled);
+
+/* Decision trace of the last solve (needs options.trace > 0).  Attempts:
+ * k (accepted steps before the attempt), eta, eta_bar, accepted.  Evaluations:
+ * k, KKT_omega(current), KKT_omega(average), candidate (1 = average), restart
+ * reason (0 none, 1 sufficient, 2 necessary, 3 artificial), omega after.
+ * Arrays hold up to `cap` entries; *n_att / *n_eval receive the counts. */
+int pdlp_get_trace(pdlp_handle* h, int64_t cap, int64_t* n_att, int64_t* att_k, double* att_eta,
+                   double* att_etabar, int8_t* att_acc, int64_t* n_eval, int64_t* ev_k,
+                   double* ev_kkt_cur, double* ev_kkt_avg, int8_t* ev_cand, int8_t* ev_reason,
+                   double* ev_omega);
+
+/* Time the two PDHG step kernels: continue the last solve for `attempts`
+ * attempt pairs launched eagerly on the handle's stream, each bracketed by HIP
+ * events, and return the mean duration (milliseconds) of the primal-step
+ * kernel (K' product fused with the x update) and of the dual-step kernel
+ * (K product fused with the y update and the step-size decision).  The
+ * attempts are real PDHG steps of the solve.  PDLP_ERR_STATE before a solve. */
+int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* ms_primal, double* ms_dual);
+
+/* Algorithmic bytes moved by one primal-step and one dual-step kernel launch
+ * (matrix stream, row pointers, one read of each gathered vector, the per-row
+ * vector reads and writes). */
+int pdlp_step_bytes(pdlp_handle* h, double* bytes_primal, double* bytes_dual);
+
+/* Last error message of h, or of the last failed pdlp_create on this thread
+ * when h is NULL.  Never NULL. */
+const char* pdlp_last_error(const pdlp_handle* h);
+
+/* Release every resource of h.  NULL-safe. */
+void pdlp_destroy(pdlp_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDLP_H */

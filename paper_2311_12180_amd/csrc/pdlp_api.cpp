@@ -1,0 +1,796 @@
+// C ABI and host runtime of the MI355X restarted-PDHG LP solver.
+//
+// pdlp_create validates the LP on the host, uploads it once, and builds the
+// scaled >=-form problem on the device (normalisation, transpose, Section 2.2
+// preconditioning).  pdlp_solve runs Algorithm 1 as a captured hipGraph of
+// attempt slots (primal kernel + dual kernel with the Algorithm 2 decision)
+// followed by the evaluation/restart kernels; the host only reads the 16-byte
+// status word between graph launches, pipelined one batch behind.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pdlp.h"
+#include "pdlp_dev.h"
+
+namespace pdlp {
+void launch_primal(const Params& p, hipStream_t s);
+void launch_dual(const Params& p, hipStream_t s);
+void launch_eval(const Params& p, hipStream_t s);
+void launch_init(const Params& p, const double* xs, const double* ys, const int8_t* le, hipStream_t s);
+void launch_output(const Params& p, double* xo, double* yo, double* rco, const int8_t* le, hipStream_t s);
+void launch_set_limit(DevState* st, int status, hipStream_t s);
+hipError_t setup_normalize(int m, const int32_t* rp, double* v, const double* b, const int8_t* rt, double* q,
+                           int8_t* ineq, int8_t* le, int32_t* rowid, hipStream_t s);
+hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
+                           int32_t* rpT, int32_t* ciT, double* vT, int32_t* rowidT, int32_t* perm_out,
+                           hipStream_t s);
+hipError_t setup_scale(int m, int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const int32_t* rowid,
+                       double* v, const int32_t* rpT, const int32_t* ciT, const int32_t* rowidT, double* vT,
+                       int ruiz, double alpha, double* D1, double* D2, double* d1, double* d2, hipStream_t s);
+hipError_t setup_vectors(int m, int n, const double* D1, const double* D2, const double* c0, const double* l0,
+                         const double* u0, double* c, double* l, double* u, double* q, hipStream_t s);
+hipError_t setup_sumsq(int64_t n, const double* a, double* part, double* out, hipStream_t s);
+hipError_t setup_absmax(int64_t nnz, const double* v, unsigned long long* out, hipStream_t s);
+hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s);
+hipError_t setup_fill(int64_t n, double* a, double val, hipStream_t s);
+}  // namespace pdlp
+
+using namespace pdlp;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+inline void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipFail{e, what};
+}
+
+// Greedy row-block partition of a CSR matrix (see RowBlock).
+std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows, int* nslots) {
+  std::vector<RowBlock> out;
+  int slots = 0;
+  int r = 0;
+  while (r < nrows) {
+    const int len = rp[r + 1] - rp[r];
+    if (len > kTile) {
+      const int nch = (len + kTile - 1) / kTile;
+      for (int c = 0; c < nch; ++c) out.push_back(RowBlock{r, r + 1, c, nch, slots});
+      slots += nch;
+      ++r;
+      continue;
+    }
+    const int r0 = r;
+    int nz = 0;
+    while (r < nrows && r - r0 < kMaxRows) {
+      const int l2 = rp[r + 1] - rp[r];
+      if (l2 > kTile || nz + l2 > kTile) break;
+      nz += l2;
+      ++r;
+    }
+    out.push_back(RowBlock{r0, r, -1, 0, 0});
+  }
+  if (out.empty()) out.push_back(RowBlock{0, 0, -1, 0, 0});
+  *nslots = slots;
+  return out;
+}
+
+}  // namespace
+
+struct pdlp_handle {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  pdlp_options opt{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<void*> dev_allocs;
+  std::vector<void*> host_allocs;
+  Params P{};
+  int32_t *rp = nullptr, *ci = nullptr, *rowid = nullptr, *rpT = nullptr, *ciT = nullptr, *rowidT = nullptr,
+          *perm = nullptr;
+  double *val = nullptr, *valT = nullptr;
+  float *valf = nullptr, *valTf = nullptr;
+  double *c0 = nullptr, *l0 = nullptr, *u0 = nullptr, *b0 = nullptr;
+  double *c = nullptr, *l = nullptr, *u = nullptr, *q = nullptr, *D1 = nullptr, *D2 = nullptr;
+  int8_t *rt = nullptr, *ineq = nullptr, *le = nullptr;
+  double *xo = nullptr, *yo = nullptr, *rco = nullptr;
+  double *wx = nullptr, *wy = nullptr;
+  bool has_warm = false;
+  double warm_omega = 0.0;
+  DevState* st = nullptr;
+  DevState* st_host[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int slots_per_round = 0, rounds = 0;
+  double eta0 = 1.0, omega0 = 1.0;
+  std::string err = "no error";
+  bool solved = false;
+  pdlp_info info{};
+  double setup_s = 0.0;
+
+  template <typename T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+    dev_allocs.push_back(p);
+    e = hipMemsetAsync(p, 0, bytes, stream);
+    if (e != hipSuccess) throw HipFail{e, "hipMemsetAsync"};
+    return static_cast<T*>(p);
+  }
+
+  void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : dev_allocs) (void)hipFree(p);
+    dev_allocs.clear();
+    for (void* p : host_allocs) (void)hipHostFree(p);
+    host_allocs.clear();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
+  }
+};
+
+static int fail(pdlp_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+static std::string hip_msg(const HipFail& f) {
+  return std::string(f.what) + ": " + hipGetErrorString(f.e);
+}
+
+extern "C" int pdlp_default_options(pdlp_options* o) {
+  if (!o) return PDLP_ERR_ARG;
+  o->eps_rel = 1e-4;
+  o->max_iter = 1000000;
+  o->time_limit_s = 3600.0;
+  o->eval_period = 64;
+  o->ruiz_iters = 10;
+  o->pc_alpha = 1.0;
+  o->pw_theta = 0.5;
+  o->eps_zero = 1e-10;
+  o->beta_suff = 0.2;
+  o->beta_nec = 0.8;
+  o->beta_art = 0.36;
+  o->a_precision = PDLP_A_FP64;
+  o->kkt_omega_power = 2;
+  o->trace = 0;
+  o->poll_every = 4;
+  o->graph = 1;
+  return PDLP_OK;
+}
+
+static int check_options(const pdlp_options& o, std::string& why) {
+  if (!(o.eps_rel >= 0.0) || !std::isfinite(o.eps_rel)) return why = "eps_rel must be finite and >= 0", -1;
+  if (o.max_iter < 0) return why = "max_iter must be >= 0", -1;
+  if (!(o.time_limit_s > 0.0)) return why = "time_limit_s must be > 0", -1;
+  if (o.eval_period < 1 || o.eval_period > 1024) return why = "eval_period must be in [1, 1024]", -1;
+  if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) return why = "ruiz_iters must be in [0, 1000]", -1;
+  if (!(o.pc_alpha <= 2.0) || std::isnan(o.pc_alpha)) return why = "pc_alpha must be <= 2", -1;
+  if (!(o.pw_theta >= 0.0 && o.pw_theta <= 1.0)) return why = "pw_theta must be in [0, 1]", -1;
+  if (!(o.eps_zero >= 0.0) || !std::isfinite(o.eps_zero)) return why = "eps_zero must be finite and >= 0", -1;
+  if (!(o.beta_suff > 0.0 && o.beta_nec > 0.0 && o.beta_art > 0.0)) return why = "restart betas must be > 0", -1;
+  if (o.a_precision != PDLP_A_FP64 && o.a_precision != PDLP_A_FP32) return why = "a_precision must be 0 or 1", -1;
+  if (o.kkt_omega_power != 1 && o.kkt_omega_power != 2) return why = "kkt_omega_power must be 1 or 2", -1;
+  if (o.trace < 0) return why = "trace must be >= 0", -1;
+  if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
+  if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
+  return 0;
+}
+
+// Host-side validation of the LP (arrays on the host).
+static int validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
+                    const double* c, const double* b, const double* l, const double* u, const int8_t* rt,
+                    std::string& why) {
+  char buf[256];
+  if (rp[0] != 0) return why = "row_ptr[0] must be 0", -1;
+  for (int32_t i = 0; i < m; ++i)
+    if (rp[i + 1] < rp[i]) {
+      snprintf(buf, sizeof buf, "row_ptr decreases at row %d", i);
+      return why = buf, -1;
+    }
+  if ((int64_t)rp[m] != nnz) return why = "row_ptr[m] != nnz", -1;
+  std::vector<int32_t> mark((size_t)n, -1);
+  for (int32_t i = 0; i < m; ++i) {
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int32_t j = ci[p];
+      if (j < 0 || j >= n) {
+        snprintf(buf, sizeof buf, "col_idx[%d] = %d out of range [0, %d)", p, j, n);
+        return why = buf, -1;
+      }
+      if (mark[(size_t)j] == i) {
+        snprintf(buf, sizeof buf, "duplicate column %d in row %d", j, i);
+        return why = buf, -1;
+      }
+      mark[(size_t)j] = i;
+      if (!std::isfinite(v[p])) {
+        snprintf(buf, sizeof buf, "val[%d] is not finite", p);
+        return why = buf, -1;
+      }
+    }
+    if (!std::isfinite(b[i])) {
+      snprintf(buf, sizeof buf, "b[%d] is not finite", i);
+      return why = buf, -1;
+    }
+    if (rt[i] < 0 || rt[i] > 2) {
+      snprintf(buf, sizeof buf, "row_type[%d] = %d is not EQ/GE/LE", i, (int)rt[i]);
+      return why = buf, -1;
+    }
+  }
+  for (int32_t j = 0; j < n; ++j) {
+    if (!std::isfinite(c[j])) {
+      snprintf(buf, sizeof buf, "c[%d] is not finite", j);
+      return why = buf, -1;
+    }
+    if (std::isnan(l[j]) || std::isnan(u[j]) || l[j] == INFINITY || u[j] == -INFINITY || l[j] > u[j]) {
+      snprintf(buf, sizeof buf, "bounds of x[%d] are invalid (l=%g, u=%g)", j, l[j], u[j]);
+      return why = buf, -1;
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+static void fetch(std::vector<T>& dst, const T* src, size_t count, int mem) {
+  dst.resize(std::max<size_t>(count, 1));
+  if (count == 0) return;
+  if (mem == PDLP_MEM_HOST) std::memcpy(dst.data(), src, count * sizeof(T));
+  else check(hipMemcpy(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost), "hipMemcpy(D2H) of the problem");
+}
+
+static void build_graph(pdlp_handle* h) {
+  const int P = h->opt.eval_period;
+  h->slots_per_round = P + std::max(2, P / 8);
+  h->rounds = std::max(1, 64 / P);
+  check(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  for (int r = 0; r < h->rounds; ++r) {
+    for (int s = 0; s < h->slots_per_round; ++s) {
+      launch_primal(h->P, h->cap_stream);
+      launch_dual(h->P, h->cap_stream);
+    }
+    launch_eval(h->P, h->cap_stream);
+  }
+  check(hipStreamEndCapture(h->cap_stream, &h->graph), "hipStreamEndCapture");
+  check(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* hip_stream, pdlp_handle** out) {
+  if (out) *out = nullptr;
+  if (!p || !out) return fail(nullptr, PDLP_ERR_ARG, "NULL problem or output pointer");
+  pdlp_options opt;
+  if (o) opt = *o;
+  else pdlp_default_options(&opt);
+  std::string why;
+  if (check_options(opt, why)) return fail(nullptr, PDLP_ERR_ARG, why);
+  if (p->m < 0 || p->n < 1 || p->nnz < 0 || p->nnz >= (int64_t)1 << 31)
+    return fail(nullptr, PDLP_ERR_ARG, "sizes must satisfy m >= 0, n >= 1, 0 <= nnz < 2^31");
+  if (p->mem != PDLP_MEM_HOST && p->mem != PDLP_MEM_DEVICE) return fail(nullptr, PDLP_ERR_ARG, "bad mem kind");
+  if (!p->row_ptr || !p->c || !p->l || !p->u || (p->nnz > 0 && (!p->col_idx || !p->val)) ||
+      (p->m > 0 && (!p->b || !p->row_type)))
+    return fail(nullptr, PDLP_ERR_ARG, "NULL problem array");
+  const int32_t m = p->m, n = p->n;
+  const int64_t nnz = p->nnz;
+  const double t0 = now_s();
+  // host copies for validation and the row-block partition
+  std::vector<int32_t> hrp, hci;
+  std::vector<double> hv, hc, hb, hl, hu;
+  std::vector<int8_t> hrt;
+  try {
+    if (p->mem == PDLP_MEM_DEVICE) {
+      int ndev = 0;
+      check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+      // the caller's producers of the device arrays run on its stream
+      check(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+    }
+    fetch(hrp, p->row_ptr, (size_t)m + 1, p->mem);
+    fetch(hci, p->col_idx, (size_t)nnz, p->mem);
+    fetch(hv, p->val, (size_t)nnz, p->mem);
+    fetch(hc, p->c, (size_t)n, p->mem);
+    fetch(hb, p->b, (size_t)m, p->mem);
+    fetch(hl, p->l, (size_t)n, p->mem);
+    fetch(hu, p->u, (size_t)n, p->mem);
+    fetch(hrt, p->row_type, (size_t)m, p->mem);
+  } catch (const HipFail& f) {
+    return fail(nullptr, PDLP_ERR_HIP, hip_msg(f));
+  }
+  if (validate(m, n, nnz, hrp.data(), hci.data(), hv.data(), hc.data(), hb.data(), hl.data(), hu.data(), hrt.data(),
+               why))
+    return fail(nullptr, PDLP_ERR_DATA, why);
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, PDLP_ERR_HIP, "no HIP device");
+
+  pdlp_handle* h = new pdlp_handle();
+  h->m = m;
+  h->n = n;
+  h->nnz = nnz;
+  h->opt = opt;
+  h->stream = (hipStream_t)hip_stream;
+  try {
+    check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hipStream_t s = h->stream;
+    // --- upload (a1)
+    h->rp = h->dalloc<int32_t>((size_t)m + 1);
+    h->ci = h->dalloc<int32_t>((size_t)nnz);
+    h->val = h->dalloc<double>((size_t)nnz);
+    h->c0 = h->dalloc<double>(n);
+    h->l0 = h->dalloc<double>(n);
+    h->u0 = h->dalloc<double>(n);
+    h->b0 = h->dalloc<double>(m);
+    h->rt = h->dalloc<int8_t>(m);
+    const hipMemcpyKind kind = hipMemcpyHostToDevice;
+    check(hipMemcpyAsync(h->rp, hrp.data(), ((size_t)m + 1) * 4, kind, s), "upload row_ptr");
+    if (nnz) check(hipMemcpyAsync(h->ci, hci.data(), (size_t)nnz * 4, kind, s), "upload col_idx");
+    if (nnz) check(hipMemcpyAsync(h->val, hv.data(), (size_t)nnz * 8, kind, s), "upload val");
+    check(hipMemcpyAsync(h->c0, hc.data(), (size_t)n * 8, kind, s), "upload c");
+    check(hipMemcpyAsync(h->l0, hl.data(), (size_t)n * 8, kind, s), "upload l");
+    check(hipMemcpyAsync(h->u0, hu.data(), (size_t)n * 8, kind, s), "upload u");
+    if (m) check(hipMemcpyAsync(h->b0, hb.data(), (size_t)m * 8, kind, s), "upload b");
+    if (m) check(hipMemcpyAsync(h->rt, hrt.data(), (size_t)m, kind, s), "upload row_type");
+    // --- >= form, transpose (a2)
+    h->q = h->dalloc<double>(m);
+    h->ineq = h->dalloc<int8_t>(m);
+    h->le = h->dalloc<int8_t>(m);
+    h->rowid = h->dalloc<int32_t>((size_t)nnz);
+    check(setup_normalize(m, h->rp, h->val, h->b0, h->rt, h->q, h->ineq, h->le, h->rowid, s), "normalize");
+    h->rpT = h->dalloc<int32_t>((size_t)n + 1);
+    h->ciT = h->dalloc<int32_t>((size_t)nnz);
+    h->valT = h->dalloc<double>((size_t)nnz);
+    h->rowidT = h->dalloc<int32_t>((size_t)nnz);
+    h->perm = h->dalloc<int32_t>((size_t)nnz);
+    check(setup_transpose(m, n, nnz, h->ci, h->val, h->rowid, h->rpT, h->ciT, h->valT, h->rowidT, h->perm, s),
+          "transpose");
+    // --- unscaled norms, then preconditioning (a3)
+    double* red = h->dalloc<double>(8);
+    double* part = h->dalloc<double>((size_t)std::max<int64_t>(n, m) / 4096 + 2);
+    check(setup_sumsq(n, h->c0, part, red + 0, s), "norm c");
+    check(setup_sumsq(m, h->q, part, red + 1, s), "norm q");
+    h->D1 = h->dalloc<double>(m);
+    h->D2 = h->dalloc<double>(n);
+    double* d1 = h->dalloc<double>(m);
+    double* d2 = h->dalloc<double>(n);
+    check(setup_fill(m, h->D1, 1.0, s), "fill D1");
+    check(setup_fill(n, h->D2, 1.0, s), "fill D2");
+    check(setup_scale(m, n, nnz, h->rp, h->ci, h->rowid, h->val, h->rpT, h->ciT, h->rowidT, h->valT, opt.ruiz_iters,
+                      opt.pc_alpha, h->D1, h->D2, d1, d2, s),
+          "scale");
+    h->c = h->dalloc<double>(n);
+    h->l = h->dalloc<double>(n);
+    h->u = h->dalloc<double>(n);
+    check(setup_vectors(m, n, h->D1, h->D2, h->c0, h->l0, h->u0, h->c, h->l, h->u, h->q, s), "scale vectors");
+    // --- a4: omega0 = ||c~|| / ||q~||, eta0 = 1 / max |K~|
+    check(setup_sumsq(n, h->c, part, red + 2, s), "norm c~");
+    check(setup_sumsq(m, h->q, part, red + 3, s), "norm q~");
+    check(setup_absmax(nnz, h->val, reinterpret_cast<unsigned long long*>(red + 4), s), "max |K~|");
+    double hred[5];
+    check(hipMemcpyAsync(hred, red, sizeof hred, hipMemcpyDeviceToHost, s), "read norms");
+    check(hipStreamSynchronize(s), "setup sync");
+    const double cn = std::sqrt(hred[2]), qn = std::sqrt(hred[3]);
+    h->omega0 = (cn > opt.eps_zero && qn > opt.eps_zero) ? cn / qn : 1.0;
+    double kmax;
+    std::memcpy(&kmax, &hred[4], sizeof kmax);
+    h->eta0 = kmax > 0.0 ? 1.0 / kmax : 1.0;
+    if (opt.a_precision == PDLP_A_FP32) {
+      h->valf = h->dalloc<float>((size_t)nnz);
+      h->valTf = h->dalloc<float>((size_t)nnz);
+      check(setup_to_f32(nnz, h->val, h->valf, s), "fp32 K");
+      check(setup_to_f32(nnz, h->valT, h->valTf, s), "fp32 K'");
+    }
+    // --- row-block partitions
+    std::vector<int32_t> hrpT((size_t)n + 1);
+    check(hipMemcpy(hrpT.data(), h->rpT, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
+    int slotsK = 0, slotsT = 0;
+    std::vector<RowBlock> bk = partition_rows(hrp.data(), m, &slotsK);
+    std::vector<RowBlock> bt = partition_rows(hrpT.data(), n, &slotsT);
+    RowBlock* dbk = h->dalloc<RowBlock>(bk.size());
+    RowBlock* dbt = h->dalloc<RowBlock>(bt.size());
+    check(hipMemcpyAsync(dbk, bk.data(), bk.size() * sizeof(RowBlock), kind, s), "upload blocks");
+    check(hipMemcpyAsync(dbt, bt.data(), bt.size() * sizeof(RowBlock), kind, s), "upload blocks");
+    Params& P = h->P;
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), slotsK, m,
+                 h->dalloc<double>(2 * (size_t)slotsK), h->dalloc<uint32_t>((size_t)slotsK)};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), slotsT, n,
+                  h->dalloc<double>(2 * (size_t)slotsT), h->dalloc<uint32_t>((size_t)slotsT)};
+    P.m = m;
+    P.n = n;
+    P.use_f32 = opt.a_precision == PDLP_A_FP32;
+    P.xcd_remap = 1;
+    for (int k = 0; k < 2; ++k) {
+      P.x[k] = h->dalloc<double>(n);
+      P.y[k] = h->dalloc<double>(m);
+      P.kx[k] = h->dalloc<double>(m);
+    }
+    P.dx = h->dalloc<double>(n);
+    P.xsum = h->dalloc<double>(n);
+    P.ysum = h->dalloc<double>(m);
+    P.xbar = h->dalloc<double>(n);
+    P.ybar = h->dalloc<double>(m);
+    P.x0 = h->dalloc<double>(n);
+    P.y0 = h->dalloc<double>(m);
+    P.c = h->c;
+    P.q = h->q;
+    P.l = h->l;
+    P.u = h->u;
+    P.ineq = h->ineq;
+    P.D1 = h->D1;
+    P.D2 = h->D2;
+    const size_t slots_k = bk.size() + (size_t)slotsK, slots_t = bt.size() + (size_t)slotsT;
+    P.partA = h->dalloc<double>(slots_t);
+    P.partB = h->dalloc<double>(2 * slots_k);
+    P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
+    P.partE1 = h->dalloc<double>(8 * slots_k);
+    P.partE2 = h->dalloc<double>(6 * slots_t);
+    P.counters = h->dalloc<uint32_t>(8);
+    h->st = h->dalloc<DevState>(1);
+    P.st = h->st;
+    if (opt.trace > 0) {
+      const size_t cap = (size_t)opt.trace;
+      P.tr = Trace{(int64_t)cap,
+                   h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
+                   h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
+                   h->dalloc<int8_t>(cap), h->dalloc<double>(cap)};
+    } else {
+      P.tr = Trace{};
+    }
+    P.P = opt.eval_period;
+    P.beta_suff = opt.beta_suff;
+    P.beta_nec = opt.beta_nec;
+    P.beta_art = opt.beta_art;
+    P.theta = opt.pw_theta;
+    P.eps_zero = opt.eps_zero;
+    P.tie_rel = 1e-12;
+    P.omega_power = opt.kkt_omega_power;
+    P.cnorm0 = std::sqrt(hred[0]);
+    P.qnorm0 = std::sqrt(hred[1]);
+    h->xo = h->dalloc<double>(n);
+    h->yo = h->dalloc<double>(m);
+    h->rco = h->dalloc<double>(n);
+    h->wx = h->dalloc<double>(n);
+    h->wy = h->dalloc<double>(m);
+    for (int k = 0; k < 2; ++k) {
+      void* hp = nullptr;
+      check(hipHostMalloc(&hp, sizeof(DevState), hipHostMallocDefault), "hipHostMalloc");
+      h->host_allocs.push_back(hp);
+      h->st_host[k] = static_cast<DevState*>(hp);
+      check(hipEventCreateWithFlags(&h->ev[k], hipEventDisableTiming), "hipEventCreate");
+    }
+    check(hipStreamSynchronize(s), "setup sync");
+    check(hipGetLastError(), "setup kernels");
+  } catch (const HipFail& f) {
+    std::string msg = hip_msg(f);
+    const int code = (f.e == hipErrorOutOfMemory || f.e == hipErrorMemoryAllocation) ? PDLP_ERR_OOM : PDLP_ERR_HIP;
+    h->release();
+    delete h;
+    return fail(nullptr, code, msg);
+  }
+  h->setup_s = now_s() - t0;
+  *out = h;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const double* y0, double omega0) {
+  if (!h) return PDLP_ERR_ARG;
+  if (x0)
+    for (int32_t j = 0; j < h->n; ++j)
+      if (!std::isfinite(x0[j])) return fail(h, PDLP_ERR_DATA, "warm-start x0 is not finite");
+  if (y0)
+    for (int32_t i = 0; i < h->m; ++i)
+      if (!std::isfinite(y0[i])) return fail(h, PDLP_ERR_DATA, "warm-start y0 is not finite");
+  if (std::isnan(omega0) || std::isinf(omega0)) return fail(h, PDLP_ERR_DATA, "warm-start omega0 is not finite");
+  try {
+    // x0 == NULL: zero start for x; y0 == NULL: zero start for y
+    std::vector<double> zx((size_t)h->n, 0.0), zy((size_t)std::max(h->m, 1), 0.0);
+    check(hipMemcpy(h->wx, x0 ? x0 : zx.data(), (size_t)h->n * 8, hipMemcpyHostToDevice), "upload x0");
+    if (h->m) check(hipMemcpy(h->wy, y0 ? y0 : zy.data(), (size_t)h->m * 8, hipMemcpyHostToDevice), "upload y0");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  h->has_warm = (x0 != nullptr) || (y0 != nullptr);
+  h->warm_omega = omega0 > 0.0 ? omega0 : 0.0;
+  return PDLP_OK;
+}
+
+// Reset the device state and run the starting-point evaluation (eager launches).
+static void start_solve(pdlp_handle* h) {
+  hipStream_t s = h->stream;
+  DevState* s0 = h->st_host[0];
+  std::memset(s0, 0, sizeof(DevState));
+  s0->eta = h->eta0;
+  s0->eta_hat = h->eta0;
+  s0->omega = h->warm_omega > 0.0 ? h->warm_omega : h->omega0;
+  s0->initial = 1;
+  s0->need_eval = 1;
+  s0->eps_rel = h->opt.eps_rel;
+  s0->max_iter = h->opt.max_iter;
+  check(hipMemcpyAsync(h->st, s0, sizeof(DevState), hipMemcpyHostToDevice, s), "upload state");
+  launch_init(h->P, h->has_warm ? h->wx : nullptr, h->has_warm ? h->wy : nullptr, h->le, s);
+  launch_eval(h->P, s);
+  check(hipGetLastError(), "launch start");
+  check(hipStreamSynchronize(s), "start sync");
+}
+
+static void finish_solve(pdlp_handle* h, double t0) {
+  hipStream_t s = h->stream;
+  launch_output(h->P, h->xo, h->yo, h->rco, h->le, s);
+  DevState* f = h->st_host[0];
+  check(hipMemcpyAsync(f, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s), "read state");
+  check(hipStreamSynchronize(s), "finish sync");
+  check(hipGetLastError(), "output kernels");
+  pdlp_info& I = h->info;
+  I.status = f->status;
+  I.returned_avg = f->ret_avg;
+  I.iterations = f->k;
+  I.attempts = f->attempts;
+  I.restarts = f->restarts;
+  I.evaluations = f->evals;
+  I.rel_kkt = f->rel_kkt;
+  I.rel_gap = f->rel_gap;
+  I.rel_pres = f->rel_p;
+  I.rel_dres = f->rel_d;
+  I.primal_obj = f->pobj;
+  I.dual_obj = f->dobj;
+  I.omega = f->omega;
+  I.eta_hat = f->eta_hat;
+  I.setup_s = h->setup_s;
+  I.solve_s = now_s() - t0;
+}
+
+extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
+  if (!h) return PDLP_ERR_ARG;
+  pdlp_options o = h->opt;
+  o.eps_rel = eps_rel;
+  o.max_iter = max_iter;
+  o.time_limit_s = time_limit_s;
+  std::string why;
+  if (check_options(o, why)) return fail(h, PDLP_ERR_ARG, why);
+  h->opt = o;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_solve(pdlp_handle* h) {
+  if (!h) return PDLP_ERR_ARG;
+  const double t0 = now_s();
+  try {
+    if (h->opt.graph && !h->gexec) build_graph(h);
+    if (!h->opt.graph) {
+      h->slots_per_round = h->opt.eval_period + std::max(2, h->opt.eval_period / 8);
+      h->rounds = std::max(1, 64 / h->opt.eval_period);
+    }
+    start_solve(h);
+    hipStream_t s = h->stream;
+    const int per = h->opt.poll_every;
+    // pipelined polling: launch batch b, then wait for the status copied after batch b-1
+    int pending = -1;  // index of the status buffer of the previous batch
+    check(hipMemcpyAsync(h->st_host[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s), "read state");
+    check(hipStreamSynchronize(s), "sync");
+    const bool done = h->st_host[0]->done != 0;
+    int cur = 0;
+    int64_t last_k = -1;
+    int stalls = 0;
+    while (!done) {
+      for (int i = 0; i < per; ++i) {
+        if (h->opt.graph) {
+          check(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
+        } else {
+          for (int r = 0; r < h->rounds; ++r) {
+            for (int k = 0; k < h->slots_per_round; ++k) {
+              launch_primal(h->P, s);
+              launch_dual(h->P, s);
+            }
+            launch_eval(h->P, s);
+          }
+          check(hipGetLastError(), "eager launches");
+        }
+      }
+      check(hipMemcpyAsync(h->st_host[cur], h->st, 16, hipMemcpyDeviceToHost, s), "read status");
+      check(hipEventRecord(h->ev[cur], s), "hipEventRecord");
+      if (pending >= 0) {
+        check(hipEventSynchronize(h->ev[pending]), "hipEventSynchronize");
+        if (h->st_host[pending]->done) break;
+        // a healthy run accepts a step within a few attempts; a batch of graphs
+        // without any accepted step means the state is broken
+        if (h->st_host[pending]->k == last_k) {
+          if (++stalls >= 64) {
+            launch_set_limit(h->st, PDLP_NUMERICAL_ERROR, s);
+            break;
+          }
+        } else {
+          stalls = 0;
+          last_k = h->st_host[pending]->k;
+        }
+      }
+      if (now_s() - t0 > h->opt.time_limit_s) {
+        launch_set_limit(h->st, PDLP_TIME_LIMIT, s);
+        break;
+      }
+      pending = cur;
+      cur ^= 1;
+    }
+    check(hipStreamSynchronize(s), "sync");
+    finish_solve(h, t0);
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  h->solved = true;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* rc, pdlp_info* info) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution before pdlp_solve");
+  try {
+    if (x) check(hipMemcpy(x, h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
+    if (y && h->m) check(hipMemcpy(y, h->yo, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y");
+    if (rc) check(hipMemcpy(rc, h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  if (info) *info = h->info;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pdlp_iter_state* st) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_iterate before pdlp_solve");
+  try {
+    DevState f;
+    check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
+    if (x_hat) check(hipMemcpy(x_hat, h->P.x[f.cur], (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x~");
+    if (y_hat && h->m) check(hipMemcpy(y_hat, h->P.y[f.cur], (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y~");
+    if (st) {
+      st->iterations = f.k;
+      st->attempts = f.attempts;
+      st->restarts = f.restarts;
+      st->evaluations = f.evals;
+      st->eta_hat = f.eta_hat;
+      st->omega = f.omega;
+      st->sum_eta = f.sum_eta;
+      st->kkt0 = f.kkt0;
+    }
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_get_scaling(pdlp_handle* h, double* D1, double* D2, double* val_scaled) {
+  if (!h) return PDLP_ERR_ARG;
+  try {
+    if (D1 && h->m) check(hipMemcpy(D1, h->D1, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download D1");
+    if (D2) check(hipMemcpy(D2, h->D2, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download D2");
+    if (val_scaled && h->nnz)
+      check(hipMemcpy(val_scaled, h->val, (size_t)h->nnz * 8, hipMemcpyDeviceToHost), "download K~");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_get_trace(pdlp_handle* h, int64_t cap, int64_t* n_att, int64_t* att_k, double* att_eta,
+                              double* att_etabar, int8_t* att_acc, int64_t* n_eval, int64_t* ev_k,
+                              double* ev_kkt_cur, double* ev_kkt_avg, int8_t* ev_cand, int8_t* ev_reason,
+                              double* ev_omega) {
+  if (!h || cap < 0) return PDLP_ERR_ARG;
+  if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_trace before pdlp_solve");
+  if (h->opt.trace <= 0) return fail(h, PDLP_ERR_STATE, "the handle was created with trace = 0");
+  try {
+    DevState f;
+    check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
+    const Trace& T = h->P.tr;
+    const int64_t na = std::min<int64_t>(f.n_att, cap), ne = std::min<int64_t>(f.n_eval, cap);
+    if (n_att) *n_att = na;
+    if (n_eval) *n_eval = ne;
+    auto cp = [&](void* dst, const void* src, int64_t cnt, size_t sz) {
+      if (dst && cnt > 0) check(hipMemcpy(dst, src, (size_t)cnt * sz, hipMemcpyDeviceToHost), "download trace");
+    };
+    cp(att_k, T.att_k, na, 8);
+    cp(att_eta, T.att_eta, na, 8);
+    cp(att_etabar, T.att_etabar, na, 8);
+    cp(att_acc, T.att_acc, na, 1);
+    cp(ev_k, T.ev_k, ne, 8);
+    cp(ev_kkt_cur, T.ev_kkt_cur, ne, 8);
+    cp(ev_kkt_avg, T.ev_kkt_avg, ne, 8);
+    cp(ev_cand, T.ev_cand, ne, 1);
+    cp(ev_reason, T.ev_reason, ne, 1);
+    cp(ev_omega, T.ev_omega, ne, 8);
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* ms_primal, double* ms_dual) {
+  if (!h || attempts < 1) return PDLP_ERR_ARG;
+  if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_profile_attempts before pdlp_solve");
+  hipStream_t s = h->stream;
+  const int S = h->slots_per_round > 0 ? h->slots_per_round : h->opt.eval_period + 2;
+  std::vector<hipEvent_t> ev((size_t)4 * S, nullptr);
+  double sa = 0.0, sb = 0.0;
+  int64_t timed = 0;
+  try {
+    for (auto& e : ev) check(hipEventCreate(&e), "hipEventCreate");
+    start_solve(h);
+    DevState f;
+    while (timed < attempts) {
+      check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
+      if (f.done) break;
+      const int64_t a0 = f.attempts;
+      for (int k = 0; k < S; ++k) {
+        check(hipEventRecord(ev[4 * k], s), "event");
+        launch_primal(h->P, s);
+        check(hipEventRecord(ev[4 * k + 1], s), "event");
+        check(hipEventRecord(ev[4 * k + 2], s), "event");
+        launch_dual(h->P, s);
+        check(hipEventRecord(ev[4 * k + 3], s), "event");
+      }
+      launch_eval(h->P, s);
+      check(hipStreamSynchronize(s), "sync");
+      check(hipGetLastError(), "profiled launches");
+      check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
+      const int64_t active = std::min<int64_t>(f.attempts - a0, S);
+      for (int k = 0; k < active && timed < attempts; ++k) {
+        float ta = 0.f, tb = 0.f;
+        check(hipEventElapsedTime(&ta, ev[4 * k], ev[4 * k + 1]), "elapsed");
+        check(hipEventElapsedTime(&tb, ev[4 * k + 2], ev[4 * k + 3]), "elapsed");
+        sa += ta;
+        sb += tb;
+        ++timed;
+      }
+      if (active == 0) break;
+    }
+  } catch (const HipFail& f) {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (timed == 0) return fail(h, PDLP_ERR_STATE, "the solve finished before any attempt could be timed");
+  if (ms_primal) *ms_primal = sa / (double)timed;
+  if (ms_dual) *ms_dual = sb / (double)timed;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_step_bytes(pdlp_handle* h, double* bytes_primal, double* bytes_dual) {
+  if (!h) return PDLP_ERR_ARG;
+  const double sv = h->opt.a_precision == PDLP_A_FP32 ? 4.0 : 8.0;
+  const double nnz = (double)h->nnz, m = (double)h->m, n = (double)h->n;
+  // matrix stream + row pointers + each gathered vector once + per-row vectors
+  if (bytes_primal) *bytes_primal = nnz * (sv + 4.0) + 4.0 * (n + 1) + 8.0 * m + 64.0 * n;
+  if (bytes_dual) *bytes_dual = nnz * (sv + 4.0) + 4.0 * (m + 1) + 8.0 * n + 57.0 * m;
+  return PDLP_OK;
+}
+
+extern "C" const char* pdlp_last_error(const pdlp_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" void pdlp_destroy(pdlp_handle* h) {
+  if (!h) return;
+  h->release();
+  delete h;
+}

@@ -1,0 +1,109 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdlp {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
+constexpr int kTile = 2048;      // nonzeros staged in LDS per row block
+constexpr int kMaxRows = 1024;   // rows per row block
+constexpr int kElemBlocks = 2048;  // fixed grid of the elementwise kernels (deterministic partials)
+
+// A row block of a CSR matrix.  chunk < 0: rows [r0, r1) with at most kTile
+// nonzeros in total, handled in one pass through LDS.  chunk >= 0: part
+// `chunk` of `nchunks` of the single long row r0 (more than kTile nonzeros);
+// the chunk partial sums are combined in chunk order by the last chunk to
+// finish, which owns counter `slot` and partial slots [slot, slot+nchunks).
+struct RowBlock {
+  int32_t r0, r1, chunk, nchunks, slot;
+};
+
+struct DevCsr {
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* v;        // FP64 scaled values
+  const float* vf;        // FP32-rounded scaled values (nullptr unless FP32 steps)
+  const RowBlock* blocks;
+  int32_t nblocks;
+  int32_t nslots;         // chunk slots (sum of nchunks over the long rows)
+  int32_t nrows;
+  double* chunk_part;     // 2 doubles per chunk slot
+  uint32_t* chunk_cnt;    // one counter per long row
+};
+
+// Solver state in device memory.  The first 16 bytes are the status word the
+// host polls.
+struct DevState {
+  int32_t done;           // 1 once a status is set
+  int32_t status;         // PDLP_OPTIMAL ... (0 while running)
+  int64_t k;              // accepted steps
+  // step state
+  double eta;             // step size of the next attempt
+  double eta_hat;
+  double omega;
+  double sum_eta;         // sum of accepted step sizes in the epoch
+  double pending_w;       // step size of the accepted iterate not yet added to the sums
+  double kkt0, kkt_prev;
+  int64_t t;              // accepted steps in the epoch
+  int64_t attempts, restarts, evals, k_last_eval;
+  int32_t cur;            // buffer index of the current iterate
+  int32_t has_pending;
+  int32_t need_eval;      // an evaluation is due (P accepted steps since the last one)
+  int32_t initial;        // the evaluation of the starting point
+  int32_t restart_flag;   // the evaluation asked for a restart (applied by the restart kernels)
+  int32_t cand_avg;       // restart candidate / returned point is the average
+  int32_t ret_avg;
+  int32_t pad;
+  // termination parameters of this solve
+  double eps_rel;
+  int64_t max_iter;
+  // last evaluation, returned point
+  double rel_kkt, rel_gap, rel_p, rel_d, pobj, dobj;
+  int64_t n_att, n_eval;  // trace entries written
+};
+
+struct Trace {
+  int64_t cap;
+  int64_t* att_k; double* att_eta; double* att_etabar; int8_t* att_acc;
+  int64_t* ev_k; double* ev_kkt_cur; double* ev_kkt_avg; int8_t* ev_cand; int8_t* ev_reason;
+  double* ev_omega;
+};
+
+struct Params {
+  DevCsr K;     // m rows
+  DevCsr KT;    // n rows
+  int32_t m, n;
+  int32_t use_f32;
+  int32_t xcd_remap;
+  // iterates (double-buffered where a step writes a new one)
+  double* x[2];
+  double* y[2];
+  double* kx[2];          // K~ x for the current x (attempt precision)
+  double* dx;             // x' - x of the current attempt
+  double* xsum; double* ysum;
+  double* xbar; double* ybar;
+  double* x0; double* y0;
+  // problem (scaled, >= form)
+  const double* c; const double* q; const double* l; const double* u;
+  const int8_t* ineq;
+  const double* D1; const double* D2;
+  // reductions
+  // per-block partials; [nblocks + nslots] entries of NV doubles (see store_partials)
+  double* partA;          // NV = 1: ||dx||^2
+  double* partB;          // NV = 2: ||dy||^2, dy'K~dx
+  double* partE0;         // [kElemBlocks * 4]
+  double* partE1;         // NV = 8
+  double* partE2;         // NV = 6
+  uint32_t* counters;     // [4] last-block tickets
+  DevState* st;
+  Trace tr;
+  // constants
+  int64_t P;
+  double beta_suff, beta_nec, beta_art, theta, eps_zero;
+  double tie_rel;         // relative band in which the candidate comparison is a tie
+  int32_t omega_power;
+  double qnorm0, cnorm0;
+};
+
+}  // namespace pdlp

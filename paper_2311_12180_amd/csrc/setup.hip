@@ -1,0 +1,258 @@
+// One-time setup kernels: >=-form normalisation, CSR transpose, Section 2.2
+// preconditioning (Ruiz inf-norm passes, then Pock-Chambolle), scaled vectors,
+// norms and the FP32-rounded matrix copies.
+//
+// The row reductions of the preconditioner run one thread per row in storage
+// order, and the vector norms sum 4096-element blocks serially and then the
+// block sums serially, so the scaled problem is bitwise reproducible.
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include "pdlp_dev.h"
+
+namespace pdlp {
+
+// LE rows a x <= b become (-a) x >= -b (eq. (primal-dual) has only >= and = rows).
+__global__ void k_normalize(int m, const int32_t* __restrict__ rp, double* __restrict__ v,
+                            const double* __restrict__ b, const int8_t* __restrict__ rt,
+                            double* __restrict__ q, int8_t* __restrict__ ineq, int8_t* __restrict__ le,
+                            int32_t* __restrict__ rowid) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const int t = rt[i];
+    const bool isle = t == 2;
+    le[i] = isle;
+    ineq[i] = t != 0;
+    q[i] = isle ? -b[i] : b[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      if (isle) v[p] = -v[p];
+      rowid[p] = i;
+    }
+  }
+}
+
+__global__ void k_iota(int64_t nnz, int32_t* __restrict__ a) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    a[p] = (int32_t)p;
+}
+
+__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ ci, int32_t* __restrict__ cnt) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[ci[p]], 1);
+}
+
+// K' entry q is K entry perm[q] (stable sort by column keeps rows ascending).
+__global__ void k_transpose_fill(int64_t nnz, const int32_t* __restrict__ perm, const int32_t* __restrict__ rowid,
+                                 const double* __restrict__ v, int32_t* __restrict__ ciT, double* __restrict__ vT) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = perm[q];
+    ciT[q] = rowid[p];
+    vT[q] = v[p];
+  }
+}
+
+// Row norm of one CSR matrix, one thread per row, storage order:
+// mode 0: max |a|; mode 1: sum |a|^e (|a| itself when e == 1).  d = 1/sqrt(norm),
+// 1 for an empty row; D *= d.
+__global__ void k_row_factor(int nrows, const int32_t* __restrict__ rp, const double* __restrict__ v, int mode,
+                             double e, double* __restrict__ d, double* __restrict__ D) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrows; i += gridDim.x * blockDim.x) {
+    double r = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      const double a = fabs(v[p]);
+      if (mode == 0) r = a > r ? a : r;
+      else r = __dadd_rn(r, e == 1.0 ? a : pow(a, e));
+    }
+    const double f = r > 0.0 ? 1.0 / sqrt(r) : 1.0;
+    d[i] = f;
+    D[i] = __dmul_rn(D[i], f);
+  }
+}
+
+// a_ij *= d_row[i] * d_col[j]  (the product of the two factors is the same in
+// K and K', so the two copies stay exact transposes of each other).
+__global__ void k_apply_factors(int64_t nnz, const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
+                                double* __restrict__ v, const double* __restrict__ drow,
+                                const double* __restrict__ dcol) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    v[p] = __dmul_rn(v[p], __dmul_rn(drow[rowid[p]], dcol[ci[p]]));
+}
+
+// c~ = D2 c, l~ = l / D2, u~ = u / D2 ; q~ = D1 q.
+__global__ void k_scale_cols(int n, const double* __restrict__ D2, const double* __restrict__ c0,
+                             const double* __restrict__ l0, const double* __restrict__ u0, double* __restrict__ c,
+                             double* __restrict__ l, double* __restrict__ u) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    c[j] = __dmul_rn(D2[j], c0[j]);
+    l[j] = __ddiv_rn(l0[j], D2[j]);
+    u[j] = __ddiv_rn(u0[j], D2[j]);
+  }
+}
+
+__global__ void k_scale_rows(int m, const double* __restrict__ D1, double* __restrict__ q) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    q[i] = __dmul_rn(D1[i], q[i]);
+}
+
+// Blocked sum of squares: one thread per 4096-element block, serial inside.
+__global__ void k_sumsq_blocks(int64_t n, const double* __restrict__ a, double* __restrict__ part) {
+  const int64_t nb = (n + 4095) / 4096;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i0 = b * 4096, i1 = i0 + 4096 < n ? i0 + 4096 : n;
+    double s = 0.0;
+    for (int64_t i = i0; i < i1; ++i) s = __dadd_rn(s, __dmul_rn(a[i], a[i]));
+    part[b] = s;
+  }
+}
+
+__global__ void k_sum_serial(int64_t nb, const double* __restrict__ part, double* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int64_t b = 0; b < nb; ++b) s = __dadd_rn(s, part[b]);
+    *out = s;
+  }
+}
+
+// max |a| over all entries (non-negative doubles order like their bit patterns).
+__global__ void k_absmax(int64_t nnz, const double* __restrict__ v, unsigned long long* __restrict__ out) {
+  double mx = 0.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const double a = fabs(v[p]);
+    mx = a > mx ? a : mx;
+  }
+  atomicMax(out, (unsigned long long)__double_as_longlong(mx));
+}
+
+__global__ void k_to_f32(int64_t nnz, const double* __restrict__ v, float* __restrict__ f) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    f[p] = (float)v[p];
+}
+
+__global__ void k_fill(int64_t n, double* __restrict__ a, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// ---------------------------------------------------------------------------- host side
+
+static inline dim3 grid_for(int64_t n, int per = 256) {
+  int64_t g = (n + per - 1) / per;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+hipError_t setup_normalize(int m, const int32_t* rp, double* v, const double* b, const int8_t* rt, double* q,
+                           int8_t* ineq, int8_t* le, int32_t* rowid, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_normalize, grid_for(m), dim3(256), 0, s, m, rp, v, b, rt, q, ineq, le, rowid);
+  return hipGetLastError();
+}
+
+// CSR(K) -> CSR(K'): stable radix sort of the nonzero positions by column.
+hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
+                           int32_t* rpT, int32_t* ciT, double* vT, int32_t* rowidT, int32_t* perm_out,
+                           hipStream_t s) {
+  hipError_t e;
+  int32_t *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *cnt = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0, scan_bytes = 0;
+  const int64_t nz = nnz > 0 ? nnz : 1;
+  if ((e = hipMalloc(&keys_in, nz * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = hipMalloc(&keys_out, nz * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&vals_in, nz * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&cnt, (size_t)(n + 1) * sizeof(int32_t))) != hipSuccess) goto out;
+  if (nnz > 0) {
+    int end_bit = 1;
+    while (end_bit < 31 && (1ll << end_bit) < (long long)n) ++end_bit;
+    if ((e = hipMemcpyAsync(keys_in, ci, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
+    hipLaunchKernelGGL(k_iota, grid_for(nnz), dim3(256), 0, s, nnz, vals_in);
+    if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys_in, keys_out, vals_in, perm_out, (int)nnz,
+                                                0, end_bit, s)) != hipSuccess)
+      goto out;
+  }
+  if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, cnt, rpT, n + 1, s)) != hipSuccess) goto out;
+  if (scan_bytes > tmp_bytes) tmp_bytes = scan_bytes;
+  if ((e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1)) != hipSuccess) goto out;
+  if (nnz > 0) {
+    size_t tb = tmp_bytes;
+    int end_bit = 1;
+    while (end_bit < 31 && (1ll << end_bit) < (long long)n) ++end_bit;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys_in, keys_out, vals_in, perm_out, (int)nnz, 0, end_bit,
+                                                s)) != hipSuccess)
+      goto out;
+  }
+  if ((e = hipMemsetAsync(cnt, 0, (size_t)(n + 1) * sizeof(int32_t), s)) != hipSuccess) goto out;
+  if (nnz > 0) hipLaunchKernelGGL(k_col_count, grid_for(nnz), dim3(256), 0, s, nnz, ci, cnt);
+  {
+    size_t tb = tmp_bytes;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, rpT, n + 1, s)) != hipSuccess) goto out;
+  }
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_transpose_fill, grid_for(nnz), dim3(256), 0, s, nnz, perm_out, rowid, v, ciT, vT);
+    // row ids of K' entries are the column indices of K in sorted order
+    if ((e = hipMemcpyAsync(rowidT, keys_out, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      goto out;
+  }
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+out:
+  (void)hipFree(keys_in);
+  (void)hipFree(keys_out);
+  (void)hipFree(vals_in);
+  (void)hipFree(cnt);
+  (void)hipFree(tmp);
+  return e;
+}
+
+// Section 2.2 preconditioning on both copies.  D1, D2 must hold ones.
+hipError_t setup_scale(int m, int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const int32_t* rowid,
+                       double* v, const int32_t* rpT, const int32_t* ciT, const int32_t* rowidT, double* vT,
+                       int ruiz, double alpha, double* D1, double* D2, double* d1, double* d2, hipStream_t s) {
+  const int passes = ruiz + (alpha >= 0.0 ? 1 : 0);
+  for (int it = 0; it < passes; ++it) {
+    const int pc = it >= ruiz;
+    if (m > 0)
+      hipLaunchKernelGGL(k_row_factor, grid_for(m), dim3(256), 0, s, m, rp, (const double*)v, pc, 2.0 - alpha, d1, D1);
+    hipLaunchKernelGGL(k_row_factor, grid_for(n), dim3(256), 0, s, n, rpT, (const double*)vT, pc, alpha, d2, D2);
+    if (nnz > 0) {
+      hipLaunchKernelGGL(k_apply_factors, grid_for(nnz), dim3(256), 0, s, nnz, rowid, ci, v, (const double*)d1,
+                         (const double*)d2);
+      hipLaunchKernelGGL(k_apply_factors, grid_for(nnz), dim3(256), 0, s, nnz, rowidT, ciT, vT, (const double*)d2,
+                         (const double*)d1);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t setup_vectors(int m, int n, const double* D1, const double* D2, const double* c0, const double* l0,
+                         const double* u0, double* c, double* l, double* u, double* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cols, grid_for(n), dim3(256), 0, s, n, D2, c0, l0, u0, c, l, u);
+  if (m > 0) hipLaunchKernelGGL(k_scale_rows, grid_for(m), dim3(256), 0, s, m, D1, q);
+  return hipGetLastError();
+}
+
+// ||a||_2^2 in the blocked serial order; result written to *out (device).
+hipError_t setup_sumsq(int64_t n, const double* a, double* part, double* out, hipStream_t s) {
+  const int64_t nb = (n + 4095) / 4096;
+  if (nb > 0) hipLaunchKernelGGL(k_sumsq_blocks, grid_for(nb, 64), dim3(64), 0, s, n, a, part);
+  hipLaunchKernelGGL(k_sum_serial, dim3(1), dim3(1), 0, s, nb, (const double*)part, out);
+  return hipGetLastError();
+}
+
+hipError_t setup_absmax(int64_t nnz, const double* v, unsigned long long* out, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) hipLaunchKernelGGL(k_absmax, grid_for(nnz, 1024), dim3(256), 0, s, nnz, v, out);
+  return hipGetLastError();
+}
+
+hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s) {
+  if (nnz > 0) hipLaunchKernelGGL(k_to_f32, grid_for(nnz), dim3(256), 0, s, nnz, v, f);
+  return hipGetLastError();
+}
+
+hipError_t setup_fill(int64_t n, double* a, double val, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, s, n, a, val);
+  return hipGetLastError();
+}
+
+}  // namespace pdlp

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/pdlp.h declares, and rejects malformed input before touching HIP."""
+import copy
+import os
+import re
+
+import numpy as np
+import pytest
+
+import lpgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2311_12180_amd import pdlp
+    pdlp.lib()
+    return pdlp
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pdlp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdlp_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = declared_functions()
+    assert len(names) >= 13
+    lib = P.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTED) == names
+
+
+def test_default_options(P):
+    o = P.pdlp_default_options()
+    assert o.eps_rel == 1e-4 and o.eval_period == 64 and o.ruiz_iters == 10
+    assert o.pc_alpha == 1.0 and o.pw_theta == 0.5 and o.eps_zero == 1e-10
+    assert (o.beta_suff, o.beta_nec, o.beta_art) == (0.2, 0.8, 0.36)
+    assert o.a_precision == 0 and o.kkt_omega_power == 2
+
+
+def _bad(p, P, code, fragment, **opts):
+    with pytest.raises(P.PdlpError) as e:
+        P.pdlp_create(p, **opts)
+    assert e.value.code == code
+    assert fragment in str(e.value)
+    assert fragment in P.pdlp_last_error(None)
+
+
+def test_rejects_malformed_problems(P):
+    base = lpgen.mixed_lp(0, m=20, n=30)
+    p = copy.deepcopy(base); p.col_idx[3] = p.n
+    _bad(p, P, P.PDLP_ERR_DATA, "out of range")
+    p = copy.deepcopy(base); r0, r1 = p.row_ptr[0], p.row_ptr[1]
+    row = np.flatnonzero(np.diff(p.row_ptr) >= 2)[0]
+    s = p.row_ptr[row]; p.col_idx[s + 1] = p.col_idx[s]
+    _bad(p, P, P.PDLP_ERR_DATA, "duplicate column")
+    p = copy.deepcopy(base); p.val[0] = np.nan
+    _bad(p, P, P.PDLP_ERR_DATA, "not finite")
+    p = copy.deepcopy(base); p.c[1] = np.inf
+    _bad(p, P, P.PDLP_ERR_DATA, "c[1]")
+    p = copy.deepcopy(base); p.b[2] = np.nan
+    _bad(p, P, P.PDLP_ERR_DATA, "b[2]")
+    p = copy.deepcopy(base); p.l[0] = 5.0; p.u[0] = 4.0
+    _bad(p, P, P.PDLP_ERR_DATA, "bounds of x[0]")
+    p = copy.deepcopy(base); p.l[1] = np.inf; p.u[1] = np.inf
+    _bad(p, P, P.PDLP_ERR_DATA, "bounds of x[1]")
+    p = copy.deepcopy(base); p.row_type[4] = 3
+    _bad(p, P, P.PDLP_ERR_DATA, "row_type[4]")
+    p = copy.deepcopy(base); p.row_ptr = p.row_ptr.copy(); p.row_ptr[5], p.row_ptr[6] = p.row_ptr[6], p.row_ptr[5]
+    if p.row_ptr[5] > p.row_ptr[6]:
+        _bad(p, P, P.PDLP_ERR_DATA, "row_ptr decreases")
+    p = copy.deepcopy(base); p.row_ptr = p.row_ptr.copy(); p.row_ptr[0] = 1
+    _bad(p, P, P.PDLP_ERR_DATA, "row_ptr[0]")
+
+
+def test_rejects_bad_sizes_and_options(P):
+    p = lpgen.mixed_lp(0, m=10, n=12)
+    q = copy.deepcopy(p); q.n = 0
+    _bad(q, P, P.PDLP_ERR_ARG, "sizes")
+    _bad(p, P, P.PDLP_ERR_ARG, "eval_period", eval_period=0)
+    _bad(p, P, P.PDLP_ERR_ARG, "a_precision", a_precision=7)
+    _bad(p, P, P.PDLP_ERR_ARG, "pw_theta", pw_theta=1.5)
+    _bad(p, P, P.PDLP_ERR_ARG, "eps_rel", eps_rel=float("nan"))
+    _bad(p, P, P.PDLP_ERR_ARG, "max_iter", max_iter=-1)
+    _bad(p, P, P.PDLP_ERR_ARG, "kkt_omega_power", kkt_omega_power=3)
+
+
+def test_null_arguments(P):
+    lib = P.lib()
+    assert lib.pdlp_default_options(None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_create(None, None, None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_solve(None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_get_solution(None, None, None, None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_set_termination(None, 1e-4, 10, 1.0) == P.PDLP_ERR_ARG
+    lib.pdlp_destroy(None)
+    assert isinstance(P.pdlp_last_error(None), str)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    from paper_2311_12180_amd import pdlp
+    monkeypatch.setattr(pdlp, "_lib", None)
+    monkeypatch.setattr(pdlp, "LIB_PATH", "/nonexistent/libpdlp_hip.so")
+    with pytest.raises(ImportError):
+        pdlp.lib()
