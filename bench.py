@@ -36,13 +36,20 @@ def log(*a):
 
 
 def _traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (profiles/*_traffic.txt: lines 'kernel <name> fetch_bytes <F>
-    write_bytes <W>'), or None."""
+    """HBM-side bytes per launch of `kernel` from the committed rocprofv3
+    counter summary (lines 'kernel <name> fetch_bytes <F> write_bytes <W>'),
+    or None when there is none or it was taken from a different kernel source
+    (the summary records the sha256 prefix of kernels.hip)."""
+    import hashlib
     path = os.path.join(ROOT, "profiles", "step_kernels_skewed_1e6x2e6_traffic.txt")
     if not os.path.exists(path):
         return None
-    for line in open(path):
+    src = os.path.join(ROOT, "paper_2311_12180_amd", "csrc", "kernels.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    text = open(path).read()
+    if f"sha256[:16] = {cur}" not in text:
+        return None
+    for line in text.splitlines():
         parts = line.split()
         if len(parts) >= 6 and parts[0] == "kernel" and parts[1] == kernel:
             return float(parts[3]) + float(parts[5])

@@ -4,29 +4,34 @@
 // (no atomics on values, so results are bitwise reproducible run to run).  A
 // row block is either a run of short rows whose nonzeros (at most kTile) are
 // streamed once, coalesced, into LDS as products and then summed per row by a
-// power-of-two group of lanes, or one chunk of a long row whose partial sums
-// are combined in chunk order by the last chunk to finish.  The PDHG updates
-// of eq. (pdhg) are the epilogues of these row sums:
-//   k_primal : (K~'y)_j -> x'_j = proj_[l,u](x_j - (eta/omega)(c_j - (K~'y)_j))
-//   k_dual   : (K~dx)_i -> y'_i = proj(y_i + eta*omega*(q_i - (K~x)_i - 2(K~dx)_i)), dx = x' - x
-// and the last workgroup of k_dual takes the Algorithm 2 step-size decision.
+// power-of-two group of lanes, or one long row (more than kTile nonzeros)
+// swept by the whole workgroup.  No workgroup ever waits for or reads the
+// results of another workgroup of the same launch: reductions leave one
+// partial per workgroup and a single-workgroup kernel after the launch adds
+// them in a fixed order (so no device-scope fences inside the big kernels).
+//
+// The PDHG updates of eq. (pdhg) are the epilogues of the row sums:
+//   k_primal : (K~'y)_j -> x'_j = proj_[l,u](x_j - (eta/omega)(c_j - (K~'y)_j)), dx_j = x'_j - x_j
+//   k_dual   : (K~dx)_i -> y'_i = proj(y_i + eta*omega*(q_i - (K~x)_i - 2(K~dx)_i))
+//   k_decide : the Algorithm 2 step-size decision on the reduced norms.
 // Evaluation kernels form the weighted averages, eq. (kkt) for both the
-// current and the average iterate, the Section 4.1 termination quantities and
-// the Section 3.4 restart decision; restart kernels apply the restart.
+// current and the average iterate and the Section 4.1 termination quantities;
+// k_eval_decide takes the Section 3.4 restart decision; restart kernels apply it.
 #include <math.h>
 
 #include "pdlp_dev.h"
 
 namespace pdlp {
 
+constexpr int kDecideBlock = 1024;   // threads of the single-workgroup reduction kernels
+
 // ---------------------------------------------------------------------------- helpers
 
 template <typename T>
 __device__ __forceinline__ T sel(int c, T a0, T a1) { return c ? a1 : a0; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; this gives each XCD
-// a contiguous range of row blocks (neighbouring rows gather neighbouring
-// entries more often than random ones, and each XCD has its own L2).
+// Workgroups are dispatched round-robin over the 8 XCDs; with remap on, each
+// XCD gets a contiguous range of row blocks (each XCD has its own L2).
 __device__ __forceinline__ int logical_block(int nb, int remap) {
   const int i = blockIdx.x;
   if (!remap || nb < 16) return i;
@@ -41,20 +46,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic workgroup sum; the result is valid in thread 0 only.
-template <int NV>
+// Deterministic workgroup sum over NW wavefronts; the result is valid in
+// thread 0 only.  `red` holds NV * NW doubles.
+template <int NV, int NW = kBlock / 64>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red[k * 4 + w] = v[k];
+    for (int k = 0; k < NV; ++k) red[k * NW + w] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = ((red[k * 4] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+    for (int k = 0; k < NV; ++k) {
+      double s = red[k * NW];
+      for (int i = 1; i < NW; ++i) s += red[k * NW + i];
+      v[k] = s;
+    }
   }
   __syncthreads();
 }
@@ -66,16 +76,36 @@ __device__ __forceinline__ const double* values<double>(const DevCsr& M) { retur
 template <>
 __device__ __forceinline__ const float* values<float>(const DevCsr& M) { return M.vf; }
 
-// Rows [r0, r1) of a short-row block: products val * gathered vector(s) are
-// staged in LDS (coalesced matrix stream), then each row is summed by L lanes
-// (L = largest power of two <= 64 with L * rows <= kBlock) and `epi(row, sums)`
-// runs once per row on the group's first lane.
+// Row block driver: runs `epi(row, sums)` exactly once for every row of the
+// block.  Short rows: the products val * gathered vector(s) are staged in LDS
+// (coalesced matrix stream), then each row is summed by L lanes (L = largest
+// power of two <= 64 with L * rows <= kBlock) and the group's first lane runs
+// the epilogue.  A long row: the workgroup sweeps it with a stride of kBlock,
+// reduces, and thread 0 runs the epilogue.
 template <int NV, typename VT, class G, class E>
-__device__ __forceinline__ void spmv_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                          const VT* __restrict__ v, int r0, int r1,
-                                          double* __restrict__ lds, G&& gather, E&& epi) {
+__device__ __forceinline__ void spmv_block(const DevCsr& M, const RowBlock& rb, double* __restrict__ lds,
+                                           double* red, G&& gather, E&& epi) {
+  const VT* __restrict__ v = values<VT>(M);
+  const int32_t* __restrict__ rp = M.rp;
+  const int32_t* __restrict__ ci = M.ci;
+  const int r0 = rb.r0, r1 = rb.r1;
   const int e0 = rp[r0];
   const int ne = rp[r1] - e0;
+  if (ne > kTile) {
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int e = e0 + (int)threadIdx.x; e < e0 + ne; e += kBlock) {
+      const double a = (double)v[e];
+      double g[NV];
+      gather(ci[e], g);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += a * g[k];
+    }
+    block_sum<NV>(s, red);
+    if (threadIdx.x == 0) epi(r0, s);
+    return;
+  }
   for (int e = threadIdx.x; e < ne; e += kBlock) {
     const double a = (double)v[e0 + e];
     double g[NV];
@@ -106,97 +136,6 @@ __device__ __forceinline__ void spmv_rows(const int32_t* __restrict__ rp, const 
   }
 }
 
-// One chunk of a long row: workgroup-wide partial sums, then the chunk
-// partials are published; the last chunk of the row to finish (ticket
-// counter) adds them in chunk order.  Returns true in every thread of that
-// last workgroup; the row sums are then valid in thread 0.
-template <int NV, typename VT, class G>
-__device__ __forceinline__ bool spmv_chunk(const DevCsr& M, const VT* __restrict__ v, const RowBlock& rb,
-                                           double* red, int* flag, G&& gather, double (&s)[NV]) {
-  const int rs = M.rp[rb.r0], re = M.rp[rb.r0 + 1];
-  const int e0 = rs + rb.chunk * kTile;
-  const int e1 = min(re, e0 + kTile);
-#pragma unroll
-  for (int k = 0; k < NV; ++k) s[k] = 0.0;
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
-    const double a = (double)v[e];
-    double g[NV];
-    gather(M.ci[e], g);
-#pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] += a * g[k];
-  }
-  block_sum<NV>(s, red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) M.chunk_part[(rb.slot + rb.chunk) * 2 + k] = s[k];
-    __threadfence();
-    const unsigned t = atomicAdd(&M.chunk_cnt[rb.slot], 1u);
-    const int last = t == (unsigned)(rb.nchunks - 1);
-    if (last) {
-      __threadfence();
-#pragma unroll
-      for (int k = 0; k < NV; ++k) s[k] = 0.0;
-      for (int c = 0; c < rb.nchunks; ++c) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] += __builtin_nontemporal_load(&M.chunk_part[(rb.slot + c) * 2 + k]);
-      }
-      M.chunk_cnt[rb.slot] = 0;
-    }
-    *flag = last;
-  }
-  __syncthreads();
-  return *flag != 0;
-}
-
-// Row-block driver: runs `epi` once for every row of the block.
-template <int NV, typename VT, class G, class E>
-__device__ __forceinline__ void spmv_block(const DevCsr& M, const RowBlock& rb, double* lds, double* red,
-                                           int* flag, G&& gather, E&& epi) {
-  const VT* v = values<VT>(M);
-  if (rb.chunk < 0) {
-    spmv_rows<NV, VT>(M.rp, M.ci, v, rb.r0, rb.r1, lds, gather, epi);
-  } else {
-    double s[NV];
-    if (spmv_chunk<NV, VT>(M, v, rb, red, flag, gather, s) && threadIdx.x == 0) epi(rb.r0, s);
-  }
-}
-
-// Last-workgroup election: true in every thread of the workgroup that
-// finishes last (ticket counter `cnt`, reset by that workgroup).
-__device__ __forceinline__ bool last_block(uint32_t* cnt, int* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned t = atomicAdd(cnt, 1u);
-    *flag = t == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (*flag) __threadfence();
-  return *flag != 0;
-}
-
-// Per-workgroup partial sums of the row epilogues.  A short-row block owns
-// slot b.  The epilogue of a long row runs in whichever chunk finishes last,
-// so its contribution goes to the row's own slot nblocks + slot (and every
-// chunk block writes zero to slot b): the final reduction then adds the same
-// numbers in the same order on every run.
-template <int NV>
-__device__ __forceinline__ void store_partials(double* part, const DevCsr& M, const RowBlock& rb, int b,
-                                               const double (&acc)[NV], const int* flag) {
-  if (threadIdx.x != 0) return;
-  if (rb.chunk < 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[NV * b + k] = acc[k];
-  } else {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) part[NV * b + k] = 0.0;
-    if (*flag) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) part[NV * (M.nblocks + rb.slot) + k] = acc[k];
-    }
-  }
-}
-
 __device__ __forceinline__ double proj_lambda(double g, double l, double u) {
   const bool lf = isfinite(l), uf = isfinite(u);
   if (lf && uf) return g;
@@ -217,7 +156,6 @@ template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_primal(Params p) {
   __shared__ double lds[kTile];
   __shared__ double red[4];
-  __shared__ int flag;
   const DevState* st = p.st;
   if (attempt_idle(st)) return;
   const int cur = st->cur;
@@ -237,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Params p) {
   const RowBlock rb = p.KT.blocks[b];
   double acc[1] = {0.0};
   spmv_block<1, VT>(
-      p.KT, rb, lds, red, &flag, [&](int i, double* g) { g[0] = y[i]; },
+      p.KT, rb, lds, red, [&](int i, double* g) { g[0] = y[i]; },
       [&](int j, const double* s) {
         const double xj = x[j];
         if (pend) xsum[j] += pw * xj;
@@ -251,12 +189,74 @@ __global__ __launch_bounds__(kBlock) void k_primal(Params p) {
         acc[0] += d * d;
       });
   block_sum<1>(acc, red);
-  store_partials<1>(p.partA, p.KT, rb, b, acc, &flag);
+  if (threadIdx.x == 0) p.partA[b] = acc[0];
 }
 
-// Algorithm 2 decision on the reduced norms (single thread).
-__device__ void step_decision(const Params& p, double nx, double ny, double dyk) {
+// Dual step fused with the K~ product, one pass over the rows of K~.  It
+// gathers dx = x' - x (written by the primal kernel), so K~dx, and with it the
+// step bound's denominator dy'K~dx, is a direct product rather than the
+// difference of two nearly equal products.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_dual(Params p) {
+  __shared__ double lds[kTile];
+  __shared__ double red[2 * 4];
+  const DevState* st = p.st;
+  if (attempt_idle(st)) return;
+  const int cur = st->cur;
+  const double sigma = st->eta * st->omega;
+  const int pend = st->has_pending;
+  const double pw = st->pending_w;
+  const double* __restrict__ dx = p.dx;
+  const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
+  double* __restrict__ yn = sel(cur, p.y[1], p.y[0]);
+  const double* __restrict__ kx = sel(cur, p.kx[0], p.kx[1]);
+  double* __restrict__ kxn = sel(cur, p.kx[1], p.kx[0]);
+  double* __restrict__ ysum = p.ysum;
+  const double* __restrict__ q = p.q;
+  const int8_t* __restrict__ ineq = p.ineq;
+  const int b = logical_block(p.K.nblocks, p.xcd_remap);
+  const RowBlock rb = p.K.blocks[b];
+  double acc[2] = {0.0, 0.0};
+  spmv_block<1, VT>(
+      p.K, rb, lds, red, [&](int j, double* g) { g[0] = dx[j]; },
+      [&](int i, const double* s) {
+        // s[0] = (K~ dx)_i; K~(2x' - x) = K~x + 2 K~dx and K~x' = K~x + K~dx
+        const double yi = y[i];
+        if (pend) ysum[i] += pw * yi;
+        const double kxo = kx[i], kd = s[0];
+        double v = yi + sigma * (q[i] - (kxo + 2.0 * kd));
+        if (ineq[i] && v < 0.0) v = 0.0;
+        yn[i] = v;
+        kxn[i] = kxo + kd;
+        const double d = v - yi;
+        acc[0] += d * d;
+        acc[1] += d * kd;
+      });
+  block_sum<2>(acc, red);
+  if (threadIdx.x == 0) {
+    p.partB[2 * b] = acc[0];
+    p.partB[2 * b + 1] = acc[1];
+  }
+}
+
+// Algorithm 2 decision on the reduced norms (single workgroup): eta_bar =
+// (omega ||dx||^2 + ||dy||^2 / omega) / (2 |dy'K dx|), eta' = min((1 - (k+2)^-0.3)
+// eta_bar, (1 + (k+2)^-0.6) eta); accept when eta <= eta_bar.  It also clears
+// the restart flag of the previous evaluation (its restart kernels have run).
+__global__ __launch_bounds__(kDecideBlock) void k_decide(Params p) {
+  __shared__ double red[3 * (kDecideBlock / 64)];
   DevState* st = p.st;
+  if (threadIdx.x == 0 && st->restart_flag) st->restart_flag = 0;
+  if (attempt_idle(st)) return;
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < p.KT.nblocks; i += kDecideBlock) r[0] += p.partA[i];
+  for (int i = threadIdx.x; i < p.K.nblocks; i += kDecideBlock) {
+    r[1] += p.partB[2 * i];
+    r[2] += p.partB[2 * i + 1];
+  }
+  block_sum<3, kDecideBlock / 64>(r, red);
+  if (threadIdx.x != 0) return;
+  const double nx = r[0], ny = r[1], dyk = r[2];
   const double eta = st->eta, omega = st->omega;
   const double num = omega * nx + ny / omega;
   const double den = 2.0 * fabs(dyk);
@@ -293,65 +293,6 @@ __device__ void step_decision(const Params& p, double nx, double ny, double dyk)
   } else {
     st->has_pending = 0;
     st->eta = eta_next;
-  }
-}
-
-// Dual step fused with the K~ product, one pass over the rows of K~: it
-// gathers dx = x' - x (written by the primal kernel), so K~dx, and with it the
-// step bound's denominator dy'K~dx, is a direct product rather than the
-// difference of two nearly equal products.  The last workgroup reduces
-// ||dx||^2, ||dy||^2, dy'K~dx and decides the step.
-template <typename VT>
-__global__ __launch_bounds__(kBlock) void k_dual(Params p) {
-  __shared__ double lds[kTile];
-  __shared__ double red[3 * 4];
-  __shared__ int flag;
-  DevState* st = p.st;
-  if (attempt_idle(st)) return;
-  const int cur = st->cur;
-  const double sigma = st->eta * st->omega;
-  const int pend = st->has_pending;
-  const double pw = st->pending_w;
-  const double* __restrict__ dx = p.dx;
-  const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
-  double* __restrict__ yn = sel(cur, p.y[1], p.y[0]);
-  const double* __restrict__ kx = sel(cur, p.kx[0], p.kx[1]);
-  double* __restrict__ kxn = sel(cur, p.kx[1], p.kx[0]);
-  double* __restrict__ ysum = p.ysum;
-  const double* __restrict__ q = p.q;
-  const int8_t* __restrict__ ineq = p.ineq;
-  const int b = logical_block(p.K.nblocks, p.xcd_remap);
-  const RowBlock rb = p.K.blocks[b];
-  double acc[2] = {0.0, 0.0};
-  spmv_block<1, VT>(
-      p.K, rb, lds, red, &flag, [&](int j, double* g) { g[0] = dx[j]; },
-      [&](int i, const double* s) {
-        // s[0] = (K~ dx)_i; K~(2x' - x) = K~x + 2 K~dx and K~x' = K~x + K~dx
-        const double yi = y[i];
-        if (pend) ysum[i] += pw * yi;
-        const double kxo = kx[i], kd = s[0];
-        double v = yi + sigma * (q[i] - (kxo + 2.0 * kd));
-        if (ineq[i] && v < 0.0) v = 0.0;
-        yn[i] = v;
-        kxn[i] = kxo + kd;
-        const double d = v - yi;
-        acc[0] += d * d;
-        acc[1] += d * kd;
-      });
-  block_sum<2>(acc, red);
-  store_partials<2>(p.partB, p.K, rb, b, acc, &flag);
-  if (!last_block(&p.counters[0], &flag)) return;
-  double r[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < p.KT.nblocks + p.KT.nslots; i += kBlock)
-    r[0] += __builtin_nontemporal_load(&p.partA[i]);
-  for (int i = threadIdx.x; i < p.K.nblocks + p.K.nslots; i += kBlock) {
-    r[1] += __builtin_nontemporal_load(&p.partB[2 * i]);
-    r[2] += __builtin_nontemporal_load(&p.partB[2 * i + 1]);
-  }
-  block_sum<3>(r, red);
-  if (threadIdx.x == 0) {
-    step_decision(p, r[0], r[1], r[2]);
-    p.counters[0] = 0;
   }
 }
 
@@ -402,7 +343,6 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
 __global__ __launch_bounds__(kBlock) void k_eval_rows(Params p) {
   __shared__ double lds[2 * kTile];
   __shared__ double red[8 * 4];
-  __shared__ int flag;
   const DevState* st = p.st;
   if (eval_idle(st)) return;
   const int cur = st->cur, init = st->initial, pend = st->has_pending;
@@ -414,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_rows(Params p) {
   const RowBlock rb = p.K.blocks[b];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   spmv_block<2, double>(
-      p.K, rb, lds, red, &flag,
+      p.K, rb, lds, red,
       [&](int j, double* g) {
         g[0] = x[j];
         g[1] = xb[j];
@@ -448,13 +388,78 @@ __global__ __launch_bounds__(kBlock) void k_eval_rows(Params p) {
         }
       });
   block_sum<8>(acc, red);
-  store_partials<8>(p.partE1, p.K, rb, b, acc, &flag);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p.partE1[8 * b + k] = acc[k];
+  }
 }
 
-__device__ void eval_decision(const Params& p, const double* S) {
+// Rows of K~': K~'y and K~'y_bar (FP64 matrix), lambda = proj_Lambda(c - K~'y),
+// the dual residual (scaled, and unscaled by D2^-1), l'lambda+ - u'lambda-.
+__global__ __launch_bounds__(kBlock) void k_eval_cols(Params p) {
+  __shared__ double lds[2 * kTile];
+  __shared__ double red[6 * 4];
+  const DevState* st = p.st;
+  if (eval_idle(st)) return;
+  const int cur = st->cur;
+  const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
+  const double* __restrict__ yb = p.ybar;
+  const int b = logical_block(p.KT.nblocks, p.xcd_remap);
+  const RowBlock rb = p.KT.blocks[b];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  spmv_block<2, double>(
+      p.KT, rb, lds, red,
+      [&](int i, double* g) {
+        g[0] = y[i];
+        g[1] = yb[i];
+      },
+      [&](int j, const double* s) {
+        const double cj = p.c[j], lj = p.l[j], uj = p.u[j], d2 = p.D2[j];
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const double g = cj - s[it];
+          const double lam = proj_lambda(g, lj, uj);
+          const double rd = g - lam;
+          acc[0 + it] += rd * rd;
+          const double ru = rd / d2;
+          acc[2 + it] += ru * ru;
+          const double lp = lam > 0.0 ? lam : 0.0, lm = lam < 0.0 ? -lam : 0.0;
+          acc[4 + it] += (lp > 0.0 ? lj * lp : 0.0) - (lm > 0.0 ? uj * lm : 0.0);
+        }
+      });
+  block_sum<6>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p.partE2[6 * b + k] = acc[k];
+  }
+}
+
+// Reduce every evaluation partial (single workgroup, fixed order) and decide:
+// termination (Section 4.1) on both iterates, else the restart candidate and
+// the restart criteria (Section 3.4), the primal weight update (Section 2.2).
+__global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0_blocks) {
+  __shared__ double red[18 * (kDecideBlock / 64)];
+  DevState* st = p.st;
+  if (eval_idle(st)) return;
+  double S[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) S[k] = 0.0;
+  for (int i = threadIdx.x; i < n_e0_blocks; i += kDecideBlock) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S[k] += p.partE0[4 * i + k];
+  }
+  for (int i = threadIdx.x; i < p.K.nblocks; i += kDecideBlock) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) S[4 + k] += p.partE1[8 * i + k];
+  }
+  for (int i = threadIdx.x; i < p.KT.nblocks; i += kDecideBlock) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[12 + k] += p.partE2[6 * i + k];
+  }
+  block_sum<18, kDecideBlock / 64>(S, red);
+  if (threadIdx.x != 0) return;
   // S: 0 c'x 1 c'xb 2 |x-x0|^2 3 |xb-x0|^2 | 4,5 rp2 scaled 6,7 rp2 unscaled 8,9 q'y 10,11 |y-y0|^2
   //    | 12,13 rd2 scaled 14,15 rd2 unscaled 16,17 l'lam+ - u'lam-     (pairs: current, average)
-  DevState* st = p.st;
   const double omega = st->omega;
   double pobj[2], dobj[2], rel[2], rg[2], rpr[2], rdr[2];
   for (int it = 0; it < 2; ++it) {
@@ -513,7 +518,6 @@ __device__ void eval_decision(const Params& p, const double* S) {
     return;
   }
   store(avg_better);
-  // Section 3.4: restart candidate, then criteria (i)-(iii)
   const double kc_cur = kkt_w(0, omega), kc_avg = kkt_w(1, omega);
   // the current iterate only when clearly better: differences at rounding level
   // (e.g. one step into an epoch, where the average is the iterate) go to the average
@@ -525,9 +529,8 @@ __device__ void eval_decision(const Params& p, const double* S) {
   else if ((double)st->t >= p.beta_art * (double)st->k) reason = 3;
   double om = omega;
   if (reason) {
-    // Section 2.2 primal weight update, smoothed in log space
-    const double dx = sqrt(S[2 + cand]), dy = sqrt(S[10 + cand]);
-    if (dx > p.eps_zero && dy > p.eps_zero) om = exp(p.theta * log(dy / dx) + (1.0 - p.theta) * log(omega));
+    const double dxn = sqrt(S[2 + cand]), dyn = sqrt(S[10 + cand]);
+    if (dxn > p.eps_zero && dyn > p.eps_zero) om = exp(p.theta * log(dyn / dxn) + (1.0 - p.theta) * log(omega));
     st->omega = om;
     st->restart_flag = 1;
     st->cand_avg = cand;
@@ -550,66 +553,6 @@ __device__ void eval_decision(const Params& p, const double* S) {
   }
 }
 
-// Rows of K~': K~'y and K~'y_bar (FP64 matrix), lambda = proj_Lambda(c - K~'y),
-// the dual residual (scaled, and unscaled by D2^-1), l'lambda+ - u'lambda-;
-// the last workgroup reduces every evaluation partial and decides.
-__global__ __launch_bounds__(kBlock) void k_eval_cols(Params p, int n_e0_blocks) {
-  __shared__ double lds[2 * kTile];
-  __shared__ double red[18 * 4];
-  __shared__ int flag;
-  const DevState* st = p.st;
-  if (eval_idle(st)) return;
-  const int cur = st->cur;
-  const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
-  const double* __restrict__ yb = p.ybar;
-  const int b = logical_block(p.KT.nblocks, p.xcd_remap);
-  const RowBlock rb = p.KT.blocks[b];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  spmv_block<2, double>(
-      p.KT, rb, lds, red, &flag,
-      [&](int i, double* g) {
-        g[0] = y[i];
-        g[1] = yb[i];
-      },
-      [&](int j, const double* s) {
-        const double cj = p.c[j], lj = p.l[j], uj = p.u[j], d2 = p.D2[j];
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {
-          const double g = cj - s[it];
-          const double lam = proj_lambda(g, lj, uj);
-          const double rd = g - lam;
-          acc[0 + it] += rd * rd;
-          const double ru = rd / d2;
-          acc[2 + it] += ru * ru;
-          const double lp = lam > 0.0 ? lam : 0.0, lm = lam < 0.0 ? -lam : 0.0;
-          acc[4 + it] += (lp > 0.0 ? lj * lp : 0.0) - (lm > 0.0 ? uj * lm : 0.0);
-        }
-      });
-  block_sum<6>(acc, red);
-  store_partials<6>(p.partE2, p.KT, rb, b, acc, &flag);
-  if (!last_block(&p.counters[1], &flag)) return;
-  double S[18];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) S[k] = 0.0;
-  for (int i = threadIdx.x; i < n_e0_blocks; i += kBlock) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) S[k] += __builtin_nontemporal_load(&p.partE0[4 * i + k]);
-  }
-  for (int i = threadIdx.x; i < p.K.nblocks + p.K.nslots; i += kBlock) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) S[4 + k] += __builtin_nontemporal_load(&p.partE1[8 * i + k]);
-  }
-  for (int i = threadIdx.x; i < p.KT.nblocks + p.KT.nslots; i += kBlock) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) S[12 + k] += __builtin_nontemporal_load(&p.partE2[6 * i + k]);
-  }
-  block_sum<18>(S, red);
-  if (threadIdx.x == 0) {
-    eval_decision(p, S);
-    p.counters[1] = 0;
-  }
-}
-
 // ---------------------------------------------------------------------------- restart
 
 // x-space part of a restart: z^{n+1,0} = candidate, sums cleared.
@@ -626,13 +569,13 @@ __global__ __launch_bounds__(kBlock) void k_restart_x(Params p) {
   }
 }
 
-// y-space part of a restart, plus K~x of the new x (in the precision of the steps).
+// y-space part of a restart, plus K~x of the new x (in the precision of the
+// steps).  The flag is cleared by the next k_decide.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_restart_y(Params p) {
   __shared__ double lds[kTile];
   __shared__ double red[4];
-  __shared__ int flag;
-  DevState* st = p.st;
+  const DevState* st = p.st;
   if (!st->restart_flag) return;
   const int cur = st->cur, cand = st->cand_avg;
   const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
@@ -641,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_restart_y(Params p) {
   const int b = logical_block(p.K.nblocks, p.xcd_remap);
   const RowBlock rb = p.K.blocks[b];
   spmv_block<1, VT>(
-      p.K, rb, lds, red, &flag, [&](int j, double* g) { g[0] = x[j]; },
+      p.K, rb, lds, red, [&](int j, double* g) { g[0] = x[j]; },
       [&](int i, const double* s) {
         const double yc = cand ? p.ybar[i] : y[i];
         y[i] = yc;
@@ -649,11 +592,6 @@ __global__ __launch_bounds__(kBlock) void k_restart_y(Params p) {
         p.ysum[i] = 0.0;
         kx[i] = s[0];
       });
-  if (!last_block(&p.counters[2], &flag)) return;
-  if (threadIdx.x == 0) {
-    st->restart_flag = 0;
-    p.counters[2] = 0;
-  }
 }
 
 // ---------------------------------------------------------------------------- start, output
@@ -670,6 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_init_x(Params p, const double* __res
     p.xsum[j] = 0.0;
     p.xbar[j] = v;
     p.x0[j] = v;
+    p.dx[j] = 0.0;
   }
 }
 
@@ -696,7 +635,6 @@ __global__ __launch_bounds__(kBlock) void k_output_cols(Params p, double* __rest
                                                         double* __restrict__ rco) {
   __shared__ double lds[kTile];
   __shared__ double red[4];
-  __shared__ int flag;
   const DevState* st = p.st;
   const int cur = st->cur, ra = st->ret_avg;
   const double* __restrict__ x = ra ? p.xbar : sel(cur, p.x[0], p.x[1]);
@@ -704,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_output_cols(Params p, double* __rest
   const int b = logical_block(p.KT.nblocks, p.xcd_remap);
   const RowBlock rb = p.KT.blocks[b];
   spmv_block<1, double>(
-      p.KT, rb, lds, red, &flag, [&](int i, double* g) { g[0] = y[i]; },
+      p.KT, rb, lds, red, [&](int i, double* g) { g[0] = y[i]; },
       [&](int j, const double* s) {
         const double d2 = p.D2[j];
         xo[j] = d2 * x[j];
@@ -750,11 +688,16 @@ void launch_dual(const Params& p, hipStream_t s) {
   else hipLaunchKernelGGL(k_dual<double>, dim3(p.K.nblocks), dim3(kBlock), 0, s, p);
 }
 
+void launch_decide(const Params& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideBlock), 0, s, p);
+}
+
 void launch_eval(const Params& p, hipStream_t s) {
   const int ge = elem_grid(p.n);
   hipLaunchKernelGGL(k_eval_x, dim3(ge), dim3(kBlock), 0, s, p);
   hipLaunchKernelGGL(k_eval_rows, dim3(p.K.nblocks), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_eval_cols, dim3(p.KT.nblocks), dim3(kBlock), 0, s, p, ge);
+  hipLaunchKernelGGL(k_eval_cols, dim3(p.KT.nblocks), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_eval_decide, dim3(1), dim3(kDecideBlock), 0, s, p, ge);
   hipLaunchKernelGGL(k_restart_x, dim3(ge), dim3(kBlock), 0, s, p);
   if (p.use_f32) hipLaunchKernelGGL(k_restart_y<float>, dim3(p.K.nblocks), dim3(kBlock), 0, s, p);
   else hipLaunchKernelGGL(k_restart_y<double>, dim3(p.K.nblocks), dim3(kBlock), 0, s, p);

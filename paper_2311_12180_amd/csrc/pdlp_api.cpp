@@ -3,7 +3,7 @@
 // pdlp_create validates the LP on the host, uploads it once, and builds the
 // scaled >=-form problem on the device (normalisation, transpose, Section 2.2
 // preconditioning).  pdlp_solve runs Algorithm 1 as a captured hipGraph of
-// attempt slots (primal kernel + dual kernel with the Algorithm 2 decision)
+// attempt slots (primal kernel, dual kernel, single-workgroup Algorithm 2 decision)
 // followed by the evaluation/restart kernels; the host only reads the 16-byte
 // status word between graph launches, pipelined one batch behind.
 #include <hip/hip_runtime.h>
@@ -22,6 +22,7 @@
 namespace pdlp {
 void launch_primal(const Params& p, hipStream_t s);
 void launch_dual(const Params& p, hipStream_t s);
+void launch_decide(const Params& p, hipStream_t s);
 void launch_eval(const Params& p, hipStream_t s);
 void launch_init(const Params& p, const double* xs, const double* ys, const int8_t* le, hipStream_t s);
 void launch_output(const Params& p, double* xo, double* yo, double* rco, const int8_t* le, hipStream_t s);
@@ -61,33 +62,32 @@ inline void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipFail{e, what};
 }
 
-// Greedy row-block partition of a CSR matrix (see RowBlock).
-std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows, int* nslots) {
-  std::vector<RowBlock> out;
-  int slots = 0;
+// Row-block partition of a CSR matrix (see RowBlock): every row longer than
+// kTile becomes a block of its own, listed first so that these heavier blocks
+// are dispatched before the short ones; the runs of short rows between them
+// are cut greedily at kTile nonzeros or kMaxRows rows.
+std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
+  std::vector<RowBlock> longs, shorts;
   int r = 0;
   while (r < nrows) {
-    const int len = rp[r + 1] - rp[r];
-    if (len > kTile) {
-      const int nch = (len + kTile - 1) / kTile;
-      for (int c = 0; c < nch; ++c) out.push_back(RowBlock{r, r + 1, c, nch, slots});
-      slots += nch;
+    if (rp[r + 1] - rp[r] > kTile) {
+      longs.push_back(RowBlock{r, r + 1});
       ++r;
       continue;
     }
     const int r0 = r;
     int nz = 0;
     while (r < nrows && r - r0 < kMaxRows) {
-      const int l2 = rp[r + 1] - rp[r];
-      if (l2 > kTile || nz + l2 > kTile) break;
-      nz += l2;
+      const int len = rp[r + 1] - rp[r];
+      if (len > kTile || nz + len > kTile) break;
+      nz += len;
       ++r;
     }
-    out.push_back(RowBlock{r0, r, -1, 0, 0});
+    shorts.push_back(RowBlock{r0, r});
   }
-  if (out.empty()) out.push_back(RowBlock{0, 0, -1, 0, 0});
-  *nslots = slots;
-  return out;
+  longs.insert(longs.end(), shorts.begin(), shorts.end());
+  if (longs.empty()) longs.push_back(RowBlock{0, 0});
+  return longs;
 }
 
 }  // namespace
@@ -271,6 +271,7 @@ static void build_graph(pdlp_handle* h) {
     for (int s = 0; s < h->slots_per_round; ++s) {
       launch_primal(h->P, h->cap_stream);
       launch_dual(h->P, h->cap_stream);
+      launch_decide(h->P, h->cap_stream);
     }
     launch_eval(h->P, h->cap_stream);
   }
@@ -403,22 +404,19 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     // --- row-block partitions
     std::vector<int32_t> hrpT((size_t)n + 1);
     check(hipMemcpy(hrpT.data(), h->rpT, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
-    int slotsK = 0, slotsT = 0;
-    std::vector<RowBlock> bk = partition_rows(hrp.data(), m, &slotsK);
-    std::vector<RowBlock> bt = partition_rows(hrpT.data(), n, &slotsT);
+    std::vector<RowBlock> bk = partition_rows(hrp.data(), m);
+    std::vector<RowBlock> bt = partition_rows(hrpT.data(), n);
     RowBlock* dbk = h->dalloc<RowBlock>(bk.size());
     RowBlock* dbt = h->dalloc<RowBlock>(bt.size());
     check(hipMemcpyAsync(dbk, bk.data(), bk.size() * sizeof(RowBlock), kind, s), "upload blocks");
     check(hipMemcpyAsync(dbt, bt.data(), bt.size() * sizeof(RowBlock), kind, s), "upload blocks");
     Params& P = h->P;
-    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), slotsK, m,
-                 h->dalloc<double>(2 * (size_t)slotsK), h->dalloc<uint32_t>((size_t)slotsK)};
-    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), slotsT, n,
-                  h->dalloc<double>(2 * (size_t)slotsT), h->dalloc<uint32_t>((size_t)slotsT)};
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n};
     P.m = m;
     P.n = n;
     P.use_f32 = opt.a_precision == PDLP_A_FP32;
-    P.xcd_remap = 1;
+    P.xcd_remap = 0;
     for (int k = 0; k < 2; ++k) {
       P.x[k] = h->dalloc<double>(n);
       P.y[k] = h->dalloc<double>(m);
@@ -438,13 +436,11 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     P.ineq = h->ineq;
     P.D1 = h->D1;
     P.D2 = h->D2;
-    const size_t slots_k = bk.size() + (size_t)slotsK, slots_t = bt.size() + (size_t)slotsT;
-    P.partA = h->dalloc<double>(slots_t);
-    P.partB = h->dalloc<double>(2 * slots_k);
+    P.partA = h->dalloc<double>(bt.size());
+    P.partB = h->dalloc<double>(2 * bk.size());
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
-    P.partE1 = h->dalloc<double>(8 * slots_k);
-    P.partE2 = h->dalloc<double>(6 * slots_t);
-    P.counters = h->dalloc<uint32_t>(8);
+    P.partE1 = h->dalloc<double>(8 * bk.size());
+    P.partE2 = h->dalloc<double>(6 * bt.size());
     h->st = h->dalloc<DevState>(1);
     P.st = h->st;
     if (opt.trace > 0) {
@@ -600,6 +596,7 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
             for (int k = 0; k < h->slots_per_round; ++k) {
               launch_primal(h->P, s);
               launch_dual(h->P, s);
+              launch_decide(h->P, s);
             }
             launch_eval(h->P, s);
           }
@@ -746,6 +743,7 @@ extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* m
         check(hipEventRecord(ev[4 * k + 2], s), "event");
         launch_dual(h->P, s);
         check(hipEventRecord(ev[4 * k + 3], s), "event");
+        launch_decide(h->P, s);
       }
       launch_eval(h->P, s);
       check(hipStreamSynchronize(s), "sync");

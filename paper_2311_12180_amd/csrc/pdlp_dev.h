@@ -10,13 +10,11 @@ constexpr int kTile = 2048;      // nonzeros staged in LDS per row block
 constexpr int kMaxRows = 1024;   // rows per row block
 constexpr int kElemBlocks = 2048;  // fixed grid of the elementwise kernels (deterministic partials)
 
-// A row block of a CSR matrix.  chunk < 0: rows [r0, r1) with at most kTile
-// nonzeros in total, handled in one pass through LDS.  chunk >= 0: part
-// `chunk` of `nchunks` of the single long row r0 (more than kTile nonzeros);
-// the chunk partial sums are combined in chunk order by the last chunk to
-// finish, which owns counter `slot` and partial slots [slot, slot+nchunks).
+// A row block of a CSR matrix: rows [r0, r1).  Either short rows with at most
+// kTile nonzeros in total (handled in one pass through LDS), or one long row
+// with more than kTile nonzeros (swept by the whole workgroup).
 struct RowBlock {
-  int32_t r0, r1, chunk, nchunks, slot;
+  int32_t r0, r1;
 };
 
 struct DevCsr {
@@ -24,12 +22,9 @@ struct DevCsr {
   const int32_t* ci;
   const double* v;        // FP64 scaled values
   const float* vf;        // FP32-rounded scaled values (nullptr unless FP32 steps)
-  const RowBlock* blocks;
+  const RowBlock* blocks; // long rows first, then runs of short rows
   int32_t nblocks;
-  int32_t nslots;         // chunk slots (sum of nchunks over the long rows)
   int32_t nrows;
-  double* chunk_part;     // 2 doubles per chunk slot
-  uint32_t* chunk_cnt;    // one counter per long row
 };
 
 // Solver state in device memory.  The first 16 bytes are the status word the
@@ -89,13 +84,12 @@ struct Params {
   const int8_t* ineq;
   const double* D1; const double* D2;
   // reductions
-  // per-block partials; [nblocks + nslots] entries of NV doubles (see store_partials)
-  double* partA;          // NV = 1: ||dx||^2
-  double* partB;          // NV = 2: ||dy||^2, dy'K~dx
+  // one partial (NV doubles) per workgroup, added in order by the decision kernels
+  double* partA;          // [K'.nblocks]      ||dx||^2
+  double* partB;          // [K.nblocks * 2]   ||dy||^2, dy'K~dx
   double* partE0;         // [kElemBlocks * 4]
-  double* partE1;         // NV = 8
-  double* partE2;         // NV = 6
-  uint32_t* counters;     // [4] last-block tickets
+  double* partE1;         // [K.nblocks * 8]
+  double* partE2;         // [K'.nblocks * 6]
   DevState* st;
   Trace tr;
   // constants
