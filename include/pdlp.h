@@ -92,6 +92,16 @@ typedef struct {
   int32_t poll_every;         /* 4: graph launches between two reads of the 8-byte status word */
   int32_t graph;              /* 1: the inner loop is a captured hipGraph; 0: the same kernels
                                  launched one by one (for callers that cannot use graphs) */
+  int32_t spmv_layout;        /* -1: chosen per matrix at create by timing plain products (default);
+                                 0: row blocks; 1: column panels (one per XCD) with a second pass
+                                 that adds each row's panel sums; 2: row blocks with contiguous
+                                 block ranges per XCD.  The layout changes the order of floating-point
+                                 sums; fix it for bitwise reproducibility across handles */
+  int32_t batch_lanes;        /* batch handles: 0 = lanes per row chosen per LP class by timing
+                                 capped solves at pdlp_create_batch (default); 1..64 (a power of
+                                 two) = that many lanes for every row */
+  int32_t batch_grid;         /* batch handles: workgroups of the persistent launch, 0 = chosen by
+                                 timing (default) */
 } pdlp_options;
 
 typedef struct {
@@ -104,8 +114,10 @@ typedef struct {
   double rel_kkt, rel_gap, rel_pres, rel_dres;   /* Section 4.1, on the original LP */
   double primal_obj, dual_obj;
   double omega, eta_hat;      /* primal weight and step size at exit */
-  double setup_s;             /* pdlp_create: upload, transpose, scaling */
+  double setup_s;             /* pdlp_create: upload, transpose, scaling, layout choice */
   double solve_s;             /* pdlp_solve wall time */
+  int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout); for an LP
+                                   of a batch: its lanes per row of K and of K' */
 } pdlp_info;
 
 /* Scaled-space state of the current iterate (for parity checks and resume). */
@@ -181,6 +193,50 @@ int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* ms_primal, d
  * (matrix stream, row pointers, one read of each gathered vector, the per-row
  * vector reads and writes). */
 int pdlp_step_bytes(pdlp_handle* h, double* bytes_primal, double* bytes_dual);
+
+/* ---- Batches: many independent LPs solved by one persistent launch ----
+ *
+ * The LPs are packed block-diagonally (LP k owns the next m_k rows and n_k
+ * columns); Algorithm 1 with its own restarts, primal weight and Section 4.1
+ * termination runs for each LP, all with the options of the handle.  A
+ * workgroup takes the next LP from a device queue (most nonzeros first), keeps
+ * its scalar state on chip, and sweeps its rows with a per-LP number of lanes
+ * per row taken from the batch schedule.  Every LP is preconditioned on its own
+ * (the Section 2.2 scalings act row- and column-wise, so packing does not
+ * mix LPs). */
+
+/* Create a handle for ps[0 .. count-1] (each validated as in pdlp_create; the
+ * error message names the first bad LP).  The totals of rows, columns and
+ * nonzeros must stay below 2^31.  Unless batch_lanes and batch_grid are both
+ * fixed, create times capped solves (64 accepted steps per LP) to choose the
+ * schedule.  Single-LP entry points (pdlp_solve, pdlp_get_solution,
+ * pdlp_get_iterate, pdlp_set_warm_start, pdlp_profile_attempts,
+ * pdlp_step_bytes) return PDLP_ERR_STATE on a batch handle; pdlp_get_scaling
+ * returns the packed arrays and pdlp_get_trace the trace of LP 0. */
+int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pdlp_options* o, void* hip_stream,
+                      pdlp_handle** out);
+
+/* Warm start of LP idx (x0[n_idx], y0[m_idx], user orientation), or of every
+ * LP when idx = -1 (x0, y0 packed in LP order, omega0 for all).  NULL for x0
+ * or y0 means zero for that part; both NULL clears the warm start.
+ * PDLP_ERR_ARG for idx out of range, PDLP_ERR_DATA for non-finite values. */
+int pdlp_set_warm_start_batch(pdlp_handle* h, int32_t idx, const double* x0, const double* y0, double omega0);
+
+/* Solve every LP of the batch from its starting point in one persistent launch;
+ * the host waits once.  time_limit_s bounds the whole launch (an LP still
+ * running then ends with PDLP_TIME_LIMIT); an LP whose attempts are rejected
+ * 1000 times in a row ends with PDLP_NUMERICAL_ERROR. */
+int pdlp_solve_batch(pdlp_handle* h);
+
+/* Solution of LP idx (x[n_idx], y[m_idx], reduced_cost[n_idx], *info), or of
+ * every LP when idx = -1 (packed in LP order, info[count]).  solve_s is the
+ * time of the whole batch solve.  PDLP_ERR_STATE before pdlp_solve_batch. */
+int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, double* y, double* reduced_cost,
+                            pdlp_info* info);
+
+/* Schedule of the persistent launch: lanes[2*count] (lanes per row of K and
+ * of K' for each LP) and the number of workgroups; NULL to skip either. */
+int pdlp_batch_schedule(pdlp_handle* h, int32_t* lanes, int32_t* grid);
 
 /* Last error message of h, or of the last failed pdlp_create on this thread
  * when h is NULL.  Never NULL. */

@@ -24,9 +24,15 @@ void launch_primal(const Params& p, hipStream_t s);
 void launch_dual(const Params& p, hipStream_t s);
 void launch_decide(const Params& p, hipStream_t s);
 void launch_eval(const Params& p, hipStream_t s);
-void launch_init(const Params& p, const double* xs, const double* ys, const int8_t* le, hipStream_t s);
-void launch_output(const Params& p, double* xo, double* yo, double* rco, const int8_t* le, hipStream_t s);
+void launch_init(const Params& p, const double* xs, const double* ys, hipStream_t s);
+void launch_output(const Params& p, hipStream_t s);
+void launch_probe(const Params& p, int which, hipStream_t s);
 void launch_set_limit(DevState* st, int status, hipStream_t s);
+void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s);
+int batch_occupancy();
+void launch_seg_sumsq(int nlp, const int32_t* off, const double* a, double* out, int stride, int slot, hipStream_t s);
+void launch_seg_absmax(int nlp, const int32_t* row_off, const int32_t* rp, const double* v, double* out,
+                       hipStream_t s);
 hipError_t setup_normalize(int m, const int32_t* rp, double* v, const double* b, const int8_t* rt, double* q,
                            int8_t* ineq, int8_t* le, int32_t* rowid, hipStream_t s);
 hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
@@ -41,6 +47,8 @@ hipError_t setup_sumsq(int64_t n, const double* a, double* part, double* out, hi
 hipError_t setup_absmax(int64_t nnz, const double* v, unsigned long long* out, hipStream_t s);
 hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s);
 hipError_t setup_fill(int64_t n, double* a, double val, hipStream_t s);
+hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
+                         int32_t* pci, double* pv, float* pvf, hipStream_t s);
 }  // namespace pdlp
 
 using namespace pdlp;
@@ -62,14 +70,15 @@ inline void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipFail{e, what};
 }
 
-// Row-block partition of a CSR matrix (see RowBlock): every row longer than
-// kTile becomes a block of its own, listed first so that these heavier blocks
-// are dispatched before the short ones; the runs of short rows between them
-// are cut greedily at kTile nonzeros or kMaxRows rows.
-std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
+// Row-block partition of a CSR-like structure (see RowBlock) over rows
+// [begin, end): every row longer than kTile becomes a block of its own, listed
+// first so that these heavier blocks are dispatched before the short ones; the
+// runs of short rows between them are cut greedily at kTile nonzeros or
+// kMaxRows rows.
+std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end) {
   std::vector<RowBlock> longs, shorts;
-  int r = 0;
-  while (r < nrows) {
+  int r = begin;
+  while (r < end) {
     if (rp[r + 1] - rp[r] > kTile) {
       longs.push_back(RowBlock{r, r + 1});
       ++r;
@@ -77,7 +86,7 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
     }
     const int r0 = r;
     int nz = 0;
-    while (r < nrows && r - r0 < kMaxRows) {
+    while (r < end && r - r0 < kMaxRows) {
       const int len = rp[r + 1] - rp[r];
       if (len > kTile || nz + len > kTile) break;
       nz += len;
@@ -86,8 +95,86 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
     shorts.push_back(RowBlock{r0, r});
   }
   longs.insert(longs.end(), shorts.begin(), shorts.end());
-  if (longs.empty()) longs.push_back(RowBlock{0, 0});
   return longs;
+}
+
+std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
+  std::vector<RowBlock> b = partition_rows(rp, 0, nrows);
+  if (b.empty()) b.push_back(RowBlock{0, 0});
+  return b;
+}
+
+// Column-panel layout (see PanelCsr), built on the host from the structure.
+struct HostPanels {
+  std::vector<int32_t> seg_ptr, seg_dst, row_seg, perm;
+  std::vector<RowBlock> sblocks;
+};
+
+HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int ncols, const int32_t* col_ptr) {
+  HostPanels H;
+  const int64_t nnz = rp[nrows];
+  // panel boundaries: about nnz / kPanels nonzeros each (col_ptr = row pointer of the transpose)
+  std::vector<int32_t> cb(kPanels + 1, ncols);
+  cb[0] = 0;
+  for (int p = 1, j = 0; p < kPanels; ++p) {
+    const int64_t target = nnz * p / kPanels;
+    while (j < ncols && col_ptr[j] < target) ++j;
+    cb[p] = j;
+  }
+  std::vector<uint8_t> colpan((size_t)ncols);
+  for (int p = 0; p < kPanels; ++p)
+    for (int j = cb[p]; j < cb[p + 1]; ++j) colpan[(size_t)j] = (uint8_t)p;
+  std::vector<uint8_t> mask((size_t)nrows, 0);
+  std::vector<int64_t> pnnz(kPanels, 0), pseg(kPanels, 0);
+  for (int r = 0; r < nrows; ++r) {
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      const int p = colpan[(size_t)ci[e]];
+      mask[(size_t)r] |= (uint8_t)(1u << p);
+      pnnz[p]++;
+    }
+    for (int p = 0; p < kPanels; ++p) pseg[p] += (mask[(size_t)r] >> p) & 1;
+  }
+  H.row_seg.assign((size_t)nrows + 1, 0);
+  for (int r = 0; r < nrows; ++r) H.row_seg[(size_t)r + 1] = H.row_seg[(size_t)r] + __builtin_popcount(mask[(size_t)r]);
+  const int nseg = H.row_seg[(size_t)nrows];
+  std::vector<int64_t> ent(kPanels), seg(kPanels);
+  int64_t eo = 0, so = 0;
+  for (int p = 0; p < kPanels; ++p) {
+    ent[p] = eo;
+    seg[p] = so;
+    eo += pnnz[p];
+    so += pseg[p];
+  }
+  std::vector<int64_t> seg_base(seg);
+  H.seg_ptr.assign((size_t)nseg + 1, 0);
+  H.seg_dst.assign((size_t)nseg, 0);
+  H.perm.assign((size_t)nnz, 0);
+  std::vector<int32_t> last(kPanels, -1);
+  for (int r = 0; r < nrows; ++r) {
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      const int p = colpan[(size_t)ci[e]];
+      if (last[p] != r) {
+        const int64_t sp = seg[p]++;
+        H.seg_ptr[(size_t)sp] = (int32_t)ent[p];
+        H.seg_dst[(size_t)sp] = H.row_seg[(size_t)r] + __builtin_popcount(mask[(size_t)r] & ((1u << p) - 1u));
+        last[p] = r;
+      }
+      H.perm[(size_t)ent[p]++] = e;
+    }
+  }
+  H.seg_ptr[(size_t)nseg] = (int32_t)nnz;
+  // phase-1 blocks of each panel, interleaved so that block i serves panel i % kPanels
+  std::vector<std::vector<RowBlock>> pb(kPanels);
+  size_t nbmax = 0;
+  for (int p = 0; p < kPanels; ++p) {
+    pb[p] = partition_rows(H.seg_ptr.data(), (int)seg_base[p], (int)(seg_base[p] + pseg[p]));
+    nbmax = std::max(nbmax, pb[p].size());
+  }
+  if (nbmax == 0) nbmax = 1;
+  H.sblocks.assign(nbmax * kPanels, RowBlock{0, 0});
+  for (int p = 0; p < kPanels; ++p)
+    for (size_t j = 0; j < pb[p].size(); ++j) H.sblocks[j * kPanels + p] = pb[p][j];
+  return H;
 }
 
 }  // namespace
@@ -119,10 +206,29 @@ struct pdlp_handle {
   hipGraphExec_t gexec = nullptr;
   int slots_per_round = 0, rounds = 0;
   double eta0 = 1.0, omega0 = 1.0;
+  double probe_ms[2] = {0.0, 0.0};
   std::string err = "no error";
   bool solved = false;
   pdlp_info info{};
   double setup_s = 0.0;
+  // batch handles (count > 0): LP b owns rows [row_off[b], row_off[b+1]) and
+  // columns [col_off[b], col_off[b+1]) of the packed block-diagonal problem
+  int32_t count = 0;
+  std::vector<int32_t> row_off_h, col_off_h;
+  std::vector<int64_t> nnz_h;
+  std::vector<uint8_t> lanes_h;
+  std::vector<int8_t> warm_h;
+  std::vector<double> omega_warm_h;
+  std::vector<DevState> bst_h;
+  int32_t grid = 0;
+  int32_t *row_off = nullptr, *col_off = nullptr, *order = nullptr;
+  uint8_t* lanes = nullptr;
+  int8_t* warm = nullptr;
+  double *norms = nullptr, *kmax = nullptr, *omega_warm = nullptr;
+  DevState* bst = nullptr;
+  uint32_t* queue = nullptr;
+  uint64_t* t0 = nullptr;
+  double tick_hz = 0.0;
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -181,6 +287,9 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->trace = 0;
   o->poll_every = 4;
   o->graph = 1;
+  o->spmv_layout = -1;
+  o->batch_lanes = 0;
+  o->batch_grid = 0;
   return PDLP_OK;
 }
 
@@ -199,6 +308,10 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.trace < 0) return why = "trace must be >= 0", -1;
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
+  if (o.spmv_layout < -1 || o.spmv_layout > 2) return why = "spmv_layout must be -1, 0, 1 or 2", -1;
+  if (o.batch_lanes < 0 || o.batch_lanes > 64 || (o.batch_lanes & (o.batch_lanes - 1)))
+    return why = "batch_lanes must be 0 or a power of two up to 64", -1;
+  if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
   return 0;
 }
 
@@ -279,6 +392,273 @@ static void build_graph(pdlp_handle* h) {
   check(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
+static int elem_grid(int n) {
+  int g = (n + kBlock - 1) / kBlock;
+  if (g > kElemBlocks) g = kElemBlocks;
+  return g < 1 ? 1 : g;
+}
+
+// Device copy of a column-panel layout; the matrix keeps layout 0 until chosen.
+static void upload_panels(pdlp_handle* h, DevCsr& M, const HostPanels& H, int64_t nnz, const int32_t* ci,
+                          const double* v, const float* vf) {
+  hipStream_t s = h->stream;
+  const hipMemcpyKind kind = hipMemcpyHostToDevice;
+  PanelCsr& S = M.pan;
+  S.nseg = (int32_t)H.seg_dst.size();
+  S.nsblocks = (int32_t)H.sblocks.size();
+  int32_t* seg_ptr = h->dalloc<int32_t>(H.seg_ptr.size());
+  int32_t* seg_dst = h->dalloc<int32_t>(H.seg_dst.size());
+  int32_t* row_seg = h->dalloc<int32_t>(H.row_seg.size());
+  RowBlock* sb = h->dalloc<RowBlock>(H.sblocks.size());
+  int32_t* perm = h->dalloc<int32_t>((size_t)nnz);
+  int32_t* pci = h->dalloc<int32_t>((size_t)nnz);
+  double* pv = h->dalloc<double>((size_t)nnz);
+  float* pvf = vf ? h->dalloc<float>((size_t)nnz) : nullptr;
+  check(hipMemcpyAsync(seg_ptr, H.seg_ptr.data(), H.seg_ptr.size() * 4, kind, s), "upload panels");
+  if (!H.seg_dst.empty()) check(hipMemcpyAsync(seg_dst, H.seg_dst.data(), H.seg_dst.size() * 4, kind, s), "upload panels");
+  check(hipMemcpyAsync(row_seg, H.row_seg.data(), H.row_seg.size() * 4, kind, s), "upload panels");
+  check(hipMemcpyAsync(sb, H.sblocks.data(), H.sblocks.size() * sizeof(RowBlock), kind, s), "upload panels");
+  if (nnz) check(hipMemcpyAsync(perm, H.perm.data(), (size_t)nnz * 4, kind, s), "upload panels");
+  check(setup_permute(nnz, perm, ci, v, vf, pci, pv, pvf, s), "permute panels");
+  check(hipStreamSynchronize(s), "panels sync");
+  S.seg_ptr = seg_ptr;
+  S.seg_dst = seg_dst;
+  S.row_seg = row_seg;
+  S.pci = pci;
+  S.pv = pv;
+  S.pvf = pvf;
+  S.sblocks = sb;
+  S.part = h->dalloc<double>(2 * (size_t)std::max(S.nseg, 1));
+}
+
+// Mean duration (ms) of a plain product pass over K (which = 0) or K' (1).
+static double time_probe(pdlp_handle* h, int which, int reps) {
+  hipStream_t s = h->stream;
+  hipEvent_t a, b;
+  check(hipEventCreate(&a), "hipEventCreate");
+  check(hipEventCreate(&b), "hipEventCreate");
+  launch_probe(h->P, which, s);
+  check(hipEventRecord(a, s), "event");
+  for (int i = 0; i < reps; ++i) launch_probe(h->P, which, s);
+  check(hipEventRecord(b, s), "event");
+  check(hipEventSynchronize(b), "event sync");
+  float ms = 0.f;
+  check(hipEventElapsedTime(&ms, a, b), "elapsed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+// Layout of each matrix: the option's, or (spmv_layout = -1) the fastest of
+// row blocks, row blocks with XCD-contiguous ranges, and column panels (when
+// built), timed on plain products.  An alternative replaces row blocks only
+// when it is faster by more than 5 %, so close calls stay on the default.
+static void choose_layouts(pdlp_handle* h) {
+  Params& P = h->P;
+  const int mode = h->opt.spmv_layout;
+  double* pin = h->dalloc<double>((size_t)std::max(h->m, h->n));
+  double* pout = h->dalloc<double>((size_t)std::max(h->m, h->n));
+  check(setup_fill(std::max(h->m, h->n), pin, 1.0, h->stream), "probe fill");
+  P.probe_in = pin;
+  P.probe_out = pout;
+  for (int which = 0; which < 2; ++which) {
+    DevCsr& M = which ? P.KT : P.K;
+    const bool has_pan = M.pan.seg_ptr != nullptr;
+    auto set = [&](int layout, int remap) {
+      M.layout = layout;
+      M.remap = remap;
+      M.nred = layout == 1 ? M.rows_grid : M.nblocks;
+    };
+    if (mode == 0) { set(0, 0); continue; }
+    if (mode == 2) { set(0, 1); continue; }
+    if (mode == 1) { set(has_pan ? 1 : 0, 0); continue; }
+    set(0, 0);
+    if (h->nnz < (1 << 20)) continue;   // small problems: row blocks
+    const double t0 = time_probe(h, which, 5);
+    int best_l = 0, best_r = 0;
+    double best = t0;
+    set(0, 1);
+    const double t1 = time_probe(h, which, 5);
+    if (t1 < 0.95 * best) { best = t1; best_l = 0; best_r = 1; }
+    if (has_pan) {
+      set(1, 0);
+      const double t2 = time_probe(h, which, 5);
+      if (t2 < 0.95 * best) { best = t2; best_l = 1; best_r = 0; }
+    }
+    set(best_l, best_r);
+    h->probe_ms[which] = best;
+  }
+}
+
+// One LP fetched to the host (from host or device arrays) and validated.
+struct HostLP {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v, c, b, l, u;
+  std::vector<int8_t> rt;
+};
+
+static int load_problem(const pdlp_problem* p, void* hip_stream, HostLP& H, std::string& why) {
+  if (p->m < 0 || p->n < 1 || p->nnz < 0 || p->nnz >= (int64_t)1 << 31)
+    return why = "sizes must satisfy m >= 0, n >= 1, 0 <= nnz < 2^31", PDLP_ERR_ARG;
+  if (p->mem != PDLP_MEM_HOST && p->mem != PDLP_MEM_DEVICE) return why = "bad mem kind", PDLP_ERR_ARG;
+  if (!p->row_ptr || !p->c || !p->l || !p->u || (p->nnz > 0 && (!p->col_idx || !p->val)) ||
+      (p->m > 0 && (!p->b || !p->row_type)))
+    return why = "NULL problem array", PDLP_ERR_ARG;
+  H.m = p->m;
+  H.n = p->n;
+  H.nnz = p->nnz;
+  try {
+    if (p->mem == PDLP_MEM_DEVICE) {
+      int ndev = 0;
+      check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+      // the caller's producers of the device arrays run on its stream
+      check(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+    }
+    fetch(H.rp, p->row_ptr, (size_t)H.m + 1, p->mem);
+    fetch(H.ci, p->col_idx, (size_t)H.nnz, p->mem);
+    fetch(H.v, p->val, (size_t)H.nnz, p->mem);
+    fetch(H.c, p->c, (size_t)H.n, p->mem);
+    fetch(H.b, p->b, (size_t)H.m, p->mem);
+    fetch(H.l, p->l, (size_t)H.n, p->mem);
+    fetch(H.u, p->u, (size_t)H.n, p->mem);
+    fetch(H.rt, p->row_type, (size_t)H.m, p->mem);
+  } catch (const HipFail& f) {
+    return why = hip_msg(f), PDLP_ERR_HIP;
+  }
+  if (validate(H.m, H.n, H.nnz, H.rp.data(), H.ci.data(), H.v.data(), H.c.data(), H.b.data(), H.l.data(),
+               H.u.data(), H.rt.data(), why))
+    return PDLP_ERR_DATA;
+  return PDLP_OK;
+}
+
+// a1-a2: upload the LP, negate LE rows into the >= form, transpose on the device.
+static void upload_normalize_transpose(pdlp_handle* h, const HostLP& H) {
+  const int32_t m = H.m, n = H.n;
+  const int64_t nnz = H.nnz;
+  hipStream_t s = h->stream;
+  h->rp = h->dalloc<int32_t>((size_t)m + 1);
+  h->ci = h->dalloc<int32_t>((size_t)nnz);
+  h->val = h->dalloc<double>((size_t)nnz);
+  h->c0 = h->dalloc<double>(n);
+  h->l0 = h->dalloc<double>(n);
+  h->u0 = h->dalloc<double>(n);
+  h->b0 = h->dalloc<double>(m);
+  h->rt = h->dalloc<int8_t>(m);
+  const hipMemcpyKind kind = hipMemcpyHostToDevice;
+  check(hipMemcpyAsync(h->rp, H.rp.data(), ((size_t)m + 1) * 4, kind, s), "upload row_ptr");
+  if (nnz) check(hipMemcpyAsync(h->ci, H.ci.data(), (size_t)nnz * 4, kind, s), "upload col_idx");
+  if (nnz) check(hipMemcpyAsync(h->val, H.v.data(), (size_t)nnz * 8, kind, s), "upload val");
+  check(hipMemcpyAsync(h->c0, H.c.data(), (size_t)n * 8, kind, s), "upload c");
+  check(hipMemcpyAsync(h->l0, H.l.data(), (size_t)n * 8, kind, s), "upload l");
+  check(hipMemcpyAsync(h->u0, H.u.data(), (size_t)n * 8, kind, s), "upload u");
+  if (m) check(hipMemcpyAsync(h->b0, H.b.data(), (size_t)m * 8, kind, s), "upload b");
+  if (m) check(hipMemcpyAsync(h->rt, H.rt.data(), (size_t)m, kind, s), "upload row_type");
+  h->q = h->dalloc<double>(m);
+  h->ineq = h->dalloc<int8_t>(m);
+  h->le = h->dalloc<int8_t>(m);
+  h->rowid = h->dalloc<int32_t>((size_t)nnz);
+  check(setup_normalize(m, h->rp, h->val, h->b0, h->rt, h->q, h->ineq, h->le, h->rowid, s), "normalize");
+  h->rpT = h->dalloc<int32_t>((size_t)n + 1);
+  h->ciT = h->dalloc<int32_t>((size_t)nnz);
+  h->valT = h->dalloc<double>((size_t)nnz);
+  h->rowidT = h->dalloc<int32_t>((size_t)nnz);
+  h->perm = h->dalloc<int32_t>((size_t)nnz);
+  check(setup_transpose(m, n, nnz, h->ci, h->val, h->rowid, h->rpT, h->ciT, h->valT, h->rowidT, h->perm, s),
+        "transpose");
+}
+
+// a3: Ruiz and Pock-Chambolle preconditioning (Section 2.2), then the scaled
+// vectors c~, l~, u~, q~ and (FP32 steps) the rounded matrix copies.
+static void scale_problem(pdlp_handle* h) {
+  const int32_t m = h->m, n = h->n;
+  const int64_t nnz = h->nnz;
+  hipStream_t s = h->stream;
+  h->D1 = h->dalloc<double>(m);
+  h->D2 = h->dalloc<double>(n);
+  double* d1 = h->dalloc<double>(m);
+  double* d2 = h->dalloc<double>(n);
+  check(setup_fill(m, h->D1, 1.0, s), "fill D1");
+  check(setup_fill(n, h->D2, 1.0, s), "fill D2");
+  check(setup_scale(m, n, nnz, h->rp, h->ci, h->rowid, h->val, h->rpT, h->ciT, h->rowidT, h->valT,
+                    h->opt.ruiz_iters, h->opt.pc_alpha, h->D1, h->D2, d1, d2, s),
+        "scale");
+  h->c = h->dalloc<double>(n);
+  h->l = h->dalloc<double>(n);
+  h->u = h->dalloc<double>(n);
+  check(setup_vectors(m, n, h->D1, h->D2, h->c0, h->l0, h->u0, h->c, h->l, h->u, h->q, s), "scale vectors");
+  if (h->opt.a_precision == PDLP_A_FP32) {
+    h->valf = h->dalloc<float>((size_t)nnz);
+    h->valTf = h->dalloc<float>((size_t)nnz);
+    check(setup_to_f32(nnz, h->val, h->valf, s), "fp32 K");
+    check(setup_to_f32(nnz, h->valT, h->valTf, s), "fp32 K'");
+  }
+}
+
+// Iterate, average and output buffers and the constants of Params.
+static void alloc_iterates(pdlp_handle* h) {
+  const int32_t m = h->m, n = h->n;
+  const pdlp_options& opt = h->opt;
+  Params& P = h->P;
+  P.m = m;
+  P.n = n;
+  P.use_f32 = opt.a_precision == PDLP_A_FP32;
+  for (int k = 0; k < 2; ++k) {
+    P.x[k] = h->dalloc<double>(n);
+    P.y[k] = h->dalloc<double>(m);
+    P.kx[k] = h->dalloc<double>(m);
+  }
+  P.dx = h->dalloc<double>(n);
+  P.xsum = h->dalloc<double>(n);
+  P.ysum = h->dalloc<double>(m);
+  P.xbar = h->dalloc<double>(n);
+  P.ybar = h->dalloc<double>(m);
+  P.x0 = h->dalloc<double>(n);
+  P.y0 = h->dalloc<double>(m);
+  P.c = h->c;
+  P.q = h->q;
+  P.l = h->l;
+  P.u = h->u;
+  P.ineq = h->ineq;
+  P.le = h->le;
+  P.D1 = h->D1;
+  P.D2 = h->D2;
+  if (opt.trace > 0) {
+    const size_t cap = (size_t)opt.trace;
+    P.tr = Trace{(int64_t)cap,
+                 h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
+                 h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
+                 h->dalloc<int8_t>(cap), h->dalloc<double>(cap)};
+  } else {
+    P.tr = Trace{};
+  }
+  P.P = opt.eval_period;
+  P.beta_suff = opt.beta_suff;
+  P.beta_nec = opt.beta_nec;
+  P.beta_art = opt.beta_art;
+  P.theta = opt.pw_theta;
+  P.eps_zero = opt.eps_zero;
+  P.tie_rel = 1e-12;
+  P.omega_power = opt.kkt_omega_power;
+  h->xo = h->dalloc<double>(n);
+  h->yo = h->dalloc<double>(m);
+  h->rco = h->dalloc<double>(n);
+  P.xo = h->xo;
+  P.yo = h->yo;
+  P.rco = h->rco;
+  h->wx = h->dalloc<double>(n);
+  h->wy = h->dalloc<double>(m);
+}
+
+static int create_failed(pdlp_handle* h, const HipFail& f) {
+  std::string msg = hip_msg(f);
+  const int code = (f.e == hipErrorOutOfMemory || f.e == hipErrorMemoryAllocation) ? PDLP_ERR_OOM : PDLP_ERR_HIP;
+  h->release();
+  delete h;
+  return fail(nullptr, code, msg);
+}
+
 extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* hip_stream, pdlp_handle** out) {
   if (out) *out = nullptr;
   if (!p || !out) return fail(nullptr, PDLP_ERR_ARG, "NULL problem or output pointer");
@@ -287,40 +667,11 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   else pdlp_default_options(&opt);
   std::string why;
   if (check_options(opt, why)) return fail(nullptr, PDLP_ERR_ARG, why);
-  if (p->m < 0 || p->n < 1 || p->nnz < 0 || p->nnz >= (int64_t)1 << 31)
-    return fail(nullptr, PDLP_ERR_ARG, "sizes must satisfy m >= 0, n >= 1, 0 <= nnz < 2^31");
-  if (p->mem != PDLP_MEM_HOST && p->mem != PDLP_MEM_DEVICE) return fail(nullptr, PDLP_ERR_ARG, "bad mem kind");
-  if (!p->row_ptr || !p->c || !p->l || !p->u || (p->nnz > 0 && (!p->col_idx || !p->val)) ||
-      (p->m > 0 && (!p->b || !p->row_type)))
-    return fail(nullptr, PDLP_ERR_ARG, "NULL problem array");
-  const int32_t m = p->m, n = p->n;
-  const int64_t nnz = p->nnz;
   const double t0 = now_s();
-  // host copies for validation and the row-block partition
-  std::vector<int32_t> hrp, hci;
-  std::vector<double> hv, hc, hb, hl, hu;
-  std::vector<int8_t> hrt;
-  try {
-    if (p->mem == PDLP_MEM_DEVICE) {
-      int ndev = 0;
-      check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
-      // the caller's producers of the device arrays run on its stream
-      check(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
-    }
-    fetch(hrp, p->row_ptr, (size_t)m + 1, p->mem);
-    fetch(hci, p->col_idx, (size_t)nnz, p->mem);
-    fetch(hv, p->val, (size_t)nnz, p->mem);
-    fetch(hc, p->c, (size_t)n, p->mem);
-    fetch(hb, p->b, (size_t)m, p->mem);
-    fetch(hl, p->l, (size_t)n, p->mem);
-    fetch(hu, p->u, (size_t)n, p->mem);
-    fetch(hrt, p->row_type, (size_t)m, p->mem);
-  } catch (const HipFail& f) {
-    return fail(nullptr, PDLP_ERR_HIP, hip_msg(f));
-  }
-  if (validate(m, n, nnz, hrp.data(), hci.data(), hv.data(), hc.data(), hb.data(), hl.data(), hu.data(), hrt.data(),
-               why))
-    return fail(nullptr, PDLP_ERR_DATA, why);
+  HostLP H;
+  if (int rc = load_problem(p, hip_stream, H, why)) return fail(nullptr, rc, why);
+  const int32_t m = H.m, n = H.n;
+  const int64_t nnz = H.nnz;
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, PDLP_ERR_HIP, "no HIP device");
@@ -334,55 +685,14 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   try {
     check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hipStream_t s = h->stream;
-    // --- upload (a1)
-    h->rp = h->dalloc<int32_t>((size_t)m + 1);
-    h->ci = h->dalloc<int32_t>((size_t)nnz);
-    h->val = h->dalloc<double>((size_t)nnz);
-    h->c0 = h->dalloc<double>(n);
-    h->l0 = h->dalloc<double>(n);
-    h->u0 = h->dalloc<double>(n);
-    h->b0 = h->dalloc<double>(m);
-    h->rt = h->dalloc<int8_t>(m);
     const hipMemcpyKind kind = hipMemcpyHostToDevice;
-    check(hipMemcpyAsync(h->rp, hrp.data(), ((size_t)m + 1) * 4, kind, s), "upload row_ptr");
-    if (nnz) check(hipMemcpyAsync(h->ci, hci.data(), (size_t)nnz * 4, kind, s), "upload col_idx");
-    if (nnz) check(hipMemcpyAsync(h->val, hv.data(), (size_t)nnz * 8, kind, s), "upload val");
-    check(hipMemcpyAsync(h->c0, hc.data(), (size_t)n * 8, kind, s), "upload c");
-    check(hipMemcpyAsync(h->l0, hl.data(), (size_t)n * 8, kind, s), "upload l");
-    check(hipMemcpyAsync(h->u0, hu.data(), (size_t)n * 8, kind, s), "upload u");
-    if (m) check(hipMemcpyAsync(h->b0, hb.data(), (size_t)m * 8, kind, s), "upload b");
-    if (m) check(hipMemcpyAsync(h->rt, hrt.data(), (size_t)m, kind, s), "upload row_type");
-    // --- >= form, transpose (a2)
-    h->q = h->dalloc<double>(m);
-    h->ineq = h->dalloc<int8_t>(m);
-    h->le = h->dalloc<int8_t>(m);
-    h->rowid = h->dalloc<int32_t>((size_t)nnz);
-    check(setup_normalize(m, h->rp, h->val, h->b0, h->rt, h->q, h->ineq, h->le, h->rowid, s), "normalize");
-    h->rpT = h->dalloc<int32_t>((size_t)n + 1);
-    h->ciT = h->dalloc<int32_t>((size_t)nnz);
-    h->valT = h->dalloc<double>((size_t)nnz);
-    h->rowidT = h->dalloc<int32_t>((size_t)nnz);
-    h->perm = h->dalloc<int32_t>((size_t)nnz);
-    check(setup_transpose(m, n, nnz, h->ci, h->val, h->rowid, h->rpT, h->ciT, h->valT, h->rowidT, h->perm, s),
-          "transpose");
-    // --- unscaled norms, then preconditioning (a3)
+    upload_normalize_transpose(h, H);
+    // unscaled norms of the Section 4.1 tests
     double* red = h->dalloc<double>(8);
     double* part = h->dalloc<double>((size_t)std::max<int64_t>(n, m) / 4096 + 2);
     check(setup_sumsq(n, h->c0, part, red + 0, s), "norm c");
     check(setup_sumsq(m, h->q, part, red + 1, s), "norm q");
-    h->D1 = h->dalloc<double>(m);
-    h->D2 = h->dalloc<double>(n);
-    double* d1 = h->dalloc<double>(m);
-    double* d2 = h->dalloc<double>(n);
-    check(setup_fill(m, h->D1, 1.0, s), "fill D1");
-    check(setup_fill(n, h->D2, 1.0, s), "fill D2");
-    check(setup_scale(m, n, nnz, h->rp, h->ci, h->rowid, h->val, h->rpT, h->ciT, h->rowidT, h->valT, opt.ruiz_iters,
-                      opt.pc_alpha, h->D1, h->D2, d1, d2, s),
-          "scale");
-    h->c = h->dalloc<double>(n);
-    h->l = h->dalloc<double>(n);
-    h->u = h->dalloc<double>(n);
-    check(setup_vectors(m, n, h->D1, h->D2, h->c0, h->l0, h->u0, h->c, h->l, h->u, h->q, s), "scale vectors");
+    scale_problem(h);
     // --- a4: omega0 = ||c~|| / ||q~||, eta0 = 1 / max |K~|
     check(setup_sumsq(n, h->c, part, red + 2, s), "norm c~");
     check(setup_sumsq(m, h->q, part, red + 3, s), "norm q~");
@@ -395,78 +705,47 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     double kmax;
     std::memcpy(&kmax, &hred[4], sizeof kmax);
     h->eta0 = kmax > 0.0 ? 1.0 / kmax : 1.0;
-    if (opt.a_precision == PDLP_A_FP32) {
-      h->valf = h->dalloc<float>((size_t)nnz);
-      h->valTf = h->dalloc<float>((size_t)nnz);
-      check(setup_to_f32(nnz, h->val, h->valf, s), "fp32 K");
-      check(setup_to_f32(nnz, h->valT, h->valTf, s), "fp32 K'");
-    }
-    // --- row-block partitions
+    // --- row-block partitions and (optionally) the column-panel layouts
     std::vector<int32_t> hrpT((size_t)n + 1);
     check(hipMemcpy(hrpT.data(), h->rpT, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
-    std::vector<RowBlock> bk = partition_rows(hrp.data(), m);
+    std::vector<RowBlock> bk = partition_rows(H.rp.data(), m);
     std::vector<RowBlock> bt = partition_rows(hrpT.data(), n);
     RowBlock* dbk = h->dalloc<RowBlock>(bk.size());
     RowBlock* dbt = h->dalloc<RowBlock>(bt.size());
     check(hipMemcpyAsync(dbk, bk.data(), bk.size() * sizeof(RowBlock), kind, s), "upload blocks");
     check(hipMemcpyAsync(dbt, bt.data(), bt.size() * sizeof(RowBlock), kind, s), "upload blocks");
     Params& P = h->P;
-    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m};
-    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n};
-    P.m = m;
-    P.n = n;
-    P.use_f32 = opt.a_precision == PDLP_A_FP32;
-    P.xcd_remap = 0;
-    for (int k = 0; k < 2; ++k) {
-      P.x[k] = h->dalloc<double>(n);
-      P.y[k] = h->dalloc<double>(m);
-      P.kx[k] = h->dalloc<double>(m);
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m, 0, 0, 0, elem_grid(m), PanelCsr{}};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n, 0, 0, 0, elem_grid(n),
+                  PanelCsr{}};
+    // a panel layout pays when the gathered vector does not fit one XCD's L2;
+    // spmv_layout = 1 builds it for any size (tests)
+    const bool want_panels = opt.spmv_layout == 1 || (opt.spmv_layout < 0 && nnz >= (1 << 20));
+    if (want_panels) {
+      std::vector<int32_t> hciT;
+      if (n >= (1 << 18) || opt.spmv_layout == 1) {
+        HostPanels HP = build_panels(H.rp.data(), H.ci.data(), m, n, hrpT.data());
+        upload_panels(h, P.K, HP, nnz, h->ci, h->val, h->valf);
+      }
+      if (m >= (1 << 18) || opt.spmv_layout == 1) {
+        hciT.resize((size_t)std::max<int64_t>(nnz, 1));
+        if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
+        HostPanels HP = build_panels(hrpT.data(), hciT.data(), n, m, H.rp.data());
+        upload_panels(h, P.KT, HP, nnz, h->ciT, h->valT, h->valTf);
+      }
     }
-    P.dx = h->dalloc<double>(n);
-    P.xsum = h->dalloc<double>(n);
-    P.ysum = h->dalloc<double>(m);
-    P.xbar = h->dalloc<double>(n);
-    P.ybar = h->dalloc<double>(m);
-    P.x0 = h->dalloc<double>(n);
-    P.y0 = h->dalloc<double>(m);
-    P.c = h->c;
-    P.q = h->q;
-    P.l = h->l;
-    P.u = h->u;
-    P.ineq = h->ineq;
-    P.D1 = h->D1;
-    P.D2 = h->D2;
-    P.partA = h->dalloc<double>(bt.size());
-    P.partB = h->dalloc<double>(2 * bk.size());
+    alloc_iterates(h);
+    const size_t redk = std::max<size_t>(bk.size(), (size_t)P.K.rows_grid);
+    const size_t redt = std::max<size_t>(bt.size(), (size_t)P.KT.rows_grid);
+    P.partA = h->dalloc<double>(redt);
+    P.partB = h->dalloc<double>(2 * redk);
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
-    P.partE1 = h->dalloc<double>(8 * bk.size());
-    P.partE2 = h->dalloc<double>(6 * bt.size());
+    P.partE1 = h->dalloc<double>(8 * redk);
+    P.partE2 = h->dalloc<double>(6 * redt);
     h->st = h->dalloc<DevState>(1);
     P.st = h->st;
-    if (opt.trace > 0) {
-      const size_t cap = (size_t)opt.trace;
-      P.tr = Trace{(int64_t)cap,
-                   h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
-                   h->dalloc<int64_t>(cap), h->dalloc<double>(cap), h->dalloc<double>(cap), h->dalloc<int8_t>(cap),
-                   h->dalloc<int8_t>(cap), h->dalloc<double>(cap)};
-    } else {
-      P.tr = Trace{};
-    }
-    P.P = opt.eval_period;
-    P.beta_suff = opt.beta_suff;
-    P.beta_nec = opt.beta_nec;
-    P.beta_art = opt.beta_art;
-    P.theta = opt.pw_theta;
-    P.eps_zero = opt.eps_zero;
-    P.tie_rel = 1e-12;
-    P.omega_power = opt.kkt_omega_power;
     P.cnorm0 = std::sqrt(hred[0]);
     P.qnorm0 = std::sqrt(hred[1]);
-    h->xo = h->dalloc<double>(n);
-    h->yo = h->dalloc<double>(m);
-    h->rco = h->dalloc<double>(n);
-    h->wx = h->dalloc<double>(n);
-    h->wy = h->dalloc<double>(m);
     for (int k = 0; k < 2; ++k) {
       void* hp = nullptr;
       check(hipHostMalloc(&hp, sizeof(DevState), hipHostMallocDefault), "hipHostMalloc");
@@ -476,12 +755,9 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     }
     check(hipStreamSynchronize(s), "setup sync");
     check(hipGetLastError(), "setup kernels");
+    choose_layouts(h);
   } catch (const HipFail& f) {
-    std::string msg = hip_msg(f);
-    const int code = (f.e == hipErrorOutOfMemory || f.e == hipErrorMemoryAllocation) ? PDLP_ERR_OOM : PDLP_ERR_HIP;
-    h->release();
-    delete h;
-    return fail(nullptr, code, msg);
+    return create_failed(h, f);
   }
   h->setup_s = now_s() - t0;
   *out = h;
@@ -490,6 +766,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
 
 extern "C" int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const double* y0, double omega0) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_set_warm_start on a batch handle (use the _batch entry points)");
   if (x0)
     for (int32_t j = 0; j < h->n; ++j)
       if (!std::isfinite(x0[j])) return fail(h, PDLP_ERR_DATA, "warm-start x0 is not finite");
@@ -523,7 +800,7 @@ static void start_solve(pdlp_handle* h) {
   s0->eps_rel = h->opt.eps_rel;
   s0->max_iter = h->opt.max_iter;
   check(hipMemcpyAsync(h->st, s0, sizeof(DevState), hipMemcpyHostToDevice, s), "upload state");
-  launch_init(h->P, h->has_warm ? h->wx : nullptr, h->has_warm ? h->wy : nullptr, h->le, s);
+  launch_init(h->P, h->has_warm ? h->wx : nullptr, h->has_warm ? h->wy : nullptr, s);
   launch_eval(h->P, s);
   check(hipGetLastError(), "launch start");
   check(hipStreamSynchronize(s), "start sync");
@@ -531,7 +808,7 @@ static void start_solve(pdlp_handle* h) {
 
 static void finish_solve(pdlp_handle* h, double t0) {
   hipStream_t s = h->stream;
-  launch_output(h->P, h->xo, h->yo, h->rco, h->le, s);
+  launch_output(h->P, s);
   DevState* f = h->st_host[0];
   check(hipMemcpyAsync(f, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s), "read state");
   check(hipStreamSynchronize(s), "finish sync");
@@ -553,6 +830,8 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.eta_hat = f->eta_hat;
   I.setup_s = h->setup_s;
   I.solve_s = now_s() - t0;
+  I.layout_k = h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0);
+  I.layout_kt = h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0);
 }
 
 extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
@@ -569,6 +848,7 @@ extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_
 
 extern "C" int pdlp_solve(pdlp_handle* h) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve on a batch handle (use the _batch entry points)");
   const double t0 = now_s();
   try {
     if (h->opt.graph && !h->gexec) build_graph(h);
@@ -638,6 +918,7 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
 
 extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* rc, pdlp_info* info) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution on a batch handle (use the _batch entry points)");
   if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution before pdlp_solve");
   try {
     if (x) check(hipMemcpy(x, h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
@@ -652,6 +933,7 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
 
 extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pdlp_iter_state* st) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_iterate on a batch handle (use the _batch entry points)");
   if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_iterate before pdlp_solve");
   try {
     DevState f;
@@ -696,7 +978,7 @@ extern "C" int pdlp_get_trace(pdlp_handle* h, int64_t cap, int64_t* n_att, int64
   if (h->opt.trace <= 0) return fail(h, PDLP_ERR_STATE, "the handle was created with trace = 0");
   try {
     DevState f;
-    check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
+    check(hipMemcpy(&f, h->count ? h->bst : h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
     const Trace& T = h->P.tr;
     const int64_t na = std::min<int64_t>(f.n_att, cap), ne = std::min<int64_t>(f.n_eval, cap);
     if (n_att) *n_att = na;
@@ -722,6 +1004,7 @@ extern "C" int pdlp_get_trace(pdlp_handle* h, int64_t cap, int64_t* n_att, int64
 
 extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* ms_primal, double* ms_dual) {
   if (!h || attempts < 1) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_profile_attempts on a batch handle (use the _batch entry points)");
   if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_profile_attempts before pdlp_solve");
   hipStream_t s = h->stream;
   const int S = h->slots_per_round > 0 ? h->slots_per_round : h->opt.eval_period + 2;
@@ -775,11 +1058,377 @@ extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* m
 
 extern "C" int pdlp_step_bytes(pdlp_handle* h, double* bytes_primal, double* bytes_dual) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_step_bytes on a batch handle (use the _batch entry points)");
   const double sv = h->opt.a_precision == PDLP_A_FP32 ? 4.0 : 8.0;
   const double nnz = (double)h->nnz, m = (double)h->m, n = (double)h->n;
   // matrix stream + row pointers + each gathered vector once + per-row vectors
   if (bytes_primal) *bytes_primal = nnz * (sv + 4.0) + 4.0 * (n + 1) + 8.0 * m + 64.0 * n;
   if (bytes_dual) *bytes_dual = nnz * (sv + 4.0) + 4.0 * (m + 1) + 8.0 * n + 57.0 * m;
+  return PDLP_OK;
+}
+
+// ---------------------------------------------------------------------------- batches of LPs
+
+namespace {
+
+// Bucket of a mean row length (ceil log2) and of an LP's row count; LPs of one
+// (length, size) class share a lanes-per-row choice.
+int length_class(double avg) {
+  int c = 0;
+  while (c < 12 && (double)(1 << c) < avg) ++c;
+  return c;
+}
+int size_class(int32_t rows) { return rows < 256 ? 0 : (rows < 1024 ? 1 : 2); }
+uint8_t default_lanes(double avg) {
+  int L = 1;
+  while (L < 64 && L < avg) L <<= 1;
+  return (uint8_t)L;
+}
+
+}  // namespace
+
+static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
+  hipStream_t s = h->stream;
+  BatchParams bp{};
+  bp.count = h->count;
+  bp.trace_lp = h->opt.trace > 0 ? 0 : -1;
+  bp.order = h->order;
+  bp.row_off = h->row_off;
+  bp.col_off = h->col_off;
+  bp.lanes = h->lanes;
+  bp.st = h->bst;
+  bp.norms = h->norms;
+  bp.kmax = h->kmax;
+  bp.omega_warm = h->omega_warm;
+  bp.warm = h->warm;
+  bp.wx = h->wx;
+  bp.wy = h->wy;
+  bp.queue = h->queue;
+  bp.t0 = h->t0;
+  const double ticks = time_limit_s * h->tick_hz;
+  bp.ticks = ticks >= 1.8e19 ? 0 : (uint64_t)std::max(1.0, ticks);
+  bp.max_reject = 1000;
+  bp.eps_rel = eps_rel;
+  bp.max_iter = max_iter;
+  bp.eps_zero = h->opt.eps_zero;
+  check(hipMemsetAsync(h->queue, 0, sizeof(uint32_t), s), "clear queue");
+  launch_batch(h->P, bp, h->grid, s);
+  check(hipGetLastError(), "batch launch");
+}
+
+// Wall time (ms) of a batch solve capped at `iters` accepted steps per LP.
+static double time_batch(pdlp_handle* h, int64_t iters, int reps) {
+  hipEvent_t a = nullptr, b = nullptr;
+  double best = 1e30;
+  try {
+    check(hipEventCreate(&a), "hipEventCreate");
+    check(hipEventCreate(&b), "hipEventCreate");
+    for (int r = 0; r < reps; ++r) {
+      check(hipEventRecord(a, h->stream), "event");
+      launch_batch_solve(h, 0.0, iters, 60.0);
+      check(hipEventRecord(b, h->stream), "event");
+      check(hipEventSynchronize(b), "sync");
+      float ms = 0.f;
+      check(hipEventElapsedTime(&ms, a, b), "elapsed");
+      best = std::min(best, (double)ms);
+    }
+  } catch (...) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+// Schedule of the persistent launch: lanes per row for the rows of K~ and of
+// K~' of every LP, chosen per (row-length, size) class by timing capped solves
+// of the whole batch (coordinate descent over the classes, lanes in 1..64),
+// then the number of workgroups.  Fixed values in the options skip the search.
+static void tune_batch(pdlp_handle* h) {
+  const int32_t cnt = h->count;
+  const pdlp_options& opt = h->opt;
+  std::vector<int> cls(2 * (size_t)cnt);
+  h->lanes_h.assign(2 * (size_t)cnt, 1);
+  for (int32_t b = 0; b < cnt; ++b) {
+    const int32_t mb = h->row_off_h[b + 1] - h->row_off_h[b], nb = h->col_off_h[b + 1] - h->col_off_h[b];
+    const double nz = (double)h->nnz_h[b];
+    const double ak = mb > 0 ? nz / mb : 0.0, at = nz / nb;
+    cls[2 * b] = 16 * length_class(ak) + size_class(mb);
+    cls[2 * b + 1] = 16 * length_class(at) + size_class(nb);
+    h->lanes_h[2 * b] = opt.batch_lanes ? (uint8_t)opt.batch_lanes : default_lanes(ak);
+    h->lanes_h[2 * b + 1] = opt.batch_lanes ? (uint8_t)opt.batch_lanes : default_lanes(at);
+  }
+  hipDeviceProp_t prop;
+  int dev = 0;
+  check(hipGetDevice(&dev), "hipGetDevice");
+  check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  const int cus = std::max(1, prop.multiProcessorCount);
+  const int full = cus * batch_occupancy();
+  h->grid = opt.batch_grid > 0 ? opt.batch_grid : std::min(cnt, full);
+  auto upload = [&]() {
+    check(hipMemcpy(h->lanes, h->lanes_h.data(), h->lanes_h.size(), hipMemcpyHostToDevice), "upload lanes");
+  };
+  upload();
+  if (opt.batch_lanes && opt.batch_grid) return;
+  const int64_t iters = 64;
+  (void)time_batch(h, iters, 1);  // first launch: code object load
+  double best = time_batch(h, iters, 2);
+  if (!opt.batch_lanes) {
+    for (int side = 0; side < 2; ++side) {
+      std::vector<int> classes;
+      for (int32_t b = 0; b < cnt; ++b) classes.push_back(cls[2 * b + side]);
+      std::sort(classes.begin(), classes.end());
+      classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+      for (int c : classes) {
+        uint8_t cur = 0;
+        for (int32_t b = 0; b < cnt; ++b)
+          if (cls[2 * b + side] == c) cur = h->lanes_h[2 * b + side];
+        const uint8_t start = cur;
+        for (int L = 1; L <= 64; L <<= 1) {
+          if (L == start) continue;
+          for (int32_t b = 0; b < cnt; ++b)
+            if (cls[2 * b + side] == c) h->lanes_h[2 * b + side] = (uint8_t)L;
+          upload();
+          const double t = time_batch(h, iters, 2);
+          if (t < 0.98 * best) {
+            best = t;
+            cur = (uint8_t)L;
+          }
+        }
+        for (int32_t b = 0; b < cnt; ++b)
+          if (cls[2 * b + side] == c) h->lanes_h[2 * b + side] = cur;
+        upload();
+      }
+    }
+  }
+  if (!opt.batch_grid) {
+    int bestg = h->grid;
+    for (int g = full / 2; g >= cus; g /= 2) {
+      if (g >= cnt) continue;
+      h->grid = g;
+      const double t = time_batch(h, iters, 2);
+      if (t < 0.98 * best) {
+        best = t;
+        bestg = g;
+      }
+    }
+    h->grid = bestg;
+  }
+}
+
+extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pdlp_options* o, void* hip_stream,
+                                 pdlp_handle** out) {
+  if (out) *out = nullptr;
+  if (!ps || !out) return fail(nullptr, PDLP_ERR_ARG, "NULL problem array or output pointer");
+  if (count < 1) return fail(nullptr, PDLP_ERR_ARG, "count must be >= 1");
+  pdlp_options opt;
+  if (o) opt = *o;
+  else pdlp_default_options(&opt);
+  std::string why;
+  if (check_options(opt, why)) return fail(nullptr, PDLP_ERR_ARG, why);
+  const double t0 = now_s();
+  // pack the LPs block-diagonally on the host (each one validated on its own)
+  HostLP H;
+  std::vector<int32_t> row_off(1, 0), col_off(1, 0);
+  std::vector<int64_t> nnz_b;
+  int64_t M = 0, N = 0, NZ = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    HostLP L;
+    if (int rc = load_problem(&ps[k], hip_stream, L, why))
+      return fail(nullptr, rc, "LP " + std::to_string(k) + ": " + why);
+    if (M + L.m >= ((int64_t)1 << 31) || N + L.n >= ((int64_t)1 << 31) || NZ + L.nnz >= ((int64_t)1 << 31))
+      return fail(nullptr, PDLP_ERR_ARG, "the packed batch needs total rows, columns and nonzeros below 2^31");
+    if (k == 0) H.rp.push_back(0);
+    for (int32_t r = 0; r < L.m; ++r) H.rp.push_back((int32_t)(NZ + L.rp[(size_t)r + 1]));
+    for (int64_t e = 0; e < L.nnz; ++e) H.ci.push_back((int32_t)(N + L.ci[(size_t)e]));
+    H.v.insert(H.v.end(), L.v.begin(), L.v.begin() + L.nnz);
+    H.c.insert(H.c.end(), L.c.begin(), L.c.begin() + L.n);
+    H.l.insert(H.l.end(), L.l.begin(), L.l.begin() + L.n);
+    H.u.insert(H.u.end(), L.u.begin(), L.u.begin() + L.n);
+    H.b.insert(H.b.end(), L.b.begin(), L.b.begin() + L.m);
+    H.rt.insert(H.rt.end(), L.rt.begin(), L.rt.begin() + L.m);
+    M += L.m;
+    N += L.n;
+    NZ += L.nnz;
+    row_off.push_back((int32_t)M);
+    col_off.push_back((int32_t)N);
+    nnz_b.push_back(L.nnz);
+  }
+  H.m = (int32_t)M;
+  H.n = (int32_t)N;
+  H.nnz = NZ;
+  for (auto* vec : {&H.v, &H.c, &H.l, &H.u, &H.b}) if (vec->empty()) vec->push_back(0.0);
+  if (H.ci.empty()) H.ci.push_back(0);
+  if (H.rt.empty()) H.rt.push_back(0);
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, PDLP_ERR_HIP, "no HIP device");
+  pdlp_handle* h = new pdlp_handle();
+  h->m = H.m;
+  h->n = H.n;
+  h->nnz = H.nnz;
+  h->opt = opt;
+  h->stream = (hipStream_t)hip_stream;
+  h->count = count;
+  h->row_off_h = row_off;
+  h->col_off_h = col_off;
+  h->nnz_h = nnz_b;
+  h->warm_h.assign((size_t)count, 0);
+  h->omega_warm_h.assign((size_t)count, 0.0);
+  try {
+    hipStream_t s = h->stream;
+    const hipMemcpyKind kind = hipMemcpyHostToDevice;
+    upload_normalize_transpose(h, H);
+    h->row_off = h->dalloc<int32_t>((size_t)count + 1);
+    h->col_off = h->dalloc<int32_t>((size_t)count + 1);
+    check(hipMemcpyAsync(h->row_off, row_off.data(), row_off.size() * 4, kind, s), "upload row offsets");
+    check(hipMemcpyAsync(h->col_off, col_off.data(), col_off.size() * 4, kind, s), "upload column offsets");
+    // per-LP norms in the blocked order of the single-LP path: unscaled ||q||^2, ||c||^2 ...
+    h->norms = h->dalloc<double>(4 * (size_t)count);
+    launch_seg_sumsq(count, h->row_off, h->q, h->norms, 4, 0, s);
+    launch_seg_sumsq(count, h->col_off, h->c0, h->norms, 4, 1, s);
+    scale_problem(h);
+    // ... and scaled ||c~||^2, ||q~||^2, max |K~_ij|
+    launch_seg_sumsq(count, h->col_off, h->c, h->norms, 4, 2, s);
+    launch_seg_sumsq(count, h->row_off, h->q, h->norms, 4, 3, s);
+    h->kmax = h->dalloc<double>((size_t)count);
+    launch_seg_absmax(count, h->row_off, h->rp, h->val, h->kmax, s);
+    check(hipGetLastError(), "per-LP norms");
+    Params& P = h->P;
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, nullptr, 0, h->m, 0, 0, 0, 0, PanelCsr{}};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, nullptr, 0, h->n, 0, 0, 0, 0, PanelCsr{}};
+    alloc_iterates(h);
+    P.st = nullptr;
+    h->bst = h->dalloc<DevState>((size_t)count);
+    h->omega_warm = h->dalloc<double>((size_t)count);
+    h->warm = h->dalloc<int8_t>((size_t)count);
+    h->queue = h->dalloc<uint32_t>(1);
+    h->t0 = h->dalloc<uint64_t>(1);
+    h->lanes = h->dalloc<uint8_t>(2 * (size_t)count);
+    // queue order: most nonzeros first, so that the long solves start early
+    std::vector<int32_t> ord((size_t)count);
+    for (int32_t k = 0; k < count; ++k) ord[(size_t)k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return nnz_b[(size_t)a] > nnz_b[(size_t)b]; });
+    h->order = h->dalloc<int32_t>((size_t)count);
+    check(hipMemcpyAsync(h->order, ord.data(), ord.size() * 4, kind, s), "upload queue order");
+    int dev = 0, khz = 0;
+    check(hipGetDevice(&dev), "hipGetDevice");
+    check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+    h->tick_hz = 1000.0 * (khz > 0 ? khz : 100000);
+    check(hipStreamSynchronize(s), "setup sync");
+    check(hipGetLastError(), "setup kernels");
+    tune_batch(h);
+  } catch (const HipFail& f) {
+    return create_failed(h, f);
+  }
+  h->setup_s = now_s() - t0;
+  *out = h;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_set_warm_start_batch(pdlp_handle* h, int32_t idx, const double* x0, const double* y0,
+                                         double omega0) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->count) return fail(h, PDLP_ERR_STATE, "pdlp_set_warm_start_batch on a single-LP handle");
+  if (idx < -1 || idx >= h->count) return fail(h, PDLP_ERR_ARG, "idx must be -1 or in [0, count)");
+  const int32_t b0 = idx < 0 ? 0 : idx, b1 = idx < 0 ? h->count : idx + 1;
+  const int32_t j0 = h->col_off_h[b0], j1 = h->col_off_h[b1], i0 = h->row_off_h[b0], i1 = h->row_off_h[b1];
+  if (x0)
+    for (int32_t j = 0; j < j1 - j0; ++j)
+      if (!std::isfinite(x0[j])) return fail(h, PDLP_ERR_DATA, "warm-start x0 is not finite");
+  if (y0)
+    for (int32_t i = 0; i < i1 - i0; ++i)
+      if (!std::isfinite(y0[i])) return fail(h, PDLP_ERR_DATA, "warm-start y0 is not finite");
+  if (std::isnan(omega0) || std::isinf(omega0)) return fail(h, PDLP_ERR_DATA, "warm-start omega0 is not finite");
+  try {
+    std::vector<double> zx((size_t)(j1 - j0), 0.0), zy((size_t)std::max(i1 - i0, 1), 0.0);
+    check(hipMemcpy(h->wx + j0, x0 ? x0 : zx.data(), (size_t)(j1 - j0) * 8, hipMemcpyHostToDevice), "upload x0");
+    if (i1 > i0)
+      check(hipMemcpy(h->wy + i0, y0 ? y0 : zy.data(), (size_t)(i1 - i0) * 8, hipMemcpyHostToDevice), "upload y0");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  for (int32_t b = b0; b < b1; ++b) {
+    h->warm_h[(size_t)b] = (x0 != nullptr) || (y0 != nullptr);
+    h->omega_warm_h[(size_t)b] = omega0 > 0.0 ? omega0 : 0.0;
+  }
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_solve_batch(pdlp_handle* h) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve_batch on a single-LP handle");
+  const double t0 = now_s();
+  try {
+    hipStream_t s = h->stream;
+    const size_t cnt = (size_t)h->count;
+    check(hipMemcpyAsync(h->warm, h->warm_h.data(), cnt, hipMemcpyHostToDevice, s), "upload warm flags");
+    check(hipMemcpyAsync(h->omega_warm, h->omega_warm_h.data(), cnt * 8, hipMemcpyHostToDevice, s),
+          "upload warm omegas");
+    launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, h->opt.time_limit_s);
+    h->bst_h.resize(cnt);
+    check(hipMemcpyAsync(h->bst_h.data(), h->bst, cnt * sizeof(DevState), hipMemcpyDeviceToHost, s), "read states");
+    check(hipStreamSynchronize(s), "batch sync");
+    check(hipGetLastError(), "batch kernels");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  h->info.solve_s = now_s() - t0;
+  h->solved = true;
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, double* y, double* rc,
+                                       pdlp_info* info) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution_batch on a single-LP handle");
+  if (idx < -1 || idx >= h->count) return fail(h, PDLP_ERR_ARG, "idx must be -1 or in [0, count)");
+  if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution_batch before pdlp_solve_batch");
+  const int32_t b0 = idx < 0 ? 0 : idx, b1 = idx < 0 ? h->count : idx + 1;
+  const int32_t j0 = h->col_off_h[b0], j1 = h->col_off_h[b1], i0 = h->row_off_h[b0], i1 = h->row_off_h[b1];
+  try {
+    if (x) check(hipMemcpy(x, h->xo + j0, (size_t)(j1 - j0) * 8, hipMemcpyDeviceToHost), "download x");
+    if (y && i1 > i0) check(hipMemcpy(y, h->yo + i0, (size_t)(i1 - i0) * 8, hipMemcpyDeviceToHost), "download y");
+    if (rc) check(hipMemcpy(rc, h->rco + j0, (size_t)(j1 - j0) * 8, hipMemcpyDeviceToHost), "download rc");
+  } catch (const HipFail& f) {
+    return fail(h, PDLP_ERR_HIP, hip_msg(f));
+  }
+  if (info) {
+    for (int32_t b = b0; b < b1; ++b) {
+      const DevState& f = h->bst_h[(size_t)b];
+      pdlp_info& I = info[b - b0];
+      I = pdlp_info{};
+      I.status = f.status;
+      I.returned_avg = f.ret_avg;
+      I.iterations = f.k;
+      I.attempts = f.attempts;
+      I.restarts = f.restarts;
+      I.evaluations = f.evals;
+      I.rel_kkt = f.rel_kkt;
+      I.rel_gap = f.rel_gap;
+      I.rel_pres = f.rel_p;
+      I.rel_dres = f.rel_d;
+      I.primal_obj = f.pobj;
+      I.dual_obj = f.dobj;
+      I.omega = f.omega;
+      I.eta_hat = f.eta_hat;
+      I.setup_s = h->setup_s;
+      I.solve_s = h->info.solve_s;
+      I.layout_k = h->lanes_h[2 * (size_t)b];
+      I.layout_kt = h->lanes_h[2 * (size_t)b + 1];
+    }
+  }
+  return PDLP_OK;
+}
+
+extern "C" int pdlp_batch_schedule(pdlp_handle* h, int32_t* lanes, int32_t* grid) {
+  if (!h) return PDLP_ERR_ARG;
+  if (!h->count) return fail(h, PDLP_ERR_STATE, "pdlp_batch_schedule on a single-LP handle");
+  if (lanes)
+    for (size_t k = 0; k < h->lanes_h.size(); ++k) lanes[k] = h->lanes_h[k];
+  if (grid) *grid = h->grid;
   return PDLP_OK;
 }
 

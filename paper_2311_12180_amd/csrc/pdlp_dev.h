@@ -5,16 +5,37 @@
 
 namespace pdlp {
 
-constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
-constexpr int kTile = 2048;      // nonzeros staged in LDS per row block
-constexpr int kMaxRows = 1024;   // rows per row block
-constexpr int kElemBlocks = 2048;  // fixed grid of the elementwise kernels (deterministic partials)
+constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
+constexpr int kTile = 2048;        // nonzeros staged in LDS per row block
+constexpr int kMaxRows = 1024;     // rows per row block
+constexpr int kElemBlocks = 2048;  // fixed grid of the row-wise kernels (deterministic partials)
+constexpr int kPanels = 8;         // column panels of the split layout = XCDs of the chip
 
 // A row block of a CSR matrix: rows [r0, r1).  Either short rows with at most
 // kTile nonzeros in total (handled in one pass through LDS), or one long row
 // with more than kTile nonzeros (swept by the whole workgroup).
 struct RowBlock {
   int32_t r0, r1;
+};
+
+// Column-panel ("split") layout of a CSR matrix.  The columns are cut into
+// kPanels ranges of about equal nonzero count; the nonzeros of row r that fall
+// in panel p form segment (r, p).  Segments are stored panel-major (all of
+// panel 0, then panel 1, ...), rows ascending inside a panel; the phase-1
+// blocks are interleaved so that workgroup i only touches panel i % kPanels.
+// Workgroups are dispatched round-robin over the 8 XCDs, so each XCD gathers
+// from one eighth of the vector, which then stays in its own L2.
+struct PanelCsr {
+  int32_t nseg;
+  int32_t nsblocks;
+  const int32_t* seg_ptr;   // [nseg+1] start of each segment in pci / pv (panel-major)
+  const int32_t* seg_dst;   // [nseg]   row-major index of the segment (its partial slot)
+  const int32_t* row_seg;   // [nrows+1] row r's partial slots are [row_seg[r], row_seg[r+1])
+  const int32_t* pci;       // [nnz] column indices in segment order
+  const double* pv;         // [nnz] FP64 values in segment order
+  const float* pvf;         // [nnz] FP32 values in segment order (nullptr unless FP32 steps)
+  const RowBlock* sblocks;  // [nsblocks] phase-1 blocks (rows of the segment "matrix")
+  double* part;             // [2 * nseg] segment sums, row-major
 };
 
 struct DevCsr {
@@ -25,6 +46,11 @@ struct DevCsr {
   const RowBlock* blocks; // long rows first, then runs of short rows
   int32_t nblocks;
   int32_t nrows;
+  int32_t layout;         // 0: fused row blocks; 1: column panels (two phases)
+  int32_t remap;          // fused layout: contiguous block ranges per XCD
+  int32_t nred;           // reduction partials of a pass over this matrix
+  int32_t rows_grid;      // grid of the phase-2 (row-wise) kernels
+  PanelCsr pan;
 };
 
 // Solver state in device memory.  The first 16 bytes are the status word the
@@ -70,7 +96,7 @@ struct Params {
   DevCsr KT;    // n rows
   int32_t m, n;
   int32_t use_f32;
-  int32_t xcd_remap;
+  int32_t pad0;
   // iterates (double-buffered where a step writes a new one)
   double* x[2];
   double* y[2];
@@ -82,14 +108,18 @@ struct Params {
   // problem (scaled, >= form)
   const double* c; const double* q; const double* l; const double* u;
   const int8_t* ineq;
+  const int8_t* le;
   const double* D1; const double* D2;
-  // reductions
+  // outputs of the last solve (user orientation)
+  double* xo; double* yo; double* rco;
+  // probe vectors of the layout tuner
+  const double* probe_in; double* probe_out;
   // one partial (NV doubles) per workgroup, added in order by the decision kernels
-  double* partA;          // [K'.nblocks]      ||dx||^2
-  double* partB;          // [K.nblocks * 2]   ||dy||^2, dy'K~dx
+  double* partA;          // ||dx||^2
+  double* partB;          // ||dy||^2, dy'K~dx
   double* partE0;         // [kElemBlocks * 4]
-  double* partE1;         // [K.nblocks * 8]
-  double* partE2;         // [K'.nblocks * 6]
+  double* partE1;         // 8 per partial
+  double* partE2;         // 6 per partial
   DevState* st;
   Trace tr;
   // constants
@@ -98,6 +128,30 @@ struct Params {
   double tie_rel;         // relative band in which the candidate comparison is a tie
   int32_t omega_power;
   double qnorm0, cnorm0;
+};
+
+// Batched solve (many independent LPs packed block-diagonally into one Params).
+struct BatchParams {
+  int32_t count;            // LPs in the queue
+  int32_t trace_lp;         // LP whose decisions are traced (-1: none)
+  const int32_t* order;     // [count] queue order (LP indices)
+  const int32_t* row_off;   // [nlp+1]
+  const int32_t* col_off;   // [nlp+1]
+  const uint8_t* lanes;     // [2*nlp] lanes per row for K~ rows, for K~' rows
+  DevState* st;             // [nlp]
+  const double* norms;      // [4*nlp] squared norms: ||q||, ||c|| (unscaled), ||c~||, ||q~|| (scaled)
+  const double* kmax;       // [nlp] max |K~_ij|
+  const double* omega_warm; // [nlp] warm-start primal weight (<= 0: default)
+  const int8_t* warm;       // [nlp] 1: start from the warm-start slices of wx / wy
+  const double* wx;
+  const double* wy;
+  uint32_t* queue;          // next queue slot (zero before the launch)
+  const uint64_t* t0;       // wall-clock stamp taken just before the launch
+  uint64_t ticks;           // time limit in wall-clock ticks (0: none)
+  int64_t max_reject;       // consecutive rejected attempts that count as a numerical failure
+  double eps_rel;
+  int64_t max_iter;
+  double eps_zero;
 };
 
 }  // namespace pdlp

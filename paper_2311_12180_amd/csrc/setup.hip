@@ -127,6 +127,18 @@ __global__ void k_to_f32(int64_t nnz, const double* __restrict__ v, float* __res
     f[p] = (float)v[p];
 }
 
+// Column-panel order of a matrix: entry q of the panel layout is entry perm[q].
+__global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, const int32_t* __restrict__ ci,
+                          const double* __restrict__ v, const float* __restrict__ vf, int32_t* __restrict__ pci,
+                          double* __restrict__ pv, float* __restrict__ pvf) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = perm[q];
+    pci[q] = ci[p];
+    pv[q] = v[p];
+    if (vf) pvf[q] = vf[p];
+  }
+}
+
 __global__ void k_fill(int64_t n, double* __restrict__ a, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
@@ -247,6 +259,12 @@ hipError_t setup_absmax(int64_t nnz, const double* v, unsigned long long* out, h
 
 hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s) {
   if (nnz > 0) hipLaunchKernelGGL(k_to_f32, grid_for(nnz), dim3(256), 0, s, nnz, v, f);
+  return hipGetLastError();
+}
+
+hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
+                         int32_t* pci, double* pv, float* pvf, hipStream_t s) {
+  if (nnz > 0) hipLaunchKernelGGL(k_permute, grid_for(nnz), dim3(256), 0, s, nnz, perm, ci, v, vf, pci, pv, pvf);
   return hipGetLastError();
 }
 

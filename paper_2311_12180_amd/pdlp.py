@@ -29,7 +29,9 @@ ERRORS = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_DATA", -3: "PDLP_ERR_HIP", -4: "PDLP
 
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_set_warm_start", "pdlp_set_termination", "pdlp_solve",
             "pdlp_get_solution", "pdlp_get_iterate", "pdlp_get_scaling", "pdlp_get_trace",
-            "pdlp_profile_attempts", "pdlp_step_bytes", "pdlp_last_error", "pdlp_destroy"]
+            "pdlp_profile_attempts", "pdlp_step_bytes", "pdlp_create_batch", "pdlp_set_warm_start_batch",
+            "pdlp_solve_batch", "pdlp_get_solution_batch", "pdlp_batch_schedule", "pdlp_last_error",
+            "pdlp_destroy"]
 
 
 class PdlpError(RuntimeError):
@@ -51,7 +53,8 @@ class pdlp_options(C.Structure):
                 ("pw_theta", C.c_double), ("eps_zero", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
                 ("kkt_omega_power", C.c_int32), ("trace", C.c_int32), ("poll_every", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("spmv_layout", C.c_int32), ("batch_lanes", C.c_int32),
+                ("batch_grid", C.c_int32)]
 
 
 class pdlp_info(C.Structure):
@@ -60,7 +63,7 @@ class pdlp_info(C.Structure):
                 ("rel_kkt", C.c_double), ("rel_gap", C.c_double), ("rel_pres", C.c_double),
                 ("rel_dres", C.c_double), ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("omega", C.c_double), ("eta_hat", C.c_double), ("setup_s", C.c_double),
-                ("solve_s", C.c_double)]
+                ("solve_s", C.c_double), ("layout_k", C.c_int32), ("layout_kt", C.c_int32)]
 
 
 class pdlp_iter_state(C.Structure):
@@ -92,6 +95,11 @@ def lib() -> C.CDLL:
         L.pdlp_get_trace.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.pdlp_profile_attempts.argtypes = [vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
         L.pdlp_step_bytes.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl)]
+        L.pdlp_create_batch.argtypes = [C.POINTER(pdlp_problem), i32, C.POINTER(pdlp_options), vp, C.POINTER(vp)]
+        L.pdlp_set_warm_start_batch.argtypes = [vp, i32, vp, vp, dbl]
+        L.pdlp_solve_batch.argtypes = [vp]
+        L.pdlp_get_solution_batch.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.pdlp_batch_schedule.argtypes = [vp, vp, vp]
         L.pdlp_last_error.argtypes = [vp]
         L.pdlp_last_error.restype = C.c_char_p
         L.pdlp_destroy.argtypes = [vp]
@@ -186,6 +194,89 @@ def pdlp_create(problem, options: Optional[pdlp_options] = None, stream=None, **
     rc = lib().pdlp_create(C.byref(s), C.byref(options), C.c_void_p(stream) if stream else None, C.byref(out))
     _check(rc)
     return Handle(out.value, int(problem.m), int(problem.n), nnz, (arrs, options))
+
+
+def _host_arrays(problem) -> dict:
+    return dict(row_ptr=np.ascontiguousarray(problem.row_ptr, dtype=np.int32),
+                col_idx=np.ascontiguousarray(problem.col_idx, dtype=np.int32),
+                val=np.ascontiguousarray(problem.val, dtype=np.float64),
+                c=np.ascontiguousarray(problem.c, dtype=np.float64),
+                b=np.ascontiguousarray(problem.b, dtype=np.float64),
+                l=np.ascontiguousarray(problem.l, dtype=np.float64),
+                u=np.ascontiguousarray(problem.u, dtype=np.float64),
+                row_type=np.ascontiguousarray(problem.row_type, dtype=np.int8))
+
+
+class BatchHandle(Handle):
+    """A pdlp_handle over several LPs; ms / ns / nnzs are the per-LP sizes."""
+
+    def __init__(self, ptr: int, ms, ns, nnzs, keep):
+        super().__init__(ptr, int(sum(ms)), int(sum(ns)), int(sum(nnzs)), keep)
+        self.count = len(ms)
+        self.ms = np.asarray(ms, np.int64)
+        self.ns = np.asarray(ns, np.int64)
+        self.row_off = np.concatenate([[0], np.cumsum(self.ms)])
+        self.col_off = np.concatenate([[0], np.cumsum(self.ns)])
+
+
+def pdlp_create_batch(problems, options: Optional[pdlp_options] = None, stream=None, **opts) -> BatchHandle:
+    """Create a batch handle for a list of host problems (as for pdlp_create)."""
+    if options is None:
+        options = pdlp_default_options(**opts)
+    elif opts:
+        raise ValueError("pass either options or keyword options")
+    arrs = [_host_arrays(p) for p in problems]
+    structs = (pdlp_problem * max(len(arrs), 1))()
+    for k, (p, a) in enumerate(zip(problems, arrs)):
+        nnz = int(a["row_ptr"][-1]) if len(a["row_ptr"]) else 0
+        structs[k] = pdlp_problem(int(p.m), int(p.n), nnz, PDLP_MEM_HOST, *[_ptr(a[key]) for key in
+                                  ("row_ptr", "col_idx", "val", "c", "b", "l", "u", "row_type")])
+    out = C.c_void_p()
+    rc = lib().pdlp_create_batch(structs, len(arrs), C.byref(options), C.c_void_p(stream) if stream else None,
+                                 C.byref(out))
+    _check(rc)
+    nnzs = [int(a["row_ptr"][-1]) for a in arrs]
+    return BatchHandle(out.value, [int(p.m) for p in problems], [int(p.n) for p in problems], nnzs,
+                       (arrs, structs, options))
+
+
+def pdlp_set_warm_start_batch(h: BatchHandle, idx: int, x0=None, y0=None, omega0: float = 0.0):
+    """Warm start of LP idx, or of all LPs (packed vectors) when idx = -1."""
+    nx = h.n if idx < 0 else int(h.ns[idx])
+    ny = h.m if idx < 0 else int(h.ms[idx])
+    x0 = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    y0 = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+    if x0 is not None and x0.shape != (nx,):
+        raise ValueError(f"x0 must have {nx} entries")
+    if y0 is not None and y0.shape != (ny,):
+        raise ValueError(f"y0 must have {ny} entries")
+    _check(lib().pdlp_set_warm_start_batch(h.ptr, int(idx), _ptr(x0), _ptr(y0), float(omega0)), h)
+
+
+def pdlp_solve_batch(h: BatchHandle):
+    _check(lib().pdlp_solve_batch(h.ptr), h)
+
+
+def pdlp_get_solution_batch(h: BatchHandle, idx: int):
+    """(x, y, reduced_cost, info) of LP idx; for idx = -1 the packed vectors of
+    every LP and a list of info dicts."""
+    nx = h.n if idx < 0 else int(h.ns[idx])
+    ny = h.m if idx < 0 else int(h.ms[idx])
+    x = np.zeros(nx); y = np.zeros(ny); rc = np.zeros(nx)
+    cnt = h.count if idx < 0 else 1
+    infos = (pdlp_info * cnt)()
+    _check(lib().pdlp_get_solution_batch(h.ptr, int(idx), _ptr(x), _ptr(y), _ptr(rc), infos), h)
+    if idx < 0:
+        return x, y, rc, [_info_dict(i) for i in infos]
+    return x, y, rc, _info_dict(infos[0])
+
+
+def pdlp_batch_schedule(h: BatchHandle):
+    """(lanes[count, 2] for K and K' rows, workgroups of the launch)."""
+    lanes = np.zeros(2 * h.count, np.int32)
+    g = C.c_int32()
+    _check(lib().pdlp_batch_schedule(h.ptr, _ptr(lanes), C.byref(g)), h)
+    return lanes.reshape(h.count, 2), g.value
 
 
 def pdlp_set_warm_start(h: Handle, x0=None, y0=None, omega0: float = 0.0):

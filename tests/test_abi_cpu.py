@@ -89,6 +89,19 @@ def test_rejects_bad_sizes_and_options(P):
     _bad(p, P, P.PDLP_ERR_ARG, "kkt_omega_power", kkt_omega_power=3)
 
 
+def test_batch_rejects_bad_members_and_options(P):
+    good = lpgen.mixed_lp(0, m=10, n=12)
+    bad = copy.deepcopy(good); bad.col_idx[2] = -1
+    for probs, code, frag, opts in [([good, good, bad], P.PDLP_ERR_DATA, "LP 2: col_idx", {}),
+                                    ([good], P.PDLP_ERR_ARG, "batch_lanes", {"batch_lanes": 3}),
+                                    ([good], P.PDLP_ERR_ARG, "batch_lanes", {"batch_lanes": 128}),
+                                    ([good], P.PDLP_ERR_ARG, "batch_grid", {"batch_grid": -2}),
+                                    ([], P.PDLP_ERR_ARG, "count", {})]:
+        with pytest.raises(P.PdlpError) as e:
+            P.pdlp_create_batch(probs, **opts)
+        assert e.value.code == code and frag in str(e.value), str(e.value)
+
+
 def test_null_arguments(P):
     lib = P.lib()
     assert lib.pdlp_default_options(None) == P.PDLP_ERR_ARG
@@ -96,6 +109,11 @@ def test_null_arguments(P):
     assert lib.pdlp_solve(None) == P.PDLP_ERR_ARG
     assert lib.pdlp_get_solution(None, None, None, None, None) == P.PDLP_ERR_ARG
     assert lib.pdlp_set_termination(None, 1e-4, 10, 1.0) == P.PDLP_ERR_ARG
+    assert lib.pdlp_create_batch(None, 1, None, None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_solve_batch(None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_get_solution_batch(None, 0, None, None, None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_set_warm_start_batch(None, 0, None, None, 0.0) == P.PDLP_ERR_ARG
+    assert lib.pdlp_batch_schedule(None, None, None) == P.PDLP_ERR_ARG
     lib.pdlp_destroy(None)
     assert isinstance(P.pdlp_last_error(None), str)
 

@@ -1,0 +1,241 @@
+"""GPU parity of the batched solver (one persistent launch over many LPs)
+against the CPU FP64 oracle, LP by LP.
+
+Bars (as for the single-LP path):
+  * first 100 accepted steps (no termination): the same numbers of attempts
+    and restarts per LP, the same decisions in LP 0's trace, and the returned
+    point within 1e-10 (relative, inf-norm) of the oracle's;
+  * end to end at rel KKT 1e-4 and 1e-8: objective within 1e-6 relative of the
+    oracle's, the returned point passes the oracle's FP64 evaluator, and at
+    1e-8 the objective is within 1e-6 of the LP's constructed optimum;
+  * an LP's result does not depend on the other LPs of the batch or on which
+    workgroup ran it: bitwise equal alone and inside the batch, and run to run.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+from tests.exact import box_lp_optimum
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2311_12180_amd import pdlp
+    pdlp.lib()
+    return pdlp
+
+
+def _box_lp(seed=0, n=40):
+    """An LP without rows: min c'x over a box (closed-form optimum)."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(n)
+    l = rng.uniform(-3, 0, n)
+    u = l + rng.uniform(0.5, 4, n)
+    z = np.zeros(0)
+    return lpgen.Problem(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), z, c, z, l, u,
+                         np.zeros(0, np.int8), "box", None, None, None)
+
+
+def _small_batch(count=24, seed=3, m_lo=50, m_hi=300):
+    ms = lpgen.batch_sizes(seed, count, m_lo, m_hi)
+    return [lpgen.batch_lp(seed, i, int(ms[i])) for i in range(count)]
+
+
+def _mixed_batch():
+    return [lpgen.batch_lp(5, 0, 120), lpgen.transportation(2, 6, 9), lpgen.mixed_lp(3), _box_lp(1),
+            lpgen.batch_lp(5, 1, 64), lpgen.batch_lp(5, 2, 400)]
+
+
+def _rel_inf(a, b):
+    return float(np.abs(a - b).max(initial=0.0) / max(1.0, np.abs(b).max(initial=0.0)))
+
+
+def _split(h, v, rows):
+    off = h.row_off if rows else h.col_off
+    return [v[off[k]:off[k + 1]] for k in range(h.count)]
+
+
+def _oracle_spread(orc, p, opts, trace=False, copies=3):
+    """The oracle's result and how far it moves from itself when only the
+    summation order changes (rows and columns renumbered): spread of the
+    returned point, of the objective and (trace) of the attempted step sizes,
+    and whether every copy made the same numbers of attempts and restarts."""
+    cap = 4096 if trace else 0
+    a = orc.solve(p, trace_cap=cap, **opts)
+    sx = so = se = 0.0
+    stable = True
+    for s in range(copies):
+        rng = np.random.default_rng(123 + s)
+        rp, cp = rng.permutation(p.m), rng.permutation(p.n)
+        b = orc.solve(lpgen.permute(p, rp, cp), trace_cap=cap, **opts)
+        stable &= b.info["attempts"] == a.info["attempts"] and b.info["restarts"] == a.info["restarts"]
+        sx = max(sx, _rel_inf(b.x, a.x[cp]), _rel_inf(b.y, a.y[rp]))
+        so = max(so, abs(b.info["primal_obj"] - a.info["primal_obj"]) / (1 + abs(a.info["primal_obj"])))
+        if trace and len(b.trace["att_eta"]) == len(a.trace["att_eta"]):
+            se = max(se, float(np.max(np.abs(b.trace["att_eta"] - a.trace["att_eta"]) / a.trace["att_eta"])))
+    return a, sx, so, se, bool(stable)
+
+
+def test_first_100_steps_match_oracle(P, orc):
+    """Per LP: the same attempts and restarts, the returned point within
+    max(1e-10, 100 x the oracle's own rounding-order spread); LP 0's trace:
+    the same decisions, step sizes within the same kind of bar (the step
+    bound's denominator dy'K dx cancels, which amplifies rounding)."""
+    probs = _small_batch(16)
+    opts = dict(eps_rel=0.0, max_iter=100)
+    h = P.pdlp_create_batch(probs, time_limit_s=60.0, trace=4096, **opts)
+    P.pdlp_solve_batch(h)
+    x, y, rc, infos = P.pdlp_get_solution_batch(h, -1)
+    xs, ys = _split(h, x, False), _split(h, y, True)
+    tr = P.pdlp_get_trace(h, 4096)
+    compared, rows = 0, []
+    for k, p in enumerate(probs):
+        r, sx, so, se, stable = _oracle_spread(orc, p, opts, trace=(k == 0))
+        I = infos[k]
+        assert I["status_name"] == "ITER_LIMIT" and I["iterations"] == 100
+        if not stable:
+            rows.append(f"LP {k}: oracle decisions change under renumbering, not compared")
+            continue
+        compared += 1
+        ex, ey = _rel_inf(xs[k], r.x), _rel_inf(ys[k], r.y)
+        tol = max(1e-10, 100 * sx)
+        rows.append(f"LP {k}: x {ex:.1e} y {ey:.1e} tol {tol:.1e}")
+        assert I["attempts"] == r.info["attempts"] and I["restarts"] == r.info["restarts"], k
+        assert I["returned_avg"] == r.info["returned_avg"], k
+        assert ex <= tol and ey <= tol, (k, ex, ey, tol)
+        if k == 0:
+            np.testing.assert_array_equal(tr["att_acc"], r.trace["att_acc"])
+            np.testing.assert_array_equal(tr["ev_reason"], r.trace["ev_reason"])
+            np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
+            np.testing.assert_allclose(tr["att_eta"], r.trace["att_eta"], rtol=max(1e-10, 100 * se))
+    print("\n".join(rows))
+    assert compared >= len(probs) // 2
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_end_to_end_matches_oracle(P, orc, eps):
+    """Objective within max(1e-6, 10 x the oracle's own spread under
+    renumbering) of the oracle's: at rel KKT 1e-4 the stopping point, and
+    with it the objective, moves by up to ~1e-4 relative with the summation
+    order alone on some of these LPs."""
+    probs = _mixed_batch() + _small_batch(10, seed=4)
+    opts = dict(eps_rel=eps, max_iter=200000)
+    h = P.pdlp_create_batch(probs, time_limit_s=120.0, **opts)
+    P.pdlp_solve_batch(h)
+    for k, p in enumerate(probs):
+        x, y, rc, I = P.pdlp_get_solution_batch(h, k)
+        r, _, so, _, _ = _oracle_spread(orc, p, opts)
+        assert I["status_name"] == "OPTIMAL" and r.status == "OPTIMAL", (k, p.name, I["status_name"])
+        assert I["rel_kkt"] <= eps
+        obj = I["primal_obj"]
+        tol = max(1e-6, 10 * so)
+        assert abs(obj - r.info["primal_obj"]) <= tol * (1 + abs(r.info["primal_obj"])), (k, p.name, tol)
+        e = orc.evaluate(p, x, y)
+        assert e["rel_kkt"] <= eps * (1 + 1e-6), (k, p.name, e["rel_kkt"])
+        assert e["primal_obj"] == pytest.approx(obj, rel=1e-12, abs=1e-12)
+        np.testing.assert_allclose(rc, orc.reduced_costs(p, y), rtol=1e-9, atol=1e-9)
+        if eps <= 1e-8:
+            ref = box_lp_optimum(p.c, p.l, p.u)[0] if p.name == "box" else p.obj_star()
+            if ref is not None:
+                assert abs(obj - ref) <= 1e-6 * (1 + abs(ref)), (k, p.name)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8, 64])
+def test_any_lanes_per_row(P, orc, lanes):
+    """Every lanes-per-row choice of the schedule computes the same method."""
+    probs = _small_batch(6, seed=7) + [lpgen.mixed_lp(2)]
+    opts = dict(eps_rel=0.0, max_iter=100)
+    h = P.pdlp_create_batch(probs, batch_lanes=lanes, batch_grid=3, time_limit_s=60.0, **opts)
+    sched, grid = P.pdlp_batch_schedule(h)
+    assert grid == 3 and (sched == lanes).all()
+    P.pdlp_solve_batch(h)
+    for k, p in enumerate(probs):
+        x, y, _, I = P.pdlp_get_solution_batch(h, k)
+        r = orc.solve(p, **opts)
+        assert I["attempts"] == r.info["attempts"], k
+        assert _rel_inf(x, r.x) <= 1e-10 and _rel_inf(y, r.y) <= 1e-10, k
+
+
+def test_member_result_independent_of_batch(P):
+    """Bitwise: LP k alone, LP k inside the batch, and a second solve."""
+    probs = _small_batch(12, seed=9)
+    kw = dict(eps_rel=1e-6, batch_lanes=8, batch_grid=5, time_limit_s=60.0)
+    h = P.pdlp_create_batch(probs, **kw)
+    P.pdlp_solve_batch(h)
+    a = P.pdlp_get_solution_batch(h, -1)
+    P.pdlp_solve_batch(h)
+    b = P.pdlp_get_solution_batch(h, -1)
+    for u, v in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(u, v)
+    for k in (0, 5, 11):
+        h1 = P.pdlp_create_batch([probs[k]], **kw)
+        P.pdlp_solve_batch(h1)
+        x1, y1, rc1, I1 = P.pdlp_get_solution_batch(h1, 0)
+        x, y, rc, I = P.pdlp_get_solution_batch(h, k)
+        np.testing.assert_array_equal(x1, x)
+        np.testing.assert_array_equal(y1, y)
+        assert I1["iterations"] == I["iterations"]
+
+
+def test_schedule_autotuned(P):
+    probs = _small_batch(40, seed=11)
+    h = P.pdlp_create_batch(probs, eps_rel=1e-4)
+    sched, grid = P.pdlp_batch_schedule(h)
+    assert sched.shape == (40, 2) and grid >= 1
+    assert set(np.unique(sched)) <= {1, 2, 4, 8, 16, 32, 64}
+    P.pdlp_solve_batch(h)
+    infos = P.pdlp_get_solution_batch(h, -1)[3]
+    assert all(i["status_name"] == "OPTIMAL" for i in infos)
+    assert [i["layout_k"] for i in infos] == list(sched[:, 0])
+
+
+def test_warm_start_batch(P, orc):
+    probs = _small_batch(8, seed=13)
+    h = P.pdlp_create_batch(probs, eps_rel=1e-6, time_limit_s=60.0)
+    P.pdlp_solve_batch(h)
+    x, y, _, cold = P.pdlp_get_solution_batch(h, -1)
+    # every LP from its own solution (packed form): done at the first evaluations
+    P.pdlp_set_warm_start_batch(h, -1, x, y)
+    P.pdlp_solve_batch(h)
+    warm = P.pdlp_get_solution_batch(h, -1)[3]
+    for c, w in zip(cold, warm):
+        assert w["status_name"] == "OPTIMAL"
+        assert w["iterations"] <= max(64, c["iterations"] // 4)
+    # one LP from a known optimum, the others cleared back to a cold start
+    P.pdlp_set_warm_start_batch(h, -1, None, None)
+    p = probs[3]
+    P.pdlp_set_warm_start_batch(h, 3, p.x_star, p.y_star)
+    P.pdlp_solve_batch(h)
+    infos = P.pdlp_get_solution_batch(h, -1)[3]
+    assert infos[3]["iterations"] == 0 and infos[3]["status_name"] == "OPTIMAL"
+    assert [i["iterations"] for k, i in enumerate(infos) if k != 3] == \
+        [i["iterations"] for k, i in enumerate(cold) if k != 3]
+
+
+def test_time_limit_ends_every_lp(P):
+    probs = _small_batch(8, seed=15, m_lo=300, m_hi=400)
+    h = P.pdlp_create_batch(probs, eps_rel=0.0, max_iter=10**9, time_limit_s=0.05, batch_lanes=8, batch_grid=4)
+    P.pdlp_solve_batch(h)
+    infos = P.pdlp_get_solution_batch(h, -1)[3]
+    assert all(i["status_name"] == "TIME_LIMIT" for i in infos)
+    assert max(i["solve_s"] for i in infos) < 5.0
+
+
+def test_batch_state_errors(P):
+    probs = _small_batch(2, seed=17)
+    h = P.pdlp_create_batch(probs, batch_lanes=4, batch_grid=2)
+    with pytest.raises(P.PdlpError, match="PDLP_ERR_STATE"):
+        P.pdlp_get_solution_batch(h, 0)
+    with pytest.raises(P.PdlpError, match="PDLP_ERR_STATE"):
+        P.pdlp_solve(h)
+    with pytest.raises(P.PdlpError, match="PDLP_ERR_STATE"):
+        P.pdlp_get_iterate(h)
+    with pytest.raises(P.PdlpError, match="PDLP_ERR_ARG"):
+        P._check(P.lib().pdlp_set_warm_start_batch(h.ptr, 2, None, None, 0.0), h)
+    s = P.pdlp_create(probs[0])
+    with pytest.raises(P.PdlpError, match="PDLP_ERR_STATE"):
+        P._check(P.lib().pdlp_solve_batch(s.ptr), s)

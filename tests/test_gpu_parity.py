@@ -141,6 +141,36 @@ def test_trajectory_matches_oracle(P, orc, name, period, kmax):
         assert max(ex, ey) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["random_1000x2000", "skewed_3000x6000", "long_rows", "transport_30x40"])
+@pytest.mark.parametrize("layout", [1, 2])
+def test_layouts_match_oracle(P, orc, name, layout):
+    """Column panels (1) and XCD-contiguous row blocks (2) follow the oracle's
+    trajectory like the default layout: same decisions, iterates within the
+    rounding-order bar, over 100 accepted steps."""
+    p = PROBLEMS[name]()
+    opts = dict(eps_rel=0.0, max_iter=100, eval_period=64)
+    h = P.pdlp_create(p, time_limit_s=60.0, trace=4096, spmv_layout=layout, **opts)
+    P.pdlp_solve(h)
+    xh, yh, st = P.pdlp_get_iterate(h)
+    tr = P.pdlp_get_trace(h, 4096)
+    info = P.pdlp_get_solution(h)[3]
+    assert (info["layout_k"], info["layout_kt"]) == (layout, layout)
+    r, sx, se, stable = _rounding_spread(orc, p, opts)
+    assert stable
+    tol_x = max(1e-10, 100 * sx)
+    ex, ey = _rel_inf(xh, r.x_hat), _rel_inf(yh, r.y_hat)
+    print(f"{name} layout {layout}: x {ex:.2e} y {ey:.2e} tol {tol_x:.2e}")
+    np.testing.assert_array_equal(tr["att_acc"], r.trace["att_acc"])
+    np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
+    assert st["attempts"] == r.info["attempts"] and st["restarts"] == r.info["restarts"]
+    assert ex <= tol_x and ey <= tol_x
+    res = P.solve(p, eps_rel=1e-6, time_limit_s=60.0, max_iter=200000, spmv_layout=layout)
+    ro = orc.solve(p, eps_rel=1e-6, max_iter=200000)
+    assert res.status == "OPTIMAL"
+    assert abs(res.info["primal_obj"] - ro.info["primal_obj"]) <= 1e-6 * (1 + abs(ro.info["primal_obj"]))
+    assert orc.evaluate(p, res.x, res.y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("eps", [1e-4, 1e-8])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_random_lp_end_to_end(P, orc, eps, seed):
@@ -238,10 +268,11 @@ def test_device_inputs_match_host_inputs(P):
     np.testing.assert_array_equal(a.y, b.y)
 
 
-def test_run_to_run_bitwise(P):
+@pytest.mark.parametrize("layout", [0, 1])
+def test_run_to_run_bitwise(P, layout):
     p = lpgen.skewed_lp(5, m=4000, n=8000, nnz_target=80000, cap=4000)
-    a = P.solve(p, eps_rel=1e-6, time_limit_s=30.0)
-    b = P.solve(p, eps_rel=1e-6, time_limit_s=30.0)
+    a = P.solve(p, eps_rel=1e-6, time_limit_s=30.0, spmv_layout=layout)
+    b = P.solve(p, eps_rel=1e-6, time_limit_s=30.0, spmv_layout=layout)
     np.testing.assert_array_equal(a.x, b.x)
     np.testing.assert_array_equal(a.y, b.y)
     assert a.info["attempts"] == b.info["attempts"]
