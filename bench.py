@@ -73,6 +73,92 @@ def cpu_baseline(prob, iters: int):
                        f"setup {info['setup_s']:.1f}s excluded, total {wall:.1f}s")}
 
 
+def _gen_batch_lp(args):
+    import lpgen
+    seed, i, m = args
+    return lpgen.batch_lp(seed, i, m)
+
+
+def _oracle_one(args):
+    import oracle
+    p, eps = args
+    r = oracle.solve(p, eps_rel=eps, max_iter=200000, threads=1)
+    return r.info["primal_obj"], r.info["iterations"], r.info["solve_s"], r.status
+
+
+def batch_section(P, stream, count: int, eps: float, sample: int):
+    """4096 random LPs (m ~ U{50..2000}, n = 2m, 8 nnz per column) solved in
+    one persistent launch to rel KKT eps, against the same LPs solved one by
+    one with the single-LP path (a sample) and the oracle (a sample, one LP
+    per host thread)."""
+    import lpgen
+    import oracle
+    from concurrent.futures import ProcessPoolExecutor
+    oracle.build()
+    ms = lpgen.batch_sizes(0, 4096)[:count]
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t = time.time()
+    with ProcessPoolExecutor(workers) as ex:
+        probs = list(ex.map(_gen_batch_lp, [(0, i, int(ms[i])) for i in range(count)], chunksize=16))
+    log(f"batch: generated {count} LPs in {time.time() - t:.1f}s ({workers} processes)")
+    t = time.time()
+    h = P.pdlp_create_batch(probs, stream=stream, eps_rel=eps, max_iter=200000, time_limit_s=600.0)
+    create_s = time.time() - t
+    lanes, grid = P.pdlp_batch_schedule(h)
+    P.pdlp_solve_batch(h)          # first solve: code load, caches
+    t = time.perf_counter()
+    P.pdlp_solve_batch(h)
+    solve_s = time.perf_counter() - t
+    x, y, rc, infos = P.pdlp_get_solution_batch(h, -1)
+    its = np.array([i["iterations"] for i in infos], np.int64)
+    att = np.array([i["attempts"] for i in infos], np.int64)
+    ev = np.array([i["evaluations"] for i in infos], np.int64)
+    status = [i["status_name"] for i in infos]
+    nnz = np.array([p.nnz for p in probs], np.float64)
+    mm = np.array([p.m for p in probs], np.float64)
+    nn = np.array([p.n for p in probs], np.float64)
+    # algorithmic bytes: each attempt streams K~' and K~ once (values + column
+    # indices + row pointers), reads/writes the step vectors; each evaluation
+    # runs three products with two gathered vectors plus the vector passes
+    att_bytes = att * (2 * nnz * 12 + 4 * (mm + nn) + 72 * nn + 69 * mm)
+    ev_bytes = ev * (3 * nnz * 12 + 2 * 4 * (mm + nn) + 16 * (mm + nn) + 120 * nn + 100 * mm)
+    gbps = float((att_bytes.sum() + ev_bytes.sum()) / solve_s / 1e9)
+    # the same LPs one by one through the single-LP path (sample)
+    t = time.perf_counter()
+    single_its = []
+    for k in range(sample):
+        hs = P.pdlp_create(probs[k], stream=stream, eps_rel=eps, max_iter=200000, time_limit_s=60.0)
+        P.pdlp_solve(hs)
+        single_its.append(P.pdlp_get_solution(hs)[3]["iterations"])
+        P.pdlp_destroy(hs)
+    single_s = (time.perf_counter() - t) / sample
+    # oracle on a sample, one LP per host thread
+    t = time.time()
+    with ProcessPoolExecutor(workers) as ex:
+        orc = list(ex.map(_oracle_one, [(probs[k], eps) for k in range(sample)]))
+    orc_wall = time.time() - t
+    obj_err = max(abs(infos[k]["primal_obj"] - orc[k][0]) / (1 + abs(orc[k][0])) for k in range(sample))
+    recheck = max(oracle.evaluate(probs[k], x[h.col_off[k]:h.col_off[k + 1]],
+                                  y[h.row_off[k]:h.row_off[k + 1]])["rel_kkt"] for k in range(sample))
+    P.pdlp_destroy(h)
+    u, cnt = np.unique(lanes, axis=0, return_counts=True)
+    return {"workload": f"{count} random LPs, m ~ U{{50..2000}} (half EQ, half LE), n = 2m, 8 nnz per column, "
+                        f"rel KKT {eps:g}, FP64",
+            "lps": count, "nnz_total": int(nnz.sum()), "create_s": round(create_s, 3),
+            "solve_s": round(solve_s, 4), "lps_per_s": round(count / solve_s, 1),
+            "optimal": status.count("OPTIMAL"), "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+            "lp_iters_per_s": round(float(its.sum() / solve_s), 1),
+            "algorithmic_GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBPS, 4),
+            "schedule": {"grid": int(grid), "lanes_k_kt_counts": [[int(a), int(b), int(c)]
+                                                                 for (a, b), c in zip(u.tolist(), cnt.tolist())]},
+            "single_lp_path": {"sample": sample, "s_per_lp": round(single_s, 5),
+                               "lps_per_s": round(1.0 / single_s, 1),
+                               "batch_speedup": round((count / solve_s) * single_s, 2)},
+            "cpu_baseline": {"kind": "oracle", "sample": sample, "cores": workers,
+                             "lps_per_s": round(sample / orc_wall, 2),
+                       "obj_rel_err_max_vs_gpu": obj_err, "gpu_rel_kkt_cpu_recheck_max": recheck}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +169,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--profile-attempts", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-LP section")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-sample", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver does not shard "
@@ -167,6 +256,11 @@ def main():
             log(f"time to 1e-4 ({name}): {ttt[name]}")
             P.pdlp_destroy(h)
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_section(P, stream, args.batch_count, 1e-6, args.batch_sample)
+        log(f"batch: {batch}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob, args.cpu_iters)
@@ -179,7 +273,7 @@ def main():
             "config": {"workload": "skewed random LP m=1e6 (half EQ, half LE) n=2e6 nnz=2e7, row lengths "
                                    "power-law capped at 10,000, FP64 matrix",
                        "m": prob.m, "n": prob.n, "nnz": prob.nnz, "eval_period": 64},
-            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt}
+            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt, "batch": batch}
     print(json.dumps(line), flush=True)
 
 

@@ -381,3 +381,43 @@ def mixed_lp(seed: int = 0, m: int = 40, n: int = 60, density: float = 0.15,
     c = _rmatvec(row_ptr, col_idx, val, y, m, n) + lam
     return Problem(m, n, row_ptr, col_idx, val, c, b, l, u, row_type,
                    name or f"mixed_lp(seed={seed},m={m},n={n})", x, y, lam)
+
+
+def transport_family_lp(seed: int, idx: int, S: int = 100, T: int = 100) -> Problem:
+    """LP number idx of a family of S x T transportation LPs (layout as in
+    `transportation`).  The family (seed) fixes base costs C ~ U(0,1)^{SxT}
+    and base demands d ~ U(1,10)^T; LP idx draws (seed, idx): c = C + N(0,
+    0.05^2), supplies s ~ U(1,10)^S, demands d * U(0.8, 1.2) rescaled so
+    that sum d = sum s."""
+    base = np.random.Generator(np.random.PCG64([seed, 0xFA11]))
+    C = base.random(S * T)
+    d0 = base.uniform(1.0, 10.0, T)
+    rng = np.random.Generator(np.random.PCG64([seed, 0xFA11, idx]))
+    c = C + 0.05 * rng.standard_normal(S * T)
+    s = rng.uniform(1.0, 10.0, S)
+    d = d0 * rng.uniform(0.8, 1.2, T)
+    d *= s.sum() / d.sum()
+    p = transportation(0, S, T)
+    return Problem(p.m, p.n, p.row_ptr, p.col_idx, p.val, c, np.concatenate([s, d]), p.l, p.u, p.row_type,
+                   f"transport_family(seed={seed},idx={idx},{S}x{T})")
+
+
+def gnn_init(seed: int, shapes) -> np.ndarray:
+    """Initial weights of a network with the given parameter shapes (a list of
+    (name, shape)), flat and representable in FP32: matrices U(-a, a) with
+    a = sqrt(6 / (fan_in + fan_out)), vectors that multiply hidden states
+    (2 or more entries) U(-a, a) with a = sqrt(3 / len), biases and scalars 0."""
+    rng = np.random.Generator(np.random.PCG64([seed, 0x6E11]))
+    out = []
+    for name, shape in shapes:
+        shape = tuple(shape)
+        if len(shape) == 2:
+            a = np.sqrt(6.0 / (shape[0] + shape[1]))
+            w = rng.uniform(-a, a, shape)
+        elif name.startswith("w_"):
+            a = np.sqrt(3.0 / shape[0])
+            w = rng.uniform(-a, a, shape)
+        else:
+            w = np.zeros(shape)
+        out.append(w.astype(np.float32).astype(np.float64).reshape(-1))
+    return np.concatenate(out)
