@@ -97,9 +97,10 @@ typedef struct {
                                  that adds each row's panel sums; 2: row blocks with contiguous
                                  block ranges per XCD.  The layout changes the order of floating-point
                                  sums; fix it for bitwise reproducibility across handles */
-  int32_t batch_lanes;        /* batch handles: 0 = lanes per row chosen per LP class by timing
-                                 capped solves at pdlp_create_batch (default); 1..64 (a power of
-                                 two) = that many lanes for every row */
+  int32_t batch_lanes;        /* batch handles: how each LP's rows are swept.  0 = chosen per LP
+                                 class by timing capped solves at pdlp_create_batch (default);
+                                 -1 = LDS-tiled row blocks for every LP; 1..64 (a power of two) =
+                                 that many lanes per row for every row */
   int32_t batch_grid;         /* batch handles: workgroups of the persistent launch, 0 = chosen by
                                  timing (default) */
 } pdlp_options;
@@ -117,7 +118,7 @@ typedef struct {
   double setup_s;             /* pdlp_create: upload, transpose, scaling, layout choice */
   double solve_s;             /* pdlp_solve wall time */
   int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout); for an LP
-                                   of a batch: its lanes per row of K and of K' */
+                                   of a batch: its sweeps of K and K' (see pdlp_batch_schedule) */
 } pdlp_info;
 
 /* Scaled-space state of the current iterate (for parity checks and resume). */
@@ -234,8 +235,9 @@ int pdlp_solve_batch(pdlp_handle* h);
 int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, double* y, double* reduced_cost,
                             pdlp_info* info);
 
-/* Schedule of the persistent launch: lanes[2*count] (lanes per row of K and
- * of K' for each LP) and the number of workgroups; NULL to skip either. */
+/* Schedule of the persistent launch: lanes[2*count] (the sweep of each LP's
+ * rows of K and of K': 0 = LDS-tiled row blocks of up to 2048 nonzeros, L > 0
+ * = L lanes per row) and the number of workgroups; NULL to skip either. */
 int pdlp_batch_schedule(pdlp_handle* h, int32_t* lanes, int32_t* grid);
 
 /* Last error message of h, or of the last failed pdlp_create on this thread

@@ -863,10 +863,29 @@ __device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const 
   }
 }
 
-__device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red) {
+// One pass of an op over an LP's rows: the LDS-tiled row blocks [b0, b1)
+// when L = 0 (the single-LP sweep), else rows [rb, re) walked with L lanes per row.
+template <int NV, typename VT, class Op>
+__device__ __forceinline__ void sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                      const VT* __restrict__ v, const RowBlock* __restrict__ blocks, int b0, int b1,
+                                      int rb, int re, int L, const Op& op, double* acc, double* lds, double* red) {
+  if (L == 0) {
+    for (int j = b0; j < b1; ++j) {
+      spmv_block<NV, VT>(rp, ci, v, blocks[j], lds, red, [&](int c, double* g) { op.gather(c, g); },
+                         [&](int r, const double* s) { op.epi(r, s, acc); });
+      __syncthreads();
+    }
+  } else {
+    lane_rows<NV, VT>(rp, ci, v, rb, re, L, op, acc);
+  }
+}
+
+__device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red,
+                                double* lds) {
   const int r0 = bp.row_off[b], r1 = bp.row_off[b + 1];
   const int c0 = bp.col_off[b], c1 = bp.col_off[b + 1];
   const int LK = bp.lanes[2 * b], LT = bp.lanes[2 * b + 1];
+  const int k0 = bp.bk_off[b], k1 = bp.bk_off[b + 1], t0 = bp.bt_off[b], t1 = bp.bt_off[b + 1];
   const Trace tr = b == bp.trace_lp ? p.tr : Trace{};
   const double qn0 = sqrt(bp.norms[4 * b]), cn0 = sqrt(bp.norms[4 * b + 1]);
   const bool f32 = p.use_f32 != 0;
@@ -946,12 +965,12 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
       __syncthreads();
       {
         const EvalRowsOp op(p, S);
-        lane_rows<2, double>(p.K.rp, p.K.ci, p.K.v, r0, r1, LK, op, acc + 4);
+        sweep<2, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 4, lds, red);
       }
       __syncthreads();
       {
         const EvalColsOp op(p, S);
-        lane_rows<2, double>(p.KT.rp, p.KT.ci, p.KT.v, c0, c1, LT, op, acc + 12);
+        sweep<2, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc + 12, lds, red);
       }
       block_sum<18>(acc, red);
       if (threadIdx.x == 0) eval_decision(S, p, tr, acc, qn0, cn0);
@@ -968,8 +987,8 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         __syncthreads();
         const RestartYOp op(p, S);
         double dummy[1];
-        if (f32) lane_rows<1, float>(p.K.rp, p.K.ci, p.K.vf, r0, r1, LK, op, dummy);
-        else lane_rows<1, double>(p.K.rp, p.K.ci, p.K.v, r0, r1, LK, op, dummy);
+        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
+        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
         __syncthreads();
         if (threadIdx.x == 0) S->restart_flag = 0;
       }
@@ -978,14 +997,14 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
       double acc[3] = {0.0, 0.0, 0.0};
       {
         const PrimalOp op(p, S);
-        if (f32) lane_rows<1, float>(p.KT.rp, p.KT.ci, p.KT.vf, c0, c1, LT, op, acc);
-        else lane_rows<1, double>(p.KT.rp, p.KT.ci, p.KT.v, c0, c1, LT, op, acc);
+        if (f32) sweep<1, float>(p.KT.rp, p.KT.ci, p.KT.vf, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+        else sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
       }
       __syncthreads();
       {
         const DualOp op(p, S);
-        if (f32) lane_rows<1, float>(p.K.rp, p.K.ci, p.K.vf, r0, r1, LK, op, acc + 1);
-        else lane_rows<1, double>(p.K.rp, p.K.ci, p.K.v, r0, r1, LK, op, acc + 1);
+        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
+        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
       }
       block_sum<3>(acc, red);
       if (threadIdx.x == 0) {
@@ -1011,7 +1030,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   {
     const OutputOp op(p, S);
     double dummy[1];
-    lane_rows<1, double>(p.KT.rp, p.KT.ci, p.KT.v, c0, c1, LT, op, dummy);
+    sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, dummy, lds, red);
     const int cur = S->cur, ra = S->ret_avg;
     const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
     for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
@@ -1028,6 +1047,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
 __global__ __launch_bounds__(kBlock) void k_batch(Params p, BatchParams bp) {
   __shared__ DevState S;
   __shared__ double red[18 * (kBlock / 64)];
+  __shared__ double lds[2 * kTile];
   __shared__ int slot;
   for (;;) {
     if (threadIdx.x == 0) slot = (int)atomicAdd(bp.queue, 1u);
@@ -1035,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(Params p, BatchParams bp) {
     const int q = slot;
     __syncthreads();
     if (q >= bp.count) break;
-    batch_solve_one(p, bp, bp.order[q], &S, red);
+    batch_solve_one(p, bp, bp.order[q], &S, red, lds);
   }
 }
 

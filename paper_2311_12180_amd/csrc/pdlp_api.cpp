@@ -223,6 +223,8 @@ struct pdlp_handle {
   int32_t grid = 0;
   int32_t *row_off = nullptr, *col_off = nullptr, *order = nullptr;
   uint8_t* lanes = nullptr;
+  RowBlock *bk = nullptr, *bt = nullptr;
+  int32_t *bk_off = nullptr, *bt_off = nullptr;
   int8_t* warm = nullptr;
   double *norms = nullptr, *kmax = nullptr, *omega_warm = nullptr;
   DevState* bst = nullptr;
@@ -309,8 +311,8 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
   if (o.spmv_layout < -1 || o.spmv_layout > 2) return why = "spmv_layout must be -1, 0, 1 or 2", -1;
-  if (o.batch_lanes < 0 || o.batch_lanes > 64 || (o.batch_lanes & (o.batch_lanes - 1)))
-    return why = "batch_lanes must be 0 or a power of two up to 64", -1;
+  if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
+    return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
   return 0;
 }
@@ -490,15 +492,6 @@ static void choose_layouts(pdlp_handle* h) {
   }
 }
 
-// One LP fetched to the host (from host or device arrays) and validated.
-struct HostLP {
-  int32_t m = 0, n = 0;
-  int64_t nnz = 0;
-  std::vector<int32_t> rp, ci;
-  std::vector<double> v, c, b, l, u;
-  std::vector<int8_t> rt;
-};
-
 static int load_problem(const pdlp_problem* p, void* hip_stream, HostLP& H, std::string& why) {
   if (p->m < 0 || p->n < 1 || p->nnz < 0 || p->nnz >= (int64_t)1 << 31)
     return why = "sizes must satisfy m >= 0, n >= 1, 0 <= nnz < 2^31", PDLP_ERR_ARG;
@@ -530,6 +523,51 @@ static int load_problem(const pdlp_problem* p, void* hip_stream, HostLP& H, std:
   if (validate(H.m, H.n, H.nnz, H.rp.data(), H.ci.data(), H.v.data(), H.c.data(), H.b.data(), H.l.data(),
                H.u.data(), H.rt.data(), why))
     return PDLP_ERR_DATA;
+  return PDLP_OK;
+}
+
+// Pack LPs block-diagonally on the host, each one validated on its own (the
+// message names the first bad LP).
+int pdlp::pack_problems(const pdlp_problem* ps, int32_t count, void* hip_stream, HostLP& H,
+                        std::vector<int32_t>& row_off, std::vector<int32_t>& col_off, std::vector<int64_t>& nnz_b,
+                        std::string& why) {
+  row_off.assign(1, 0);
+  col_off.assign(1, 0);
+  nnz_b.clear();
+  int64_t M = 0, N = 0, NZ = 0;
+  H = HostLP{};
+  H.rp.push_back(0);
+  for (int32_t k = 0; k < count; ++k) {
+    HostLP L;
+    if (int rc = load_problem(&ps[k], hip_stream, L, why)) {
+      why = "LP " + std::to_string(k) + ": " + why;
+      return rc;
+    }
+    if (M + L.m >= ((int64_t)1 << 31) || N + L.n >= ((int64_t)1 << 31) || NZ + L.nnz >= ((int64_t)1 << 31)) {
+      why = "the packed LPs need total rows, columns and nonzeros below 2^31";
+      return PDLP_ERR_ARG;
+    }
+    for (int32_t r = 0; r < L.m; ++r) H.rp.push_back((int32_t)(NZ + L.rp[(size_t)r + 1]));
+    for (int64_t e = 0; e < L.nnz; ++e) H.ci.push_back((int32_t)(N + L.ci[(size_t)e]));
+    H.v.insert(H.v.end(), L.v.begin(), L.v.begin() + L.nnz);
+    H.c.insert(H.c.end(), L.c.begin(), L.c.begin() + L.n);
+    H.l.insert(H.l.end(), L.l.begin(), L.l.begin() + L.n);
+    H.u.insert(H.u.end(), L.u.begin(), L.u.begin() + L.n);
+    H.b.insert(H.b.end(), L.b.begin(), L.b.begin() + L.m);
+    H.rt.insert(H.rt.end(), L.rt.begin(), L.rt.begin() + L.m);
+    M += L.m;
+    N += L.n;
+    NZ += L.nnz;
+    row_off.push_back((int32_t)M);
+    col_off.push_back((int32_t)N);
+    nnz_b.push_back(L.nnz);
+  }
+  H.m = (int32_t)M;
+  H.n = (int32_t)N;
+  H.nnz = NZ;
+  for (auto* vec : {&H.v, &H.c, &H.l, &H.u, &H.b}) if (vec->empty()) vec->push_back(0.0);
+  if (H.ci.empty()) H.ci.push_back(0);
+  if (H.rt.empty()) H.rt.push_back(0);
   return PDLP_OK;
 }
 
@@ -1079,11 +1117,6 @@ int length_class(double avg) {
   return c;
 }
 int size_class(int32_t rows) { return rows < 256 ? 0 : (rows < 1024 ? 1 : 2); }
-uint8_t default_lanes(double avg) {
-  int L = 1;
-  while (L < 64 && L < avg) L <<= 1;
-  return (uint8_t)L;
-}
 
 }  // namespace
 
@@ -1096,6 +1129,10 @@ static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter,
   bp.row_off = h->row_off;
   bp.col_off = h->col_off;
   bp.lanes = h->lanes;
+  bp.bk = h->bk;
+  bp.bk_off = h->bk_off;
+  bp.bt = h->bt;
+  bp.bt_off = h->bt_off;
   bp.st = h->bst;
   bp.norms = h->norms;
   bp.kmax = h->kmax;
@@ -1157,8 +1194,8 @@ static void tune_batch(pdlp_handle* h) {
     const double ak = mb > 0 ? nz / mb : 0.0, at = nz / nb;
     cls[2 * b] = 16 * length_class(ak) + size_class(mb);
     cls[2 * b + 1] = 16 * length_class(at) + size_class(nb);
-    h->lanes_h[2 * b] = opt.batch_lanes ? (uint8_t)opt.batch_lanes : default_lanes(ak);
-    h->lanes_h[2 * b + 1] = opt.batch_lanes ? (uint8_t)opt.batch_lanes : default_lanes(at);
+    h->lanes_h[2 * b] = opt.batch_lanes > 0 ? (uint8_t)opt.batch_lanes : 0;
+    h->lanes_h[2 * b + 1] = opt.batch_lanes > 0 ? (uint8_t)opt.batch_lanes : 0;
   }
   hipDeviceProp_t prop;
   int dev = 0;
@@ -1171,11 +1208,12 @@ static void tune_batch(pdlp_handle* h) {
     check(hipMemcpy(h->lanes, h->lanes_h.data(), h->lanes_h.size(), hipMemcpyHostToDevice), "upload lanes");
   };
   upload();
-  if (opt.batch_lanes && opt.batch_grid) return;
+  const bool tune_lanes = opt.batch_lanes == 0;
+  if (!tune_lanes && opt.batch_grid) return;
   const int64_t iters = 64;
   (void)time_batch(h, iters, 1);  // first launch: code object load
   double best = time_batch(h, iters, 2);
-  if (!opt.batch_lanes) {
+  if (tune_lanes) {
     for (int side = 0; side < 2; ++side) {
       std::vector<int> classes;
       for (int32_t b = 0; b < cnt; ++b) classes.push_back(cls[2 * b + side]);
@@ -1186,7 +1224,7 @@ static void tune_batch(pdlp_handle* h) {
         for (int32_t b = 0; b < cnt; ++b)
           if (cls[2 * b + side] == c) cur = h->lanes_h[2 * b + side];
         const uint8_t start = cur;
-        for (int L = 1; L <= 64; L <<= 1) {
+        for (int L : {0, 1, 2, 4, 8, 16, 32, 64}) {
           if (L == start) continue;
           for (int32_t b = 0; b < cnt; ++b)
             if (cls[2 * b + side] == c) h->lanes_h[2 * b + side] = (uint8_t)L;
@@ -1229,39 +1267,10 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
   std::string why;
   if (check_options(opt, why)) return fail(nullptr, PDLP_ERR_ARG, why);
   const double t0 = now_s();
-  // pack the LPs block-diagonally on the host (each one validated on its own)
   HostLP H;
-  std::vector<int32_t> row_off(1, 0), col_off(1, 0);
+  std::vector<int32_t> row_off, col_off;
   std::vector<int64_t> nnz_b;
-  int64_t M = 0, N = 0, NZ = 0;
-  for (int32_t k = 0; k < count; ++k) {
-    HostLP L;
-    if (int rc = load_problem(&ps[k], hip_stream, L, why))
-      return fail(nullptr, rc, "LP " + std::to_string(k) + ": " + why);
-    if (M + L.m >= ((int64_t)1 << 31) || N + L.n >= ((int64_t)1 << 31) || NZ + L.nnz >= ((int64_t)1 << 31))
-      return fail(nullptr, PDLP_ERR_ARG, "the packed batch needs total rows, columns and nonzeros below 2^31");
-    if (k == 0) H.rp.push_back(0);
-    for (int32_t r = 0; r < L.m; ++r) H.rp.push_back((int32_t)(NZ + L.rp[(size_t)r + 1]));
-    for (int64_t e = 0; e < L.nnz; ++e) H.ci.push_back((int32_t)(N + L.ci[(size_t)e]));
-    H.v.insert(H.v.end(), L.v.begin(), L.v.begin() + L.nnz);
-    H.c.insert(H.c.end(), L.c.begin(), L.c.begin() + L.n);
-    H.l.insert(H.l.end(), L.l.begin(), L.l.begin() + L.n);
-    H.u.insert(H.u.end(), L.u.begin(), L.u.begin() + L.n);
-    H.b.insert(H.b.end(), L.b.begin(), L.b.begin() + L.m);
-    H.rt.insert(H.rt.end(), L.rt.begin(), L.rt.begin() + L.m);
-    M += L.m;
-    N += L.n;
-    NZ += L.nnz;
-    row_off.push_back((int32_t)M);
-    col_off.push_back((int32_t)N);
-    nnz_b.push_back(L.nnz);
-  }
-  H.m = (int32_t)M;
-  H.n = (int32_t)N;
-  H.nnz = NZ;
-  for (auto* vec : {&H.v, &H.c, &H.l, &H.u, &H.b}) if (vec->empty()) vec->push_back(0.0);
-  if (H.ci.empty()) H.ci.push_back(0);
-  if (H.rt.empty()) H.rt.push_back(0);
+  if (int rc = pdlp::pack_problems(ps, count, hip_stream, H, row_off, col_off, nnz_b, why)) return fail(nullptr, rc, why);
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, PDLP_ERR_HIP, "no HIP device");
@@ -1307,6 +1316,27 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     h->queue = h->dalloc<uint32_t>(1);
     h->t0 = h->dalloc<uint64_t>(1);
     h->lanes = h->dalloc<uint8_t>(2 * (size_t)count);
+    // LDS-tiled row blocks of every LP's rows of K~ and of K~'
+    {
+      std::vector<int32_t> hrpT((size_t)h->n + 1);
+      check(hipMemcpy(hrpT.data(), h->rpT, ((size_t)h->n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
+      std::vector<RowBlock> bk, bt;
+      std::vector<int32_t> bko(1, 0), bto(1, 0);
+      for (int32_t k = 0; k < count; ++k) {
+        for (const RowBlock& r : partition_rows(H.rp.data(), row_off[(size_t)k], row_off[(size_t)k + 1])) bk.push_back(r);
+        for (const RowBlock& r : partition_rows(hrpT.data(), col_off[(size_t)k], col_off[(size_t)k + 1])) bt.push_back(r);
+        bko.push_back((int32_t)bk.size());
+        bto.push_back((int32_t)bt.size());
+      }
+      h->bk = h->dalloc<RowBlock>(bk.size());
+      h->bt = h->dalloc<RowBlock>(bt.size());
+      h->bk_off = h->dalloc<int32_t>(bko.size());
+      h->bt_off = h->dalloc<int32_t>(bto.size());
+      if (!bk.empty()) check(hipMemcpy(h->bk, bk.data(), bk.size() * sizeof(RowBlock), kind), "upload blocks");
+      if (!bt.empty()) check(hipMemcpy(h->bt, bt.data(), bt.size() * sizeof(RowBlock), kind), "upload blocks");
+      check(hipMemcpy(h->bk_off, bko.data(), bko.size() * 4, kind), "upload block offsets");
+      check(hipMemcpy(h->bt_off, bto.data(), bto.size() * 4, kind), "upload block offsets");
+    }
     // queue order: most nonzeros first, so that the long solves start early
     std::vector<int32_t> ord((size_t)count);
     for (int32_t k = 0; k < count; ++k) ord[(size_t)k] = k;

@@ -3,6 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
+#include "pdlp.h"
+
 namespace pdlp {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
@@ -137,7 +142,11 @@ struct BatchParams {
   const int32_t* order;     // [count] queue order (LP indices)
   const int32_t* row_off;   // [nlp+1]
   const int32_t* col_off;   // [nlp+1]
-  const uint8_t* lanes;     // [2*nlp] lanes per row for K~ rows, for K~' rows
+  const uint8_t* lanes;     // [2*nlp] K~ rows, K~' rows: 0 = LDS-tiled row blocks, else lanes per row
+  const RowBlock* bk;       // row blocks of every LP's rows of K~ (LP b: [bk_off[b], bk_off[b+1]))
+  const int32_t* bk_off;
+  const RowBlock* bt;       // row blocks of every LP's rows of K~'
+  const int32_t* bt_off;
   DevState* st;             // [nlp]
   const double* norms;      // [4*nlp] squared norms: ||q||, ||c|| (unscaled), ||c~||, ||q~|| (scaled)
   const double* kmax;       // [nlp] max |K~_ij|
@@ -153,5 +162,23 @@ struct BatchParams {
   int64_t max_iter;
   double eps_zero;
 };
+
+// One LP, or LPs packed block-diagonally, on the host (user orientation).
+struct HostLP {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v, c, b, l, u;
+  std::vector<int8_t> rt;
+};
+
+// Validate `count` LPs (host or device arrays) and pack them block-diagonally;
+// returns PDLP_OK or an error code with the reason (naming the first bad LP).
+int pack_problems(const pdlp_problem* ps, int32_t count, void* hip_stream, HostLP& H, std::vector<int32_t>& row_off,
+                  std::vector<int32_t>& col_off, std::vector<int64_t>& nnz_b, std::string& why);
+
+hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
+                           int32_t* rpT, int32_t* ciT, double* vT, int32_t* rowidT, int32_t* perm_out,
+                           hipStream_t s);
 
 }  // namespace pdlp

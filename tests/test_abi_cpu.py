@@ -19,8 +19,8 @@ def P():
     return pdlp
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "pdlp.h")).read()
+def declared_functions(header="pdlp.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(pdlp_[a-z_]+)\s*\(", text)))
 
@@ -32,6 +32,37 @@ def test_every_declared_symbol_is_exported(P):
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTED) == names
+
+
+def test_network_symbols_are_exported(P):
+    from paper_2311_12180_amd import gnn
+    names = declared_functions("pdlp_gnn.h")
+    assert sorted(gnn.EXPORTED) == names
+    lib = gnn.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_network_rejects_bad_input(P):
+    from paper_2311_12180_amd import gnn
+    good = lpgen.mixed_lp(0, m=10, n=12)
+    bad = copy.deepcopy(good); bad.b[3] = np.inf
+    with pytest.raises(P.PdlpError) as e:
+        gnn.pdlp_gnn_create([good, bad])
+    assert e.value.code == P.PDLP_ERR_DATA and "LP 1: b[3]" in str(e.value)
+    x = np.zeros(24); y = np.zeros(20)
+    with pytest.raises(P.PdlpError) as e:
+        gnn.pdlp_gnn_create([good, good], x, y, np.array([1.0, -1.0]))
+    assert e.value.code == P.PDLP_ERR_DATA and "omega_star" in str(e.value)
+    with pytest.raises(P.PdlpError) as e:
+        gnn.pdlp_gnn_create([good], x[:12], None, np.array([1.0]))
+    assert e.value.code == P.PDLP_ERR_ARG
+    lib = gnn.lib()
+    assert lib.pdlp_gnn_create(None, 1, None, None, None, None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_gnn_set_params(None, None) == P.PDLP_ERR_ARG
+    assert lib.pdlp_gnn_predict(None, 0, 1, None, None, None) == P.PDLP_ERR_ARG
+    lib.pdlp_gnn_destroy(None)
+    assert isinstance(gnn.pdlp_gnn_last_error(None), str)
 
 
 def test_default_options(P):

@@ -40,6 +40,27 @@ def _box_lp(seed=0, n=40):
                          np.zeros(0, np.int8), "box", None, None, None)
 
 
+def _long_rows_lp(seed=0):
+    """An LP with rows longer than one LDS tile (2048 nonzeros), empty rows and
+    a dense column (a whole-workgroup row sweep inside the batched kernel)."""
+    rng = np.random.default_rng(seed)
+    m, n = 40, 5000
+    rows, cols = [], []
+    for i in range(m):
+        L = 4500 if i == 7 else (2100 if i == 20 else (0 if i % 11 == 0 else int(rng.integers(1, 20))))
+        rows += [i] * L
+        cols += list(rng.choice(n - 1, L, replace=False))
+    rows += list(range(m)); cols += [n - 1] * m
+    rows, cols = np.array(rows), np.array(cols)
+    _, keep = np.unique(rows * n + cols, return_index=True)
+    rows, cols = rows[keep], cols[keep]
+    row_ptr, col_idx, val = lpgen._csr_from_coo(m, n, rows, cols, rng.standard_normal(len(rows)))
+    rt = rng.integers(0, 3, m).astype(np.int8)
+    l = np.zeros(n); u = np.full(n, 3.0)
+    b, c, xs, ys, lam = lpgen._certify(rng, m, n, row_ptr, col_idx, val, rt, l, u)
+    return lpgen.Problem(m, n, row_ptr, col_idx, val, c, b, l, u, rt, "long_rows_batch", xs, ys, lam)
+
+
 def _small_batch(count=24, seed=3, m_lo=50, m_hi=300):
     ms = lpgen.batch_sizes(seed, count, m_lo, m_hi)
     return [lpgen.batch_lp(seed, i, int(ms[i])) for i in range(count)]
@@ -119,9 +140,10 @@ def test_first_100_steps_match_oracle(P, orc):
 @pytest.mark.parametrize("eps", [1e-4, 1e-8])
 def test_end_to_end_matches_oracle(P, orc, eps):
     """Objective within max(1e-6, 10 x the oracle's own spread under
-    renumbering) of the oracle's: at rel KKT 1e-4 the stopping point, and
-    with it the objective, moves by up to ~1e-4 relative with the summation
-    order alone on some of these LPs."""
+    renumbering) of the oracle's when the run followed the oracle's decisions;
+    at rel KKT 1e-4 the stopping point, and with it the objective, moves by up
+    to ~1e-4 relative with the summation order alone on some of these LPs, so
+    a run whose decisions differ is held to 2 eps."""
     probs = _mixed_batch() + _small_batch(10, seed=4)
     opts = dict(eps_rel=eps, max_iter=200000)
     h = P.pdlp_create_batch(probs, time_limit_s=120.0, **opts)
@@ -132,7 +154,10 @@ def test_end_to_end_matches_oracle(P, orc, eps):
         assert I["status_name"] == "OPTIMAL" and r.status == "OPTIMAL", (k, p.name, I["status_name"])
         assert I["rel_kkt"] <= eps
         obj = I["primal_obj"]
-        tol = max(1e-6, 10 * so)
+        same_path = I["attempts"] == r.info["attempts"] and I["iterations"] == r.info["iterations"]
+        # on the oracle's path: its own rounding spread; off it (a decision went
+        # the other way), two eps-optimal stopping points are up to ~2 eps apart
+        tol = max(1e-6, 10 * so) if same_path else max(1e-6, 10 * so, 2 * eps)
         assert abs(obj - r.info["primal_obj"]) <= tol * (1 + abs(r.info["primal_obj"])), (k, p.name, tol)
         e = orc.evaluate(p, x, y)
         assert e["rel_kkt"] <= eps * (1 + 1e-6), (k, p.name, e["rel_kkt"])
@@ -144,20 +169,24 @@ def test_end_to_end_matches_oracle(P, orc, eps):
                 assert abs(obj - ref) <= 1e-6 * (1 + abs(ref)), (k, p.name)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 8, 64])
+@pytest.mark.parametrize("lanes", [-1, 1, 2, 8, 64])
 def test_any_lanes_per_row(P, orc, lanes):
-    """Every lanes-per-row choice of the schedule computes the same method."""
-    probs = _small_batch(6, seed=7) + [lpgen.mixed_lp(2)]
+    """Every sweep of the schedule (LDS-tiled row blocks, or 1..64 lanes per
+    row) computes the same method."""
+    probs = _small_batch(6, seed=7) + [lpgen.mixed_lp(2), _long_rows_lp()]
     opts = dict(eps_rel=0.0, max_iter=100)
     h = P.pdlp_create_batch(probs, batch_lanes=lanes, batch_grid=3, time_limit_s=60.0, **opts)
     sched, grid = P.pdlp_batch_schedule(h)
-    assert grid == 3 and (sched == lanes).all()
+    assert grid == 3 and (sched == max(lanes, 0)).all()
     P.pdlp_solve_batch(h)
     for k, p in enumerate(probs):
         x, y, _, I = P.pdlp_get_solution_batch(h, k)
-        r = orc.solve(p, **opts)
+        r, sx, _, _, stable = _oracle_spread(orc, p, opts)
+        if not stable:
+            continue
+        tol = max(1e-10, 100 * sx)
         assert I["attempts"] == r.info["attempts"], k
-        assert _rel_inf(x, r.x) <= 1e-10 and _rel_inf(y, r.y) <= 1e-10, k
+        assert _rel_inf(x, r.x) <= tol and _rel_inf(y, r.y) <= tol, (k, tol)
 
 
 def test_member_result_independent_of_batch(P):
@@ -186,7 +215,7 @@ def test_schedule_autotuned(P):
     h = P.pdlp_create_batch(probs, eps_rel=1e-4)
     sched, grid = P.pdlp_batch_schedule(h)
     assert sched.shape == (40, 2) and grid >= 1
-    assert set(np.unique(sched)) <= {1, 2, 4, 8, 16, 32, 64}
+    assert set(np.unique(sched)) <= {0, 1, 2, 4, 8, 16, 32, 64}
     P.pdlp_solve_batch(h)
     infos = P.pdlp_get_solution_batch(h, -1)[3]
     assert all(i["status_name"] == "OPTIMAL" for i in infos)
