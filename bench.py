@@ -35,23 +35,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+STEP_SOURCES = ("pdlp_dev.h", "pdlp_ops.h", "kernels.hip")
+
+
+def step_kernels_hash() -> str:
+    """sha256 prefix over the sources the single-LP step kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2311_12180_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _traffic_from_profiles(kernel: str):
-    """HBM-side bytes per launch of `kernel` from the committed rocprofv3
-    counter summary (lines 'kernel <name> fetch_bytes <F> write_bytes <W>'),
-    or None when there is none or it was taken from a different kernel source
-    (the summary records the sha256 prefix of kernels.hip)."""
+    """Bytes between L2 and the memory fabric per launch of step `kernel`
+    (primal_step / dual_step) from the committed rocprofv3 counter summary
+    (lines 'step <name> fetch_bytes <F> write_bytes <W>'), or None when there is
+    none or it was taken from a different kernel source (the summary records
+    the sha256 prefix of kernels.hip)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "step_kernels_skewed_1e6x2e6_traffic.txt")
     if not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_2311_12180_amd", "csrc", "kernels.hip")
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    cur = step_kernels_hash()
     text = open(path).read()
     if f"sha256[:16] = {cur}" not in text:
         return None
     for line in text.splitlines():
         parts = line.split()
-        if len(parts) >= 6 and parts[0] == "kernel" and parts[1] == kernel:
+        if len(parts) >= 6 and parts[0] == "step" and parts[1] == kernel:
             return float(parts[3]) + float(parts[5])
     return None
 
@@ -159,6 +171,87 @@ def batch_section(P, stream, count: int, eps: float, sample: int):
                        "obj_rel_err_max_vs_gpu": obj_err, "gpu_rel_kkt_cpu_recheck_max": recheck}}
 
 
+def _gen_family_lp(args):
+    import lpgen
+    seed, i = args
+    return lpgen.transport_family_lp(seed, i, 100, 100)
+
+
+def warmstart_section(P, stream, n_train: int, n_test: int, epochs: int, batch: int, lr: float, eps: float):
+    """Learned warm start on a family of 100 x 100 transportation LPs: cold
+    batched solves give the targets, the network trains on the GPU, and the
+    held-out LPs are solved warm (cold fallback) and cold to rel KKT eps."""
+    import lpgen
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2311_12180_amd import gnn as G
+    from paper_2311_12180_amd import warmstart as W
+    count = n_train + n_test
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t = time.time()
+    with ProcessPoolExecutor(workers) as ex:
+        probs = list(ex.map(_gen_family_lp, [(0, i) for i in range(count)], chunksize=64))
+    gen_s = time.time() - t
+    log(f"warm start: generated {count} LPs in {gen_s:.1f}s")
+    # targets: cold solves of the training LPs (one batched launch)
+    xs, ys, infos, cold_train_s = W.solve_batch(probs[:n_train], eps, stream)
+    ok = [k for k, i in enumerate(infos) if i["status_name"] == "OPTIMAL"]
+    ys = [W.canonical_transport_duals(y, 100) for y in ys]
+    om = np.array([infos[k]["omega"] for k in range(n_train)])
+    log(f"warm start: cold solves of {n_train} training LPs in {cold_train_s:.1f}s ({len(ok)} optimal)")
+    train_probs = [probs[k] for k in ok]
+    gs = G.pdlp_gnn_create(train_probs, [xs[k] for k in ok], [ys[k] for k in ok], om[ok], stream=stream)
+    theta0 = lpgen.gnn_init(0, _gnn_shapes())
+    # unit-scale loss terms: targets in the network's units (x s_a/s_b, y s_a/s_c; s_a = 1 here)
+    sb = [float(np.max(np.abs(probs[k].b))) for k in ok]
+    sc = [float(np.max(np.abs(probs[k].c))) for k in ok]
+    wts = W.balance_weights([xs[k] / sb[i] for i, k in enumerate(ok)], [ys[k] / sc[i] for i, k in enumerate(ok)],
+                            np.log(om[ok]))
+    losses, train_s = W.train(gs, len(ok), epochs, batch, lr, theta0, seed=0, log=log, weights=wts)
+    theta = G.pdlp_gnn_get_params(gs)
+    G.pdlp_gnn_destroy(gs)
+    # held-out LPs: predict, warm solve (with fallback), cold solve
+    test = probs[n_train:]
+    gt = G.pdlp_gnn_create(test, stream=stream)
+    G.pdlp_gnn_set_params(gt, theta)
+    t = time.perf_counter()
+    x0, y0, om0 = W.predict(gt, 0, n_test)
+    infer_s = time.perf_counter() - t
+    G.pdlp_gnn_destroy(gt)
+    _, _, cold, cold_s = W.solve_batch(test, eps, stream)
+    warm, warm_s, fb_s, fb = W.warm_solve_with_fallback(test, eps, (x0, y0, om0), stream)
+    ci = np.array([i["iterations"] for i in cold], float)
+    wi = np.array([i["iterations"] for i in warm], float)
+    # the same held-out LPs warm-started from the mean training solution (no network)
+    xm = np.mean([xs[k] for k in ok], axis=0)
+    ym = np.mean([ys[k] for k in ok], axis=0)
+    _, _, avg, avg_s = W.solve_batch(test, eps, stream, warm=([xm] * n_test, [ym] * n_test,
+                                                             np.full(n_test, float(np.exp(np.mean(np.log(om[ok])))))))
+    ai = np.array([i["iterations"] for i in avg], float)
+    return {"workload": f"{count} transportation LPs 100 x 100 (n = 10,000, m = 200) of one family; "
+                        f"train {n_train}, test {n_test}; rel KKT {eps:g}",
+            "generate_s": round(gen_s, 1), "cold_train_solves_s": round(cold_train_s, 2),
+            "train": {"epochs": epochs, "batch_lps": batch, "lr": lr, "seconds": round(train_s, 2),
+                      "loss_weights": [round(w, 4) for w in wts],
+                      "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1]},
+            "inference_s": round(infer_s, 4),
+            "test_cold": {"solve_s": round(cold_s, 3), "iterations_mean": float(ci.mean()),
+                          "iterations_median": float(np.median(ci)), "optimal": sum(i["status_name"] == "OPTIMAL" for i in cold)},
+            "test_warm": {"solve_s": round(warm_s, 3), "fallback_s": round(fb_s, 3), "fallbacks": len(fb),
+                          "iterations_mean": float(wi.mean()), "iterations_median": float(np.median(wi)),
+                          "optimal": sum(i["status_name"] == "OPTIMAL" for i in warm)},
+            "test_warm_from_mean_solution": {"solve_s": round(avg_s, 3), "iterations_mean": float(ai.mean())},
+            "iterations_ratio_warm_over_cold": round(float(wi.mean() / ci.mean()), 4),
+            "time_ratio_warm_over_cold": round(float((warm_s + fb_s + infer_s) / cold_s), 4)}
+
+
+def _gnn_shapes():
+    H = 64
+    shapes = [("W_v0", (5, H)), ("b_v0", (H,)), ("W_c0", (4, H)), ("b_c0", (H,))]
+    for r in range(3):
+        shapes += [(f"Phi{r}", (2 * H, H)), (f"phi{r}", (H,)), (f"Psi{r}", (2 * H, H)), (f"psi{r}", (H,))]
+    return shapes + [("w_x", (H,)), ("b_x", (1,)), ("w_y", (H,)), ("b_y", (1,)), ("w_o", (2 * H,)), ("b_o", (1,))]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,9 +262,15 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--profile-attempts", type=int, default=200)
+    ap.add_argument("--layout", type=int, nargs=2, default=(-1, -2), metavar=("K", "KT"),
+                    help="SpMV layouts of K and K' (-1: chosen at create by timing; pin them for profiler runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-LP section")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-sample", type=int, default=64)
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start section")
+    ap.add_argument("--ws-train", type=int, default=16000)
+    ap.add_argument("--ws-test", type=int, default=4000)
+    ap.add_argument("--ws-epochs", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver does not shard "
@@ -201,7 +300,8 @@ def main():
     del a, b
 
     stream = torch.cuda.current_stream().cuda_stream
-    h = P.pdlp_create(prob, stream=stream, eps_rel=0.0, max_iter=args.warmup, time_limit_s=600.0)
+    h = P.pdlp_create(prob, stream=stream, eps_rel=0.0, max_iter=args.warmup, time_limit_s=600.0,
+                      spmv_layout=args.layout[0], spmv_layout_kt=args.layout[1])
     _, _, _, info0 = None, None, None, None
     P.pdlp_solve(h)            # warm-up: graph capture, first launches
     log(f"setup {P.pdlp_get_solution(h)[3]['setup_s']:.2f}s; warm-up {args.warmup} steps done")
@@ -221,13 +321,17 @@ def main():
     # per-kernel durations (HIP events on the solver's stream) and the roofline
     ms_a, ms_b = P.pdlp_profile_attempts(h, args.profile_attempts)
     by_a, by_b = P.pdlp_step_bytes(h)
-    kern = {"k_primal": (ms_a, by_a), "k_dual": (ms_b, by_b)}
+    # a step is one kernel (row blocks) or two (column panels: segment sums, then rows)
+    names = {0: "{}<{}>", 1: "k_seg<{1}> + k_rows<{1}>", 2: "{}<{}> (XCD-contiguous blocks)"}
+    lk, lt = info["layout_k"], info["layout_kt"]
+    kern = {"primal_step": (ms_a, by_a, names[lt].format("k_fused", "PrimalOp")),
+            "dual_step": (ms_b, by_b, names[lk].format("k_fused", "DualOp"))}
     dom = max(kern, key=lambda k: kern[k][0])
-    ms_d, by_d = kern[dom]
+    ms_d, by_d, kname = kern[dom]
     achieved = by_d / (ms_d * 1e-3) / 1e9
     traffic = _traffic_from_profiles(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": dom,
+                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": f"{dom}: {kname}",
                 "bytes_per_launch": by_d, "ms_per_launch": ms_d,
                 "other_kernel": {"name": [k for k in kern if k != dom][0],
                                  "ms_per_launch": kern[[k for k in kern if k != dom][0]][0],
@@ -261,6 +365,11 @@ def main():
         batch = batch_section(P, stream, args.batch_count, 1e-6, args.batch_sample)
         log(f"batch: {batch}")
 
+    ws = None
+    if not args.no_warmstart:
+        ws = warmstart_section(P, stream, args.ws_train, args.ws_test, args.ws_epochs, 64, 1e-3, 1e-6)
+        log(f"warm start: {ws}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob, args.cpu_iters)
@@ -272,8 +381,10 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "skewed random LP m=1e6 (half EQ, half LE) n=2e6 nnz=2e7, row lengths "
                                    "power-law capped at 10,000, FP64 matrix",
-                       "m": prob.m, "n": prob.n, "nnz": prob.nnz, "eval_period": 64},
-            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt, "batch": batch}
+                       "m": prob.m, "n": prob.n, "nnz": prob.nnz, "eval_period": 64,
+                       "spmv_layout_k_kt": [info["layout_k"], info["layout_kt"]]},
+            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt, "batch": batch,
+            "warm_start": ws}
     print(json.dumps(line), flush=True)
 
 

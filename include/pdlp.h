@@ -96,13 +96,16 @@ typedef struct {
                                  0: row blocks; 1: column panels (one per XCD) with a second pass
                                  that adds each row's panel sums; 2: row blocks with contiguous
                                  block ranges per XCD.  The layout changes the order of floating-point
-                                 sums; fix it for bitwise reproducibility across handles */
+                                 sums; fix it for bitwise reproducibility across handles.  This
+                                 field applies to K, and to K' unless spmv_layout_kt says otherwise */
   int32_t batch_lanes;        /* batch handles: how each LP's rows are swept.  0 = chosen per LP
                                  class by timing capped solves at pdlp_create_batch (default);
                                  -1 = LDS-tiled row blocks for every LP; 1..64 (a power of two) =
                                  that many lanes per row for every row */
   int32_t batch_grid;         /* batch handles: workgroups of the persistent launch, 0 = chosen by
                                  timing (default) */
+  int32_t spmv_layout_kt;     /* -2: K' follows spmv_layout (default); -1, 0, 1, 2: as spmv_layout,
+                                 for K' alone */
 } pdlp_options;
 
 typedef struct {

@@ -24,9 +24,10 @@
  * phi_r[64], Psi_r[128][64], psi_r[64], then w_x[64], b_x, w_y[64], b_y,
  * w_o[128], b_o: PDLP_GNN_PARAMS floats.
  *
- * Loss of one LP with a solution (x*, y*, omega*): mean_j (xh_j - x*_j s_a/s_b)^2
- * + mean_i (yh_i - y*_i s_a/s_c)^2 + (oh - log omega*)^2, where xh, yh, oh are
- * the head outputs; a step averages it over a range of LPs.
+ * Loss of one LP with a solution (x*, y*, omega*): w_x mean_j (xh_j - x*_j s_a/s_b)^2
+ * + w_y mean_i (yh_i - y*_i s_a/s_c)^2 + w_o (oh - log omega*)^2, where xh, yh, oh
+ * are the head outputs and (w_x, w_y, w_o) the term weights (1 unless set);
+ * a step averages it over a range of LPs.
  *
  * Every function returns 0 (PDLP_OK) or a negative PDLP_ERR_* code of pdlp.h. */
 #ifndef PDLP_GNN_H
@@ -57,6 +58,11 @@ int pdlp_gnn_create(const pdlp_problem* ps, int32_t count, const double* x_star,
 /* Replace the FP32 master weights (theta[PDLP_GNN_PARAMS], host) and clear the
  * Adam moments and step count. */
 int pdlp_gnn_set_params(pdlp_gnn* g, const float* theta);
+
+/* Weights of the three loss terms (finite, >= 0; 1, 1, 1 after create): the
+ * terms have very different scales (a primal weight spans decades across a
+ * family while scaled x and y entries are small), so a caller balances them. */
+int pdlp_gnn_set_loss_weights(pdlp_gnn* g, double w_x, double w_y, double w_o);
 
 /* Copy the FP32 master weights to theta[PDLP_GNN_PARAMS] (host). */
 int pdlp_gnn_get_params(pdlp_gnn* g, float* theta);

@@ -20,8 +20,9 @@ joined by the nonzeros a_ij:
              oh = [mean_j h_v | mean_i h_c] w_o + b_o
   outputs    x0 = xh s_b/s_a,  y0 = yh s_c/s_a,  omega0 = exp(oh)
 
-Loss of one LP against a solution (x*, y*, omega*):
-  mean_j (xh_j - x*_j s_a/s_b)^2 + mean_i (yh_i - y*_i s_a/s_c)^2 + (oh - log omega*)^2,
+Loss of one LP against a solution (x*, y*, omega*), with term weights
+(w_x, w_y, w_o), 1 by default:
+  w_x mean_j (xh_j - x*_j s_a/s_b)^2 + w_y mean_i (yh_i - y*_i s_a/s_c)^2 + w_o (oh - log omega*)^2,
 averaged over the LPs of a mini-batch; Adam (Kingma & Ba) on FP32 master
 weights.  With ``bf16=True`` the operands of the eight 128 x 64 products (forward
 and both backward products) are rounded to bfloat16 (round to nearest even)
@@ -130,20 +131,25 @@ def predictions(g: dict, xh, yh, oh):
     return xh * g["s_b"] / g["s_a"], yh * g["s_c"] / g["s_a"], float(np.exp(oh))
 
 
-def loss_one(g, xh, yh, oh, t):
+def loss_one(g, xh, yh, oh, t, wts=(1.0, 1.0, 1.0)):
+    """w_x mean_j (xh - xt)^2 + w_y mean_i (yh - yt)^2 + w_o (oh - ot)^2."""
     xt, yt, ot = t
-    L = float(np.mean((xh - xt) ** 2)) + (float(np.mean((yh - yt) ** 2)) if g["m"] else 0.0) + (oh - ot) ** 2
+    wx, wy, wo = wts
+    L = (wx * float(np.mean((xh - xt) ** 2)) + (wy * float(np.mean((yh - yt) ** 2)) if g["m"] else 0.0)
+         + wo * (oh - ot) ** 2)
     return L
 
 
-def backward(p: dict, g: dict, cache: dict, xh, yh, oh, t, scale: float = 1.0, bf16_ops: bool = False) -> dict:
+def backward(p: dict, g: dict, cache: dict, xh, yh, oh, t, scale: float = 1.0, bf16_ops: bool = False,
+             wts=(1.0, 1.0, 1.0)) -> dict:
     """Gradient of scale * loss_one with respect to every parameter."""
     xt, yt, ot = t
+    wx, wy, wo = wts
     n, m = g["n"], g["m"]
     grads = {name: np.zeros(shape) for name, shape in PARAMS}
-    dxh = scale * 2.0 * (xh - xt) / n
-    dyh = scale * 2.0 * (yh - yt) / m if m else np.zeros(0)
-    doh = scale * 2.0 * (oh - ot)
+    dxh = scale * wx * 2.0 * (xh - xt) / n
+    dyh = scale * wy * 2.0 * (yh - yt) / m if m else np.zeros(0)
+    doh = scale * wo * 2.0 * (oh - ot)
     hv, hc = cache["hv"], cache["hc"]
     grads["w_x"] = hv.T @ dxh
     grads["b_x"] = np.array([dxh.sum()])
@@ -179,7 +185,7 @@ def backward(p: dict, g: dict, cache: dict, xh, yh, oh, t, scale: float = 1.0, b
     return grads
 
 
-def batch_loss_and_grad(theta: np.ndarray, graphs, tgts, bf16_ops: bool = False):
+def batch_loss_and_grad(theta: np.ndarray, graphs, tgts, bf16_ops: bool = False, wts=(1.0, 1.0, 1.0)):
     """Mean loss over the LPs and its gradient (flat vectors)."""
     p = unflatten(theta)
     K = len(graphs)
@@ -187,8 +193,8 @@ def batch_loss_and_grad(theta: np.ndarray, graphs, tgts, bf16_ops: bool = False)
     acc = np.zeros(N_PARAMS)
     for g, t in zip(graphs, tgts):
         xh, yh, oh, cache = forward(p, g, bf16_ops)
-        total += loss_one(g, xh, yh, oh, t) / K
-        acc += flatten(backward(p, g, cache, xh, yh, oh, t, 1.0 / K, bf16_ops))
+        total += loss_one(g, xh, yh, oh, t, wts) / K
+        acc += flatten(backward(p, g, cache, xh, yh, oh, t, 1.0 / K, bf16_ops, wts))
     return total, acc
 
 

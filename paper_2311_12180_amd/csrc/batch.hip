@@ -1,0 +1,302 @@
+// Batched restarted PDHG: many independent LPs in one persistent launch (see
+// the comment of the batched-LP section below).  Uses the shared ops and
+// decision functions of pdlp_ops.h, so every LP runs the same arithmetic as
+// the single-LP kernels.
+#include <math.h>
+
+#include "pdlp_ops.h"
+
+namespace pdlp {
+
+// ---------------------------------------------------------------------------- batched LPs
+//
+// Many independent LPs (packed block-diagonally: LP b owns rows
+// [row_off[b], row_off[b+1]) of K~ and columns [col_off[b], col_off[b+1]))
+// are solved by one persistent launch.  A workgroup takes the next LP from an
+// atomic queue (largest first), runs the whole of Algorithm 1 on it with every
+// phase of the single-LP path -- the same ops and the same decision functions
+// -- separated by workgroup barriers, keeps the LP's state in LDS, writes the
+// solution and takes the next LP.  Rows are swept by groups of L lanes (L per
+// LP from the batch schedule: lanes for the rows of K~ and for those of K~').
+
+// Row sweep of one LP's rows [rb, re) with L lanes per row; op.epi runs on the
+// group's first lane.
+template <int NV, typename VT, class Op>
+__device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                          const VT* __restrict__ v, int rb, int re, int L, const Op& op,
+                                          double* acc) {
+  const int groups = kBlock / L;
+  const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
+  for (int r = rb + grp; r < re; r += groups) {
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    const int e1 = rp[r + 1];
+    for (int e = rp[r] + lane; e < e1; e += L) {
+      const double a = (double)v[e];
+      double g[NV];
+      op.gather(ci[e], g);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += a * g[k];
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += __shfl_down(s[k], off, L);
+    }
+    if (lane == 0) op.epi(r, s, acc);
+  }
+}
+
+// One pass of an op over an LP's rows: the LDS-tiled row blocks [b0, b1)
+// when L = 0 (the single-LP sweep), else rows [rb, re) walked with L lanes per row.
+template <int NV, typename VT, class Op>
+__device__ __forceinline__ void sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                      const VT* __restrict__ v, const RowBlock* __restrict__ blocks, int b0, int b1,
+                                      int rb, int re, int L, const Op& op, double* acc, double* lds, double* red) {
+  if (L == 0) {
+    for (int j = b0; j < b1; ++j) {
+      spmv_block<NV, VT>(rp, ci, v, blocks[j], lds, red, [&](int c, double* g) { op.gather(c, g); },
+                         [&](int r, const double* s) { op.epi(r, s, acc); });
+      __syncthreads();
+    }
+  } else {
+    lane_rows<NV, VT>(rp, ci, v, rb, re, L, op, acc);
+  }
+}
+
+__device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red,
+                                double* lds) {
+  const int r0 = bp.row_off[b], r1 = bp.row_off[b + 1];
+  const int c0 = bp.col_off[b], c1 = bp.col_off[b + 1];
+  const int LK = bp.lanes[2 * b], LT = bp.lanes[2 * b + 1];
+  const int k0 = bp.bk_off[b], k1 = bp.bk_off[b + 1], t0 = bp.bt_off[b], t1 = bp.bt_off[b + 1];
+  const Trace tr = b == bp.trace_lp ? p.tr : Trace{};
+  const double qn0 = sqrt(bp.norms[4 * b]), cn0 = sqrt(bp.norms[4 * b + 1]);
+  const bool f32 = p.use_f32 != 0;
+  if (threadIdx.x == 0) {
+    DevState z{};
+    *S = z;
+    const double km = bp.kmax[b];
+    S->eta = S->eta_hat = km > 0.0 ? 1.0 / km : 1.0;
+    const double cn = sqrt(bp.norms[4 * b + 2]), qn = sqrt(bp.norms[4 * b + 3]);
+    const double w0 = (cn > bp.eps_zero && qn > bp.eps_zero) ? cn / qn : 1.0;
+    S->omega = bp.omega_warm[b] > 0.0 ? bp.omega_warm[b] : w0;
+    S->initial = 1;
+    S->need_eval = 1;
+    S->eps_rel = bp.eps_rel;
+    S->max_iter = bp.max_iter;
+  }
+  // starting point (as k_init_x / k_init_y)
+  const bool warm = bp.warm[b] != 0;
+  for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+    double v = warm ? bp.wx[j] / p.D2[j] : 0.0;
+    if (v < p.l[j]) v = p.l[j];
+    if (v > p.u[j]) v = p.u[j];
+    p.x[0][j] = v;
+    p.x[1][j] = v;
+    p.xsum[j] = 0.0;
+    p.xbar[j] = v;
+    p.x0[j] = v;
+    p.dx[j] = 0.0;
+  }
+  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    double v = 0.0;
+    if (warm) {
+      v = (p.le[i] ? -bp.wy[i] : bp.wy[i]) / p.D1[i];
+      if (p.ineq[i] && v < 0.0) v = 0.0;
+    }
+    p.y[0][i] = v;
+    p.y[1][i] = v;
+    p.ysum[i] = 0.0;
+    p.ybar[i] = v;
+    p.y0[i] = v;
+    p.kx[0][i] = 0.0;
+    p.kx[1][i] = 0.0;
+  }
+  __syncthreads();
+  int64_t k_seen = 0, rejected = 0;  // thread 0: accepted steps at the last attempt, rejections since
+  for (;;) {
+    if (S->need_eval) {
+      // --- evaluation: averages, eq. (kkt) pieces, Section 4.1 quantities
+      double acc[18];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) acc[k] = 0.0;
+      {
+        const int cur = S->cur, init = S->initial, pend = S->has_pending;
+        const double pw = S->pending_w, se = S->sum_eta;
+        const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+        for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+          const double xj = x[j];
+          double xb = xj;
+          if (!init && se > 0.0) {
+            double s = p.xsum[j];
+            if (pend) {
+              s += pw * xj;
+              p.xsum[j] = s;
+            }
+            xb = s / se;
+          }
+          p.xbar[j] = xb;
+          const double cj = p.c[j], x0j = p.x0[j];
+          acc[0] += cj * xj;
+          acc[1] += cj * xb;
+          double d = xj - x0j;
+          acc[2] += d * d;
+          d = xb - x0j;
+          acc[3] += d * d;
+        }
+      }
+      __syncthreads();
+      {
+        const EvalRowsOp op(p, S);
+        sweep<2, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 4, lds, red);
+      }
+      __syncthreads();
+      {
+        const EvalColsOp op(p, S);
+        sweep<2, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc + 12, lds, red);
+      }
+      block_sum<18>(acc, red);
+      if (threadIdx.x == 0) eval_decision(S, p, tr, acc, qn0, cn0);
+      __syncthreads();
+      if (S->restart_flag) {
+        const int cur = S->cur, cand = S->cand_avg;
+        double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+        for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+          const double xc = cand ? p.xbar[j] : x[j];
+          x[j] = xc;
+          p.x0[j] = xc;
+          p.xsum[j] = 0.0;
+        }
+        __syncthreads();
+        const RestartYOp op(p, S);
+        double dummy[1];
+        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
+        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
+        __syncthreads();
+        if (threadIdx.x == 0) S->restart_flag = 0;
+      }
+    } else {
+      // --- one attempt of Algorithm 2
+      double acc[3] = {0.0, 0.0, 0.0};
+      {
+        const PrimalOp op(p, S);
+        if (f32) sweep<1, float>(p.KT.rp, p.KT.ci, p.KT.vf, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+        else sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+      }
+      __syncthreads();
+      {
+        const DualOp op(p, S);
+        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
+        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
+      }
+      block_sum<3>(acc, red);
+      if (threadIdx.x == 0) {
+        step_decision(S, p, tr, acc[0], acc[1], acc[2]);
+        rejected = S->k == k_seen ? rejected + 1 : 0;
+        k_seen = S->k;
+        if (!S->done && rejected >= bp.max_reject) {
+          S->status = 4;
+          S->ret_avg = 0;
+          S->done = 1;
+        }
+      }
+    }
+    if (threadIdx.x == 0 && !S->done && bp.ticks && wall_clock64() - *bp.t0 > bp.ticks) {
+      S->status = 3;
+      S->ret_avg = 0;
+      S->done = 1;
+    }
+    __syncthreads();
+    if (S->done) break;
+  }
+  // --- output of this LP (as the output op and k_output_y)
+  {
+    const OutputOp op(p, S);
+    double dummy[1];
+    sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, dummy, lds, red);
+    const int cur = S->cur, ra = S->ret_avg;
+    const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
+    for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
+      const double v = p.D1[i] * y[i];
+      p.yo[i] = p.le[i] ? -v : v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) bp.st[b] = *S;
+}
+
+// Persistent batch solver: every workgroup takes LPs from the queue until it
+// is empty, so the launch ends when every LP has been solved.
+__global__ __launch_bounds__(kBlock) void k_batch(Params p, BatchParams bp) {
+  __shared__ DevState S;
+  __shared__ double red[18 * (kBlock / 64)];
+  __shared__ double lds[2 * kTile];
+  __shared__ int slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = (int)atomicAdd(bp.queue, 1u);
+    __syncthreads();
+    const int q = slot;
+    __syncthreads();
+    if (q >= bp.count) break;
+    batch_solve_one(p, bp, bp.order[q], &S, red, lds);
+  }
+}
+
+__global__ void k_stamp(uint64_t* t0) {
+  if (threadIdx.x == 0) *t0 = wall_clock64();
+}
+
+// Per-LP sums of squares of a[off[b] .. off[b+1]) in blocks of 4096 (serial
+// inside a block and across blocks), one thread per LP.
+__global__ void k_seg_sumsq(int nlp, const int32_t* __restrict__ off, const double* __restrict__ a,
+                            double* __restrict__ out, int stride, int slot) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nlp; b += gridDim.x * blockDim.x) {
+    double tot = 0.0;
+    for (int64_t i0 = off[b]; i0 < off[b + 1]; i0 += 4096) {
+      const int64_t i1 = i0 + 4096 < off[b + 1] ? i0 + 4096 : off[b + 1];
+      double s = 0.0;
+      for (int64_t i = i0; i < i1; ++i) s = __dadd_rn(s, __dmul_rn(a[i], a[i]));
+      tot = __dadd_rn(tot, s);
+    }
+    out[stride * b + slot] = tot;
+  }
+}
+
+// Per-LP max |K~_ij| over the LP's nonzeros.
+__global__ void k_seg_absmax(int nlp, const int32_t* __restrict__ row_off, const int32_t* __restrict__ rp,
+                             const double* __restrict__ v, double* __restrict__ out) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nlp; b += gridDim.x * blockDim.x) {
+    double mx = 0.0;
+    for (int e = rp[row_off[b]]; e < rp[row_off[b + 1]]; ++e) {
+      const double a = fabs(v[e]);
+      mx = a > mx ? a : mx;
+    }
+    out[b] = mx;
+  }
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, const_cast<uint64_t*>(bp.t0));
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), 0, s, p, bp);
+}
+
+int batch_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBlock, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+void launch_seg_sumsq(int nlp, const int32_t* off, const double* a, double* out, int stride, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_sumsq, dim3((nlp + 255) / 256), dim3(256), 0, s, nlp, off, a, out, stride, slot);
+}
+
+void launch_seg_absmax(int nlp, const int32_t* row_off, const int32_t* rp, const double* v, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_absmax, dim3((nlp + 255) / 256), dim3(256), 0, s, nlp, row_off, rp, v, out);
+}
+
+
+}  // namespace pdlp

@@ -287,13 +287,15 @@ __global__ __launch_bounds__(kBlock) void k_pool(int count, const int32_t* __res
   }
 }
 
-// Per LP (one workgroup each): the loss and the seeds of the backward pass,
-// dxh = 2 (xh - xt) / (n K), dyh = 2 (yh - yt) / (m K), doh = 2 (oh - ot) / K.
+// Per LP (one workgroup each): the weighted loss and the seeds of the backward
+// pass, dxh = 2 w_x (xh - xt) / (n K), dyh = 2 w_y (yh - yt) / (m K),
+// doh = 2 w_o (oh - ot) / K.
 __global__ __launch_bounds__(kBlock) void k_loss(int count, int first, const int32_t* __restrict__ voff,
                                                  const int32_t* __restrict__ coff, int v0, int c0,
                                                  const float* __restrict__ xh, const float* __restrict__ yh,
                                                  const float* __restrict__ oh, const float* __restrict__ xt,
                                                  const float* __restrict__ yt, const float* __restrict__ ot,
+                                                 float wx, float wy, float wo,
                                                  float* __restrict__ dxh, float* __restrict__ dyh,
                                                  float* __restrict__ doh, double* __restrict__ loss) {
   __shared__ double red[2][kBlock / 64];
@@ -305,12 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_loss(int count, int first, const int
     for (int j = jb + threadIdx.x; j < je; j += kBlock) {
       const float d = xh[j] - xt[voff[k] + (j - jb)];
       sx += (double)d * d;
-      dxh[j] = 2.f * d / (nk * K);
+      dxh[j] = 2.f * wx * d / (nk * K);
     }
     for (int i = ib + threadIdx.x; i < ie; i += kBlock) {
       const float d = yh[i] - yt[coff[k] + (i - ib)];
       sy += (double)d * d;
-      dyh[i] = 2.f * d / (mk * K);
+      dyh[i] = 2.f * wy * d / (mk * K);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -329,8 +331,9 @@ __global__ __launch_bounds__(kBlock) void k_loss(int count, int first, const int
         c += red[1][q];
       }
       const double dw = (double)oh[k] - (double)ot[first + k];
-      loss[k] = (je > jb ? a / (je - jb) : 0.0) + (ie > ib ? c / (ie - ib) : 0.0) + dw * dw;
-      doh[k] = (float)(2.0 * dw / K);
+      loss[k] = (je > jb ? (double)wx * a / (je - jb) : 0.0) + (ie > ib ? (double)wy * c / (ie - ib) : 0.0) +
+                (double)wo * dw * dw;
+      doh[k] = (float)(2.0 * (double)wo * dw / K);
     }
     __syncthreads();
   }
@@ -667,10 +670,10 @@ void launch_pool(int count, const int32_t* voff, const int32_t* coff, int v0, in
                      wo, bo, pool, oh);
 }
 void launch_loss(int count, int first, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* xh,
-                 const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float* dxh,
-                 float* dyh, float* doh, double* loss, hipStream_t s) {
+                 const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float wx,
+                 float wy, float wo, float* dxh, float* dyh, float* doh, double* loss, hipStream_t s) {
   hipLaunchKernelGGL(k_loss, dim3(count < 8192 ? count : 8192), dim3(kBlock), 0, s, count, first, voff, coff, v0, c0,
-                     xh, yh, oh, xt, yt, ot, dxh, dyh, doh, loss);
+                     xh, yh, oh, xt, yt, ot, wx, wy, wo, dxh, dyh, doh, loss);
 }
 void launch_predict(int nv, int nc, int v0, int c0, const int32_t* vown, const int32_t* cown, const double* scales,
                     const float* xh, const float* yh, double* x0, double* y0, hipStream_t s) {

@@ -41,8 +41,8 @@ void launch_head(int N, const float* H, const float* w, const float* b, float* o
 void launch_pool(int count, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* Hv,
                  const float* Hc, const float* wo, const float* bo, float* pool, float* oh, hipStream_t s);
 void launch_loss(int count, int first, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* xh,
-                 const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float* dxh,
-                 float* dyh, float* doh, double* loss, hipStream_t s);
+                 const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float wx,
+                 float wy, float wo, float* dxh, float* dyh, float* doh, double* loss, hipStream_t s);
 void launch_predict(int nv, int nc, int v0, int c0, const int32_t* vown, const int32_t* cown, const double* scales,
                     const float* xh, const float* yh, double* x0, double* y0, hipStream_t s);
 void launch_omega(int count, const float* oh, double* om, hipStream_t s);
@@ -102,6 +102,7 @@ struct pdlp_gnn {
   double* scales = nullptr;
   float *xt = nullptr, *yt = nullptr, *ot = nullptr;
   bool has_targets = false;
+  float loss_w[3] = {1.f, 1.f, 1.f};
   float *theta = nullptr, *grad = nullptr, *am = nullptr, *av = nullptr;
   int64_t adam_t = 0;
   unsigned short* wbf = nullptr;  // per transform (2 per round): W [128][64], then W' [64][128]
@@ -323,6 +324,16 @@ extern "C" int pdlp_gnn_set_params(pdlp_gnn* g, const float* theta) {
   return PDLP_OK;
 }
 
+extern "C" int pdlp_gnn_set_loss_weights(pdlp_gnn* g, double wx, double wy, double wo) {
+  if (!g) return PDLP_ERR_ARG;
+  for (double w : {wx, wy, wo})
+    if (!(w >= 0.0) || !std::isfinite(w)) return gfail(g, PDLP_ERR_ARG, "loss weights must be finite and >= 0");
+  g->loss_w[0] = (float)wx;
+  g->loss_w[1] = (float)wy;
+  g->loss_w[2] = (float)wo;
+  return PDLP_OK;
+}
+
 extern "C" int pdlp_gnn_get_params(pdlp_gnn* g, float* theta) {
   if (!g || !theta) return PDLP_ERR_ARG;
   try {
@@ -387,7 +398,7 @@ double backward(pdlp_gnn* g, const Range& R) {
   hipStream_t s = g->stream;
   const float* th = g->theta;
   launch_loss(R.K, R.first, g->col_off + R.first, g->row_off + R.first, R.v0, R.c0, g->xh, g->yh, g->oh, g->xt,
-              g->yt, g->ot, g->dxh, g->dyh, g->doh, g->loss, s);
+              g->yt, g->ot, g->loss_w[0], g->loss_w[1], g->loss_w[2], g->dxh, g->dyh, g->doh, g->loss, s);
   // heads
   launch_head_bwd(R.nv, R.first, g->vown + R.v0, g->col_off, g->hv[kRounds], g->dxh, g->doh, th + kWx, th + kWo,
                   g->dhv, g->part, s);

@@ -290,6 +290,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->poll_every = 4;
   o->graph = 1;
   o->spmv_layout = -1;
+  o->spmv_layout_kt = -2;
   o->batch_lanes = 0;
   o->batch_grid = 0;
   return PDLP_OK;
@@ -311,6 +312,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
   if (o.spmv_layout < -1 || o.spmv_layout > 2) return why = "spmv_layout must be -1, 0, 1 or 2", -1;
+  if (o.spmv_layout_kt < -2 || o.spmv_layout_kt > 2) return why = "spmv_layout_kt must be -2, -1, 0, 1 or 2", -1;
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
@@ -457,7 +459,6 @@ static double time_probe(pdlp_handle* h, int which, int reps) {
 // when it is faster by more than 5 %, so close calls stay on the default.
 static void choose_layouts(pdlp_handle* h) {
   Params& P = h->P;
-  const int mode = h->opt.spmv_layout;
   double* pin = h->dalloc<double>((size_t)std::max(h->m, h->n));
   double* pout = h->dalloc<double>((size_t)std::max(h->m, h->n));
   check(setup_fill(std::max(h->m, h->n), pin, 1.0, h->stream), "probe fill");
@@ -465,6 +466,7 @@ static void choose_layouts(pdlp_handle* h) {
   P.probe_out = pout;
   for (int which = 0; which < 2; ++which) {
     DevCsr& M = which ? P.KT : P.K;
+    const int mode = (which == 1 && h->opt.spmv_layout_kt != -2) ? h->opt.spmv_layout_kt : h->opt.spmv_layout;
     const bool has_pan = M.pan.seg_ptr != nullptr;
     auto set = [&](int layout, int remap) {
       M.layout = layout;
@@ -758,14 +760,16 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
                   PanelCsr{}};
     // a panel layout pays when the gathered vector does not fit one XCD's L2;
     // spmv_layout = 1 builds it for any size (tests)
-    const bool want_panels = opt.spmv_layout == 1 || (opt.spmv_layout < 0 && nnz >= (1 << 20));
-    if (want_panels) {
+    const int mode_k = opt.spmv_layout, mode_kt = opt.spmv_layout_kt != -2 ? opt.spmv_layout_kt : opt.spmv_layout;
+    const bool want_k = mode_k == 1 || (mode_k == -1 && nnz >= (1 << 20) && n >= (1 << 18));
+    const bool want_kt = mode_kt == 1 || (mode_kt == -1 && nnz >= (1 << 20) && m >= (1 << 18));
+    {
       std::vector<int32_t> hciT;
-      if (n >= (1 << 18) || opt.spmv_layout == 1) {
+      if (want_k) {
         HostPanels HP = build_panels(H.rp.data(), H.ci.data(), m, n, hrpT.data());
         upload_panels(h, P.K, HP, nnz, h->ci, h->val, h->valf);
       }
-      if (m >= (1 << 18) || opt.spmv_layout == 1) {
+      if (want_kt) {
         hciT.resize((size_t)std::max<int64_t>(nnz, 1));
         if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
         HostPanels HP = build_panels(hrpT.data(), hciT.data(), n, m, H.rp.data());

@@ -13,7 +13,8 @@ import numpy as np
 from . import pdlp as _P
 
 PDLP_GNN_PARAMS = 50499
-EXPORTED = ["pdlp_gnn_create", "pdlp_gnn_set_params", "pdlp_gnn_get_params", "pdlp_gnn_loss_grad",
+EXPORTED = ["pdlp_gnn_create", "pdlp_gnn_set_params", "pdlp_gnn_set_loss_weights", "pdlp_gnn_get_params",
+            "pdlp_gnn_loss_grad",
             "pdlp_gnn_train_step", "pdlp_gnn_predict", "pdlp_gnn_last_error", "pdlp_gnn_destroy"]
 
 _ready = False
@@ -27,6 +28,7 @@ def lib() -> C.CDLL:
         L.pdlp_gnn_create.argtypes = [C.POINTER(_P.pdlp_problem), i32, vp, vp, vp, vp, C.POINTER(vp)]
         L.pdlp_gnn_set_params.argtypes = [vp, vp]
         L.pdlp_gnn_get_params.argtypes = [vp, vp]
+        L.pdlp_gnn_set_loss_weights.argtypes = [vp, dbl, dbl, dbl]
         L.pdlp_gnn_loss_grad.argtypes = [vp, i32, i32, C.POINTER(dbl), vp]
         L.pdlp_gnn_train_step.argtypes = [vp, i32, i32, C.c_float, C.POINTER(dbl)]
         L.pdlp_gnn_predict.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -103,6 +105,10 @@ def pdlp_gnn_set_params(g: GraphSet, theta):
     if th.shape != (PDLP_GNN_PARAMS,):
         raise ValueError(f"theta must have {PDLP_GNN_PARAMS} entries")
     _check(lib().pdlp_gnn_set_params(g.ptr, th.ctypes.data), g)
+
+
+def pdlp_gnn_set_loss_weights(g: GraphSet, w_x: float, w_y: float, w_o: float):
+    _check(lib().pdlp_gnn_set_loss_weights(g.ptr, float(w_x), float(w_y), float(w_o)), g)
 
 
 def pdlp_gnn_get_params(g: GraphSet) -> np.ndarray:

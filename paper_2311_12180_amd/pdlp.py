@@ -54,7 +54,7 @@ class pdlp_options(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
                 ("kkt_omega_power", C.c_int32), ("trace", C.c_int32), ("poll_every", C.c_int32),
                 ("graph", C.c_int32), ("spmv_layout", C.c_int32), ("batch_lanes", C.c_int32),
-                ("batch_grid", C.c_int32)]
+                ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32)]
 
 
 class pdlp_info(C.Structure):

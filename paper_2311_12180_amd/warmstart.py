@@ -50,12 +50,23 @@ def solve_batch(problems: Sequence, eps: float, stream=None, warm=None, time_lim
     return xs, ys, infos, dt
 
 
+def balance_weights(x_t: Sequence[np.ndarray], y_t: Sequence[np.ndarray], log_omega: np.ndarray):
+    """Loss weights that give each term unit scale on the training targets:
+    1 / mean square of the scaled x and y targets, 1 / variance of log omega."""
+    mx = float(np.mean(np.concatenate([np.asarray(v) ** 2 for v in x_t])))
+    my = float(np.mean(np.concatenate([np.asarray(v) ** 2 for v in y_t]))) if len(y_t) else 1.0
+    vo = float(np.var(log_omega))
+    return (1.0 / mx if mx > 0 else 1.0, 1.0 / my if my > 0 else 1.0, 1.0 / vo if vo > 0 else 1.0)
+
+
 def train(gs: "_G.GraphSet", n_train: int, epochs: int, batch: int, lr: float, theta0: np.ndarray,
-          seed: int = 0, log=None):
+          seed: int = 0, log=None, weights=None):
     """Adam on LPs [0, n_train) of the graph set in mini-batches of `batch`
     consecutive LPs, visited in a shuffled order each epoch.  Returns the mean
     loss per epoch and the training wall time."""
     _G.pdlp_gnn_set_params(gs, theta0)
+    if weights is not None:
+        _G.pdlp_gnn_set_loss_weights(gs, *weights)
     rng = np.random.default_rng(seed)
     starts = np.arange(0, n_train - batch + 1, batch)
     losses = []

@@ -49,14 +49,15 @@ def test_gradient_matches_finite_differences(which):
     graphs = [gnn.graph(p) for p in probs]
     tgts = [_targets(g, rng) for g in graphs]
     theta = _theta()
-    L, grad = gnn.batch_loss_and_grad(theta, graphs, tgts)
+    wts = (2.0, 0.5, 0.25)
+    L, grad = gnn.batch_loss_and_grad(theta, graphs, tgts, wts=wts)
     # every embedding, bias and head coordinate plus a sample of the round
     # matrices; a coordinate whose step crosses a ReLU kink (the one-sided
     # differences disagree) is not differentiable there and is left out
     names = np.concatenate([[nm] * int(np.prod(sh)) for nm, sh in gnn.PARAMS])
     small = np.flatnonzero([not (nm.startswith("Phi") or nm.startswith("Psi")) for nm in names])
     idx = np.union1d(small, rng.choice(gnn.N_PARAMS, 400, replace=False))
-    f = lambda t: gnn.batch_loss_and_grad(t, graphs, tgts)[0]
+    f = lambda t: gnn.batch_loss_and_grad(t, graphs, tgts, wts=wts)[0]
     h = 1e-6
     kinks, errs = 0, []
     for i in idx:
@@ -73,6 +74,16 @@ def test_gradient_matches_finite_differences(which):
     assert kinks <= len(idx) // 100, kinks
     assert max(errs) <= 1e-6, max(errs)
     assert L > 0
+
+
+def test_loss_weights_scale_the_terms():
+    g = gnn.graph(_lp())
+    rng = np.random.default_rng(1)
+    xh, yh, oh = rng.standard_normal(g["n"]), rng.standard_normal(g["m"]), 0.3
+    t = _targets(g, rng)
+    ex = np.mean((xh - t[0]) ** 2); ey = np.mean((yh - t[1]) ** 2); eo = (oh - t[2]) ** 2
+    assert gnn.loss_one(g, xh, yh, oh, t) == pytest.approx(ex + ey + eo, rel=1e-14)
+    assert gnn.loss_one(g, xh, yh, oh, t, (3.0, 0.0, 0.5)) == pytest.approx(3 * ex + 0.5 * eo, rel=1e-14)
 
 
 def test_forward_closed_form():

@@ -83,10 +83,12 @@ def test_gradient_matches_reference(N):
     th = _theta(5)
     g = N.pdlp_gnn_create(probs, xs, ys, om)
     N.pdlp_gnn_set_params(g, th)
+    wts = (3.0, 0.5, 0.25)
+    N.pdlp_gnn_set_loss_weights(g, *wts)
     L, grad = N.pdlp_gnn_loss_grad(g, 0, len(probs))
     graphs = [G.graph(p) for p in probs]
     tg = [G.targets(gr, x, y, o) for gr, x, y, o in zip(graphs, xs, ys, om)]
-    Lr, gr_ = G.batch_loss_and_grad(th, graphs, tg, bf16_ops=True)
+    Lr, gr_ = G.batch_loss_and_grad(th, graphs, tg, bf16_ops=True, wts=wts)
     assert abs(L - Lr) <= 1e-4 * abs(Lr)
     got, ref = G.unflatten(grad.astype(np.float64)), G.unflatten(gr_)
     worst = {name: _rel(got[name], ref[name]) for name, _ in G.PARAMS}
