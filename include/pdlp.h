@@ -95,7 +95,9 @@ typedef struct {
   int32_t spmv_layout;        /* -1: chosen per matrix at create by timing plain products (default);
                                  0: row blocks; 1: column panels (one per XCD) with a second pass
                                  that adds each row's panel sums; 2: row blocks with contiguous
-                                 block ranges per XCD.  The layout changes the order of floating-point
+                                 block ranges per XCD; 4, 5, 6: 0, 1, 2 with a persistent grid
+                                 (one workgroup per 8 waves of every CU, looping over the row
+                                 blocks).  The layout changes the order of floating-point
                                  sums; fix it for bitwise reproducibility across handles.  This
                                  field applies to K, and to K' unless spmv_layout_kt says otherwise */
   int32_t batch_lanes;        /* batch handles: how each LP's rows are swept.  0 = chosen per LP
@@ -120,8 +122,10 @@ typedef struct {
   double omega, eta_hat;      /* primal weight and step size at exit */
   double setup_s;             /* pdlp_create: upload, transpose, scaling, layout choice */
   double solve_s;             /* pdlp_solve wall time */
-  int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout); for an LP
-                                   of a batch: its sweeps of K and K' (see pdlp_batch_schedule) */
+  int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout, plus 4 when
+                                   the create-time timing chose a persistent grid for the row-block
+                                   kernels); for an LP of a batch: its sweeps of K and K' (see
+                                   pdlp_batch_schedule) */
 } pdlp_info;
 
 /* Scaled-space state of the current iterate (for parity checks and resume). */

@@ -48,19 +48,24 @@ __global__ __launch_bounds__(kBlock) void k_fused(Params p) {
   if (Op::idle(p.st)) return;
   const Op op(p, p.st);
   const DevCsr& M = Op::mat(p);
-  const int b = logical_block(M.nblocks, M.remap);
-  double acc[AccSize<Op>::N];
+  // one block per workgroup, or a persistent grid striding over the blocks;
+  // the partials stay one per block either way
+  for (int i = blockIdx.x; i < M.nblocks; i += gridDim.x) {
+    const int b = logical_block(i, M.nblocks, M.remap);
+    double acc[AccSize<Op>::N];
 #pragma unroll
-  for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
-  spmv_block<Op::NV, VT>(
-      M.rp, M.ci, pick<VT>(M.v, M.vf), M.blocks[b], lds, red, [&](int c, double* g) { op.gather(c, g); },
-      [&](int r, const double* s) { op.epi(r, s, acc); });
-  if constexpr (Op::NACC > 0) {
-    block_sum<Op::NACC>(acc, red);
-    if (threadIdx.x == 0) {
+    for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
+    spmv_block<Op::NV, VT>(
+        M.rp, M.ci, pick<VT>(M.v, M.vf), M.blocks[b], lds, red, [&](int c, double* g) { op.gather(c, g); },
+        [&](int r, const double* s) { op.epi(r, s, acc); });
+    if constexpr (Op::NACC > 0) {
+      block_sum<Op::NACC>(acc, red);
+      if (threadIdx.x == 0) {
 #pragma unroll
-      for (int k = 0; k < Op::NACC; ++k) Op::part(p)[Op::NACC * b + k] = acc[k];
+        for (int k = 0; k < Op::NACC; ++k) Op::part(p)[Op::NACC * b + k] = acc[k];
+      }
     }
+    __syncthreads();   // the next block reuses lds
   }
 }
 
@@ -74,14 +79,17 @@ __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
   const PanelCsr& S = Op::mat(p).pan;
   double* __restrict__ part = S.part;
   const int32_t* __restrict__ dst = S.seg_dst;
-  spmv_block<Op::NV, VT>(
-      S.seg_ptr, S.pci, pick<VT>(S.pv, S.pvf), S.sblocks[blockIdx.x], lds, red,
-      [&](int c, double* g) { op.gather(c, g); },
-      [&](int s, const double* sums) {
-        const int d = dst[s];
+  for (int i = blockIdx.x; i < S.nsblocks; i += gridDim.x) {
+    spmv_block<Op::NV, VT>(
+        S.seg_ptr, S.pci, pick<VT>(S.pv, S.pvf), S.sblocks[i], lds, red,
+        [&](int c, double* g) { op.gather(c, g); },
+        [&](int s, const double* sums) {
+          const int d = dst[s];
 #pragma unroll
-        for (int k = 0; k < Op::NV; ++k) part[Op::NV * d + k] = sums[k];
-      });
+          for (int k = 0; k < Op::NV; ++k) part[Op::NV * d + k] = sums[k];
+        });
+    __syncthreads();   // the next block reuses lds
+  }
 }
 
 // Panel layout, phase 2: each row adds its segment sums in panel order and
@@ -279,9 +287,11 @@ static inline int elem_grid(int n) {
 template <class Op, typename VT>
 static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
   if (M.layout == 0) {
-    hipLaunchKernelGGL((k_fused<Op, VT>), dim3(M.nblocks), dim3(kBlock), 0, s, p);
+    const int g = M.grid > 0 && M.grid < M.nblocks ? M.grid : M.nblocks;
+    hipLaunchKernelGGL((k_fused<Op, VT>), dim3(g), dim3(kBlock), 0, s, p);
   } else {
-    hipLaunchKernelGGL((k_seg<Op, VT>), dim3(M.pan.nsblocks), dim3(kBlock), 0, s, p);
+    const int g = M.grid > 0 && M.grid < M.pan.nsblocks ? M.grid : M.pan.nsblocks;
+    hipLaunchKernelGGL((k_seg<Op, VT>), dim3(g), dim3(kBlock), 0, s, p);
     hipLaunchKernelGGL((k_rows<Op>), dim3(M.rows_grid), dim3(kBlock), 0, s, p);
   }
 }

@@ -207,6 +207,7 @@ struct pdlp_handle {
   int slots_per_round = 0, rounds = 0;
   double eta0 = 1.0, omega0 = 1.0;
   double probe_ms[2] = {0.0, 0.0};
+  int32_t persist_grid = 2048;   // persistent grid of the row-block kernels (CUs x 8, a multiple of 8)
   std::string err = "no error";
   bool solved = false;
   pdlp_info info{};
@@ -311,8 +312,10 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.trace < 0) return why = "trace must be >= 0", -1;
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
-  if (o.spmv_layout < -1 || o.spmv_layout > 2) return why = "spmv_layout must be -1, 0, 1 or 2", -1;
-  if (o.spmv_layout_kt < -2 || o.spmv_layout_kt > 2) return why = "spmv_layout_kt must be -2, -1, 0, 1 or 2", -1;
+  auto bad_layout = [](int v) { return v < -1 || v > 6 || v == 3; };
+  if (bad_layout(o.spmv_layout)) return why = "spmv_layout must be -1, 0, 1, 2, 4, 5 or 6", -1;
+  if (o.spmv_layout_kt != -2 && bad_layout(o.spmv_layout_kt))
+    return why = "spmv_layout_kt must be -2, -1, 0, 1, 2, 4, 5 or 6", -1;
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
@@ -468,28 +471,42 @@ static void choose_layouts(pdlp_handle* h) {
     DevCsr& M = which ? P.KT : P.K;
     const int mode = (which == 1 && h->opt.spmv_layout_kt != -2) ? h->opt.spmv_layout_kt : h->opt.spmv_layout;
     const bool has_pan = M.pan.seg_ptr != nullptr;
-    auto set = [&](int layout, int remap) {
+    // persistent grid: at most CUs x 8 workgroups (a multiple of 8, keeping
+    // each workgroup on one XCD), each taking about four blocks or more
+    auto pgrid = [&](int layout) {
+      const int nb = layout == 1 ? M.pan.nsblocks : M.nblocks;
+      const int want = ((nb + 3) / 4 + 7) / 8 * 8;
+      return std::max(8, std::min(h->persist_grid, want));
+    };
+    auto set = [&](int layout, int remap, int grid) {
       M.layout = layout;
       M.remap = remap;
+      M.grid = grid ? pgrid(layout) : 0;
       M.nred = layout == 1 ? M.rows_grid : M.nblocks;
     };
-    if (mode == 0) { set(0, 0); continue; }
-    if (mode == 2) { set(0, 1); continue; }
-    if (mode == 1) { set(has_pan ? 1 : 0, 0); continue; }
-    set(0, 0);
-    if (h->nnz < (1 << 20)) continue;   // small problems: row blocks
-    const double t0 = time_probe(h, which, 5);
-    int best_l = 0, best_r = 0;
-    double best = t0;
-    set(0, 1);
-    const double t1 = time_probe(h, which, 5);
-    if (t1 < 0.95 * best) { best = t1; best_l = 0; best_r = 1; }
-    if (has_pan) {
-      set(1, 0);
-      const double t2 = time_probe(h, which, 5);
-      if (t2 < 0.95 * best) { best = t2; best_l = 1; best_r = 0; }
+    if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid
+      const int g = (mode & 4) ? 1 : 0;
+      if ((mode & 3) == 0) set(0, 0, g);
+      else if ((mode & 3) == 2) set(0, 1, g);
+      else set(has_pan ? 1 : 0, 0, g);
+      continue;
     }
-    set(best_l, best_r);
+    set(0, 0, 0);
+    if (h->nnz < (1 << 20)) continue;   // small problems: row blocks
+    // candidates: (layout, remap) x (one workgroup per block, persistent grid)
+    double best = time_probe(h, which, 5);
+    int best_l = 0, best_r = 0, best_g = 0;
+    const int cands[3][2] = {{0, 0}, {0, 1}, {1, 0}};
+    for (const auto& c : cands) {
+      if (c[0] == 1 && !has_pan) continue;
+      for (int g : {0, 1}) {
+        if (c[0] == 0 && c[1] == 0 && g == 0) continue;   // the baseline, timed above
+        set(c[0], c[1], g);
+        const double t = time_probe(h, which, 5);
+        if (t < 0.95 * best) { best = t; best_l = c[0]; best_r = c[1]; best_g = g; }
+      }
+    }
+    set(best_l, best_r, best_g);
     h->probe_ms[which] = best;
   }
 }
@@ -755,14 +772,14 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     check(hipMemcpyAsync(dbk, bk.data(), bk.size() * sizeof(RowBlock), kind, s), "upload blocks");
     check(hipMemcpyAsync(dbt, bt.data(), bt.size() * sizeof(RowBlock), kind, s), "upload blocks");
     Params& P = h->P;
-    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m, 0, 0, 0, elem_grid(m), PanelCsr{}};
-    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n, 0, 0, 0, elem_grid(n),
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m, 0, 0, 0, elem_grid(m), 0, PanelCsr{}};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n, 0, 0, 0, elem_grid(n), 0,
                   PanelCsr{}};
     // a panel layout pays when the gathered vector does not fit one XCD's L2;
     // spmv_layout = 1 builds it for any size (tests)
     const int mode_k = opt.spmv_layout, mode_kt = opt.spmv_layout_kt != -2 ? opt.spmv_layout_kt : opt.spmv_layout;
-    const bool want_k = mode_k == 1 || (mode_k == -1 && nnz >= (1 << 20) && n >= (1 << 18));
-    const bool want_kt = mode_kt == 1 || (mode_kt == -1 && nnz >= (1 << 20) && m >= (1 << 18));
+    const bool want_k = (mode_k >= 0 && (mode_k & 3) == 1) || (mode_k == -1 && nnz >= (1 << 20) && n >= (1 << 18));
+    const bool want_kt = (mode_kt >= 0 && (mode_kt & 3) == 1) || (mode_kt == -1 && nnz >= (1 << 20) && m >= (1 << 18));
     {
       std::vector<int32_t> hciT;
       if (want_k) {
@@ -797,6 +814,13 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     }
     check(hipStreamSynchronize(s), "setup sync");
     check(hipGetLastError(), "setup kernels");
+    {
+      hipDeviceProp_t prop;
+      int dev = 0;
+      check(hipGetDevice(&dev), "hipGetDevice");
+      check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+      h->persist_grid = std::max(8, prop.multiProcessorCount * 8);
+    }
     choose_layouts(h);
   } catch (const HipFail& f) {
     return create_failed(h, f);
@@ -872,8 +896,8 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.eta_hat = f->eta_hat;
   I.setup_s = h->setup_s;
   I.solve_s = now_s() - t0;
-  I.layout_k = h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0);
-  I.layout_kt = h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0);
+  I.layout_k = (h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0)) + (h->P.K.grid > 0 ? 4 : 0);
+  I.layout_kt = (h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0)) + (h->P.KT.grid > 0 ? 4 : 0);
 }
 
 extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
@@ -1310,8 +1334,8 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     launch_seg_absmax(count, h->row_off, h->rp, h->val, h->kmax, s);
     check(hipGetLastError(), "per-LP norms");
     Params& P = h->P;
-    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, nullptr, 0, h->m, 0, 0, 0, 0, PanelCsr{}};
-    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, nullptr, 0, h->n, 0, 0, 0, 0, PanelCsr{}};
+    P.K = DevCsr{h->rp, h->ci, h->val, h->valf, nullptr, 0, h->m, 0, 0, 0, 0, 0, PanelCsr{}};
+    P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, nullptr, 0, h->n, 0, 0, 0, 0, 0, PanelCsr{}};
     alloc_iterates(h);
     P.st = nullptr;
     h->bst = h->dalloc<DevState>((size_t)count);

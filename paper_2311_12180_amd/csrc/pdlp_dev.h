@@ -55,6 +55,8 @@ struct DevCsr {
   int32_t remap;          // fused layout: contiguous block ranges per XCD
   int32_t nred;           // reduction partials of a pass over this matrix
   int32_t rows_grid;      // grid of the phase-2 (row-wise) kernels
+  int32_t grid;           // grid of the row-block (phase-1) kernels: 0 = one workgroup per block,
+                          // else a persistent grid (a multiple of 8) looping over the blocks
   PanelCsr pan;
 };
 

@@ -16,9 +16,10 @@ template <typename T>
 __device__ __forceinline__ T sel(int c, T a0, T a1) { return c ? a1 : a0; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; with remap on, each
-// XCD gets a contiguous range of row blocks.
-__device__ __forceinline__ int logical_block(int nb, int remap) {
-  const int i = blockIdx.x;
+// XCD gets a contiguous range of row blocks.  i is the dispatch-order index
+// (blockIdx.x plus a multiple of a grid that is a multiple of 8, so that it
+// stays on the same XCD).
+__device__ __forceinline__ int logical_block(int i, int nb, int remap) {
   if (!remap || nb < 16) return i;
   const int q = nb >> 3, r = nb & 7;
   const int x = i & 7, j = i >> 3;

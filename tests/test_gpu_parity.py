@@ -142,9 +142,10 @@ def test_trajectory_matches_oracle(P, orc, name, period, kmax):
 
 
 @pytest.mark.parametrize("name", ["random_1000x2000", "skewed_3000x6000", "long_rows", "transport_30x40"])
-@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("layout", [1, 2, 4, 5, 6])
 def test_layouts_match_oracle(P, orc, name, layout):
-    """Column panels (1) and XCD-contiguous row blocks (2) follow the oracle's
+    """Column panels (1), XCD-contiguous row blocks (2) and their persistent-grid
+    forms (4, 5, 6) follow the oracle's
     trajectory like the default layout: same decisions, iterates within the
     rounding-order bar, over 100 accepted steps."""
     p = PROBLEMS[name]()
