@@ -19,13 +19,29 @@ namespace pdlp {
 // solution and takes the next LP.  Rows are swept by groups of L lanes (L per
 // LP from the batch schedule: lanes for the rows of K~ and for those of K~').
 
-// Row sweep of one LP's rows [rb, re) with L lanes per row; op.epi runs on the
+constexpr int kBB = 512;    // threads of a batch workgroup (8 wavefronts): one LP at a time
+constexpr int kBT = 4096;   // nonzeros per LDS tile of the batched sweeps (8 per thread)
+constexpr int kBW = kBB / 64;
+
+// Gather from an LDS copy of an LP's slice of a vector (global index i).
+struct LdsGather {
+  const double* v;
+  int base;
+  __device__ void operator()(int i, double* g) const { g[0] = v[i - base]; }
+};
+template <class Op>
+struct OpGather {
+  const Op& op;
+  __device__ void operator()(int i, double* g) const { op.gather(i, g); }
+};
+
+// Row sweep of one LP's rows [rb, re) with L lanes per row; epi runs on the
 // group's first lane.
-template <int NV, typename VT, class Op>
+template <int NV, typename VT, class G, class E>
 __device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                          const VT* __restrict__ v, int rb, int re, int L, const Op& op,
-                                          double* acc) {
-  const int groups = kBlock / L;
+                                          const VT* __restrict__ v, int rb, int re, int L, const G& gather,
+                                          const E& epi) {
+  const int groups = kBB / L;
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   for (int r = rb + grp; r < re; r += groups) {
     double s[NV];
@@ -35,7 +51,7 @@ __device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const 
     for (int e = rp[r] + lane; e < e1; e += L) {
       const double a = (double)v[e];
       double g[NV];
-      op.gather(ci[e], g);
+      gather(ci[e], g);
 #pragma unroll
       for (int k = 0; k < NV; ++k) s[k] += a * g[k];
     }
@@ -43,29 +59,50 @@ __device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const 
 #pragma unroll
       for (int k = 0; k < NV; ++k) s[k] += __shfl_down(s[k], off, L);
     }
-    if (lane == 0) op.epi(r, s, acc);
+    if (lane == 0) epi(r, s);
   }
 }
 
-// One pass of an op over an LP's rows: the LDS-tiled row blocks [b0, b1)
-// when L = 0 (the single-LP sweep), else rows [rb, re) walked with L lanes per row.
-template <int NV, typename VT, class Op>
+// One pass over an LP's rows: its LDS-tiled row blocks [b0, b1) when L = 0
+// (the single-LP sweep at batch width), else rows [rb, re) with L lanes per
+// row.  Ends with a workgroup barrier.
+template <int NV, typename VT, class G, class E>
 __device__ __forceinline__ void sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                       const VT* __restrict__ v, const RowBlock* __restrict__ blocks, int b0, int b1,
-                                      int rb, int re, int L, const Op& op, double* acc, double* lds, double* red) {
+                                      int rb, int re, int L, const G& gather, const E& epi, double* lds,
+                                      double* red) {
   if (L == 0) {
     for (int j = b0; j < b1; ++j) {
-      spmv_block<NV, VT>(rp, ci, v, blocks[j], lds, red, [&](int c, double* g) { op.gather(c, g); },
-                         [&](int r, const double* s) { op.epi(r, s, acc); });
+      // two gathered vectors (the evaluations): load each tile in two halves
+      spmv_block<NV, VT, kBB, kBT, NV>(rp, ci, v, blocks[j], lds, red, gather, epi);
       __syncthreads();
     }
   } else {
-    lane_rows<NV, VT>(rp, ci, v, rb, re, L, op, acc);
+    lane_rows<NV, VT>(rp, ci, v, rb, re, L, gather, epi);
+    __syncthreads();
   }
 }
 
+// Steps of one attempt with the gathered vector taken from global memory
+// (the op's own gather) or from the LP's LDS copy.
+template <typename VT, class Op>
+__device__ __forceinline__ void step_sweep(const DevCsr& M, const VT* v, const RowBlock* blocks, int b0, int b1,
+                                           int rb, int re, int L, const Op& op, double* acc, const double* lvec,
+                                           int lbase, double* lds, double* red) {
+  const auto epi = [&](int r, const double* s) { op.epi(r, s, acc); };
+  if (lvec) sweep<1, VT>(M.rp, M.ci, v, blocks, b0, b1, rb, re, L, LdsGather{lvec, lbase}, epi, lds, red);
+  else sweep<1, VT>(M.rp, M.ci, v, blocks, b0, b1, rb, re, L, OpGather<Op>{op}, epi, lds, red);
+}
+
+template <int NV, class Op>
+__device__ __forceinline__ void plain_sweep(const DevCsr& M, const RowBlock* blocks, int b0, int b1, int rb, int re,
+                                            int L, const Op& op, double* acc, double* lds, double* red) {
+  sweep<NV, double>(M.rp, M.ci, M.v, blocks, b0, b1, rb, re, L, OpGather<Op>{op},
+                    [&](int r, const double* s) { op.epi(r, s, acc); }, lds, red);
+}
+
 __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red,
-                                double* lds) {
+                                double* E, double* lds, double* ly, double* ldx) {
   const int r0 = bp.row_off[b], r1 = bp.row_off[b + 1];
   const int c0 = bp.col_off[b], c1 = bp.col_off[b + 1];
   const int LK = bp.lanes[2 * b], LT = bp.lanes[2 * b + 1];
@@ -73,6 +110,8 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   const Trace tr = b == bp.trace_lp ? p.tr : Trace{};
   const double qn0 = sqrt(bp.norms[4 * b]), cn0 = sqrt(bp.norms[4 * b + 1]);
   const bool f32 = p.use_f32 != 0;
+  // LDS copies of the gathered step vectors when the LP fits (else nullptr)
+  const bool lv = ly != nullptr && r1 - r0 <= bp.lds_m && c1 - c0 <= bp.lds_n;
   if (threadIdx.x == 0) {
     DevState z{};
     *S = z;
@@ -88,7 +127,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   }
   // starting point (as k_init_x / k_init_y)
   const bool warm = bp.warm[b] != 0;
-  for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+  for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
     double v = warm ? bp.wx[j] / p.D2[j] : 0.0;
     if (v < p.l[j]) v = p.l[j];
     if (v > p.u[j]) v = p.u[j];
@@ -99,7 +138,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
     p.x0[j] = v;
     p.dx[j] = 0.0;
   }
-  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
+  for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
     double v = 0.0;
     if (warm) {
       v = (p.le[i] ? -bp.wy[i] : bp.wy[i]) / p.D1[i];
@@ -117,15 +156,15 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   int64_t k_seen = 0, rejected = 0;  // thread 0: accepted steps at the last attempt, rejections since
   for (;;) {
     if (S->need_eval) {
-      // --- evaluation: averages, eq. (kkt) pieces, Section 4.1 quantities
-      double acc[18];
-#pragma unroll
-      for (int k = 0; k < 18; ++k) acc[k] = 0.0;
+      // --- evaluation: averages, eq. (kkt) pieces, Section 4.1 quantities.
+      // Each pass is reduced right after it runs (element by element, as one
+      // block_sum of all 18 would) to keep few accumulators live.
       {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
         const int cur = S->cur, init = S->initial, pend = S->has_pending;
         const double pw = S->pending_w, se = S->sum_eta;
         const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
-        for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+        for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
           const double xj = x[j];
           double xb = xj;
           if (!init && se > 0.0) {
@@ -145,24 +184,37 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
           d = xb - x0j;
           acc[3] += d * d;
         }
+        block_sum<4, kBW>(acc, red);
+        if (threadIdx.x == 0)
+          for (int k = 0; k < 4; ++k) E[k] = acc[k];
       }
-      __syncthreads();
       {
+        double acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
         const EvalRowsOp op(p, S);
-        sweep<2, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 4, lds, red);
+        plain_sweep<2>(p.K, bp.bk, k0, k1, r0, r1, LK, op, acc, lds, red);
+        block_sum<8, kBW>(acc, red);
+        if (threadIdx.x == 0)
+          for (int k = 0; k < 8; ++k) E[4 + k] = acc[k];
       }
-      __syncthreads();
       {
+        double acc[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] = 0.0;
         const EvalColsOp op(p, S);
-        sweep<2, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc + 12, lds, red);
+        plain_sweep<2>(p.KT, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+        block_sum<6, kBW>(acc, red);
+        if (threadIdx.x == 0) {
+          for (int k = 0; k < 6; ++k) E[12 + k] = acc[k];
+          eval_decision(S, p, tr, E, qn0, cn0);
+        }
       }
-      block_sum<18>(acc, red);
-      if (threadIdx.x == 0) eval_decision(S, p, tr, acc, qn0, cn0);
       __syncthreads();
       if (S->restart_flag) {
         const int cur = S->cur, cand = S->cand_avg;
         double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
-        for (int j = c0 + threadIdx.x; j < c1; j += kBlock) {
+        for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
           const double xc = cand ? p.xbar[j] : x[j];
           x[j] = xc;
           p.x0[j] = xc;
@@ -171,26 +223,34 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         __syncthreads();
         const RestartYOp op(p, S);
         double dummy[1];
-        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
-        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, dummy, lds, red);
-        __syncthreads();
+        const auto epi = [&](int r, const double* s) { op.epi(r, s, dummy); };
+        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, OpGather<RestartYOp>{op}, epi, lds, red);
+        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, OpGather<RestartYOp>{op}, epi, lds, red);
         if (threadIdx.x == 0) S->restart_flag = 0;
       }
     } else {
       // --- one attempt of Algorithm 2
       double acc[3] = {0.0, 0.0, 0.0};
+      if (lv) {   // the current y, gathered by the primal sweep
+        const double* __restrict__ y = sel(S->cur, p.y[0], p.y[1]);
+        for (int i = r0 + threadIdx.x; i < r1; i += kBB) ly[i - r0] = y[i];
+        __syncthreads();
+      }
       {
         const PrimalOp op(p, S);
-        if (f32) sweep<1, float>(p.KT.rp, p.KT.ci, p.KT.vf, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
-        else sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+        if (f32) step_sweep(p.KT, p.KT.vf, bp.bt, t0, t1, c0, c1, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
+        else step_sweep(p.KT, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
       }
-      __syncthreads();
+      if (lv) {   // dx = x' - x, gathered by the dual sweep
+        for (int j = c0 + threadIdx.x; j < c1; j += kBB) ldx[j - c0] = p.dx[j];
+        __syncthreads();
+      }
       {
         const DualOp op(p, S);
-        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
-        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lds, red);
+        if (f32) step_sweep(p.K, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
+        else step_sweep(p.K, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
       }
-      block_sum<3>(acc, red);
+      block_sum<3, kBW>(acc, red);
       if (threadIdx.x == 0) {
         step_decision(S, p, tr, acc[0], acc[1], acc[2]);
         rejected = S->k == k_seen ? rejected + 1 : 0;
@@ -214,10 +274,10 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   {
     const OutputOp op(p, S);
     double dummy[1];
-    sweep<1, double>(p.KT.rp, p.KT.ci, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, dummy, lds, red);
+    plain_sweep<1>(p.KT, bp.bt, t0, t1, c0, c1, LT, op, dummy, lds, red);
     const int cur = S->cur, ra = S->ret_avg;
     const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
-    for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
       const double v = p.D1[i] * y[i];
       p.yo[i] = p.le[i] ? -v : v;
     }
@@ -227,19 +287,25 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
 }
 
 // Persistent batch solver: every workgroup takes LPs from the queue until it
-// is empty, so the launch ends when every LP has been solved.
-__global__ __launch_bounds__(kBlock) void k_batch(Params p, BatchParams bp) {
+// is empty, so the launch ends when every LP has been solved.  Dynamic LDS:
+// the tile staging (2 x kBT doubles), then (when bp.lds_m + bp.lds_n > 0)
+// room for an LP's y (lds_m doubles) and dx (lds_n doubles).
+__global__ __launch_bounds__(kBB) void k_batch(Params p, BatchParams bp) {
+  extern __shared__ double dyn[];
   __shared__ DevState S;
-  __shared__ double red[18 * (kBlock / 64)];
-  __shared__ double lds[2 * kTile];
+  __shared__ double red[8 * kBW];
+  __shared__ double E[18];
   __shared__ int slot;
+  double* lds = dyn;
+  double* ly = bp.lds_m + bp.lds_n > 0 ? dyn + 2 * kBT : nullptr;
+  double* ldx = ly ? ly + bp.lds_m : nullptr;
   for (;;) {
     if (threadIdx.x == 0) slot = (int)atomicAdd(bp.queue, 1u);
     __syncthreads();
     const int q = slot;
     __syncthreads();
     if (q >= bp.count) break;
-    batch_solve_one(p, bp, bp.order[q], &S, red, lds);
+    batch_solve_one(p, bp, bp.order[q], &S, red, E, lds, ly, ldx);
   }
 }
 
@@ -278,15 +344,32 @@ __global__ void k_seg_absmax(int nlp, const int32_t* __restrict__ row_off, const
 
 // ---------------------------------------------------------------------------- launchers
 
-void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, const_cast<uint64_t*>(bp.t0));
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBlock), 0, s, p, bp);
+size_t batch_lds_bytes(const BatchParams& bp) {
+  return sizeof(double) * (2 * (size_t)kBT + (size_t)bp.lds_m + (size_t)bp.lds_n);
 }
 
-int batch_occupancy() {
+hipError_t batch_prepare(size_t lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_bytes);
+}
+
+void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, const_cast<uint64_t*>(bp.t0));
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), batch_lds_bytes(bp), s, p, bp);
+}
+
+int batch_occupancy(size_t lds_bytes) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBlock, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBB, lds_bytes) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
+}
+
+int batch_tile() { return kBT; }
+
+int batch_static_lds() {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_batch)) != hipSuccess) return 4096;
+  return (int)a.sharedSizeBytes;
 }
 
 void launch_seg_sumsq(int nlp, const int32_t* off, const double* a, double* out, int stride, int slot, hipStream_t s) {

@@ -29,7 +29,11 @@ void launch_output(const Params& p, hipStream_t s);
 void launch_probe(const Params& p, int which, hipStream_t s);
 void launch_set_limit(DevState* st, int status, hipStream_t s);
 void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s);
-int batch_occupancy();
+int batch_occupancy(size_t lds_bytes);
+size_t batch_lds_bytes(const BatchParams& bp);
+hipError_t batch_prepare(size_t lds_bytes);
+int batch_tile();
+int batch_static_lds();
 void launch_seg_sumsq(int nlp, const int32_t* off, const double* a, double* out, int stride, int slot, hipStream_t s);
 void launch_seg_absmax(int nlp, const int32_t* row_off, const int32_t* rp, const double* v, double* out,
                        hipStream_t s);
@@ -71,15 +75,15 @@ inline void check(hipError_t e, const char* what) {
 }
 
 // Row-block partition of a CSR-like structure (see RowBlock) over rows
-// [begin, end): every row longer than kTile becomes a block of its own, listed
+// [begin, end): every row longer than `tile` becomes a block of its own, listed
 // first so that these heavier blocks are dispatched before the short ones; the
-// runs of short rows between them are cut greedily at kTile nonzeros or
+// runs of short rows between them are cut greedily at `tile` nonzeros or
 // kMaxRows rows.
-std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end) {
+std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end, int tile = kTile) {
   std::vector<RowBlock> longs, shorts;
   int r = begin;
   while (r < end) {
-    if (rp[r + 1] - rp[r] > kTile) {
+    if (rp[r + 1] - rp[r] > tile) {
       longs.push_back(RowBlock{r, r + 1});
       ++r;
       continue;
@@ -88,7 +92,7 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end) {
     int nz = 0;
     while (r < end && r - r0 < kMaxRows) {
       const int len = rp[r + 1] - rp[r];
-      if (len > kTile || nz + len > kTile) break;
+      if (len > tile || nz + len > tile) break;
       nz += len;
       ++r;
     }
@@ -232,6 +236,8 @@ struct pdlp_handle {
   uint32_t* queue = nullptr;
   uint64_t* t0 = nullptr;
   double tick_hz = 0.0;
+  int32_t lds_m = 0, lds_n = 0;   // LDS room for an LP's y and dx in the batched kernel
+  size_t lds_bytes = 0;
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -1173,6 +1179,8 @@ static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter,
   const double ticks = time_limit_s * h->tick_hz;
   bp.ticks = ticks >= 1.8e19 ? 0 : (uint64_t)std::max(1.0, ticks);
   bp.max_reject = 1000;
+  bp.lds_m = h->lds_m;
+  bp.lds_n = h->lds_n;
   bp.eps_rel = eps_rel;
   bp.max_iter = max_iter;
   bp.eps_zero = h->opt.eps_zero;
@@ -1230,7 +1238,7 @@ static void tune_batch(pdlp_handle* h) {
   check(hipGetDevice(&dev), "hipGetDevice");
   check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
   const int cus = std::max(1, prop.multiProcessorCount);
-  const int full = cus * batch_occupancy();
+  const int full = cus * batch_occupancy(h->lds_bytes);
   h->grid = opt.batch_grid > 0 ? opt.batch_grid : std::min(cnt, full);
   auto upload = [&]() {
     check(hipMemcpy(h->lanes, h->lanes_h.data(), h->lanes_h.size(), hipMemcpyHostToDevice), "upload lanes");
@@ -1351,8 +1359,11 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
       std::vector<RowBlock> bk, bt;
       std::vector<int32_t> bko(1, 0), bto(1, 0);
       for (int32_t k = 0; k < count; ++k) {
-        for (const RowBlock& r : partition_rows(H.rp.data(), row_off[(size_t)k], row_off[(size_t)k + 1])) bk.push_back(r);
-        for (const RowBlock& r : partition_rows(hrpT.data(), col_off[(size_t)k], col_off[(size_t)k + 1])) bt.push_back(r);
+        const int tile = batch_tile();
+        for (const RowBlock& r : partition_rows(H.rp.data(), row_off[(size_t)k], row_off[(size_t)k + 1], tile))
+          bk.push_back(r);
+        for (const RowBlock& r : partition_rows(hrpT.data(), col_off[(size_t)k], col_off[(size_t)k + 1], tile))
+          bt.push_back(r);
         bko.push_back((int32_t)bk.size());
         bto.push_back((int32_t)bt.size());
       }
@@ -1375,6 +1386,34 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     check(hipGetDevice(&dev), "hipGetDevice");
     check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
     h->tick_hz = 1000.0 * (khz > 0 ? khz : 100000);
+    // LDS of a batch workgroup: the tile staging, plus the largest LP's y and
+    // dx when they fit in what one workgroup may allocate
+    {
+      hipDeviceProp_t prop;
+      check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+      const size_t limit = std::max<size_t>(prop.sharedMemPerBlock, prop.sharedMemPerBlockOptin);
+      const size_t stat = (size_t)batch_static_lds();
+      int32_t mmax = 0, nmax = 0;
+      for (int32_t k = 0; k < count; ++k) {
+        mmax = std::max(mmax, row_off[(size_t)k + 1] - row_off[(size_t)k]);
+        nmax = std::max(nmax, col_off[(size_t)k + 1] - col_off[(size_t)k]);
+      }
+      BatchParams q{};
+      const size_t base = batch_lds_bytes(q);
+      if (base + stat > limit)
+        throw HipFail{hipErrorInvalidConfiguration, "the batched kernel's LDS tile exceeds the per-workgroup limit"};
+      q.lds_m = mmax;
+      q.lds_n = nmax;
+      if (batch_lds_bytes(q) + stat <= limit && batch_prepare(batch_lds_bytes(q)) == hipSuccess) {
+        h->lds_m = mmax;
+        h->lds_n = nmax;
+      } else {
+        check(batch_prepare(base), "batch LDS attribute");
+      }
+      q.lds_m = h->lds_m;
+      q.lds_n = h->lds_n;
+      h->lds_bytes = batch_lds_bytes(q);
+    }
     check(hipStreamSynchronize(s), "setup sync");
     check(hipGetLastError(), "setup kernels");
     tune_batch(h);

@@ -160,6 +160,7 @@ struct BatchParams {
   const uint64_t* t0;       // wall-clock stamp taken just before the launch
   uint64_t ticks;           // time limit in wall-clock ticks (0: none)
   int64_t max_reject;       // consecutive rejected attempts that count as a numerical failure
+  int32_t lds_m, lds_n;     // LDS room for an LP's y and dx (0, 0: the steps gather from global memory)
   double eps_rel;
   int64_t max_iter;
   double eps_zero;

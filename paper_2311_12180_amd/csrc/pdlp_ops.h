@@ -62,16 +62,16 @@ __device__ __forceinline__ const double* pick<double>(const double* v, const flo
 template <>
 __device__ __forceinline__ const float* pick<float>(const double*, const float* vf) { return vf; }
 
-constexpr int kPer = kTile / kBlock;   // nonzeros per thread in one tile
-
-// Loads of one tile of nonzeros [base, base + count) (count <= kTile): each
+// Loads of one tile of nonzeros [base, base + count) (count <= TILE), for a
+// workgroup of BS threads (TILE / BS nonzeros per thread): each
 // thread first issues all of its column and value loads, then all of its
 // gathers, so a tile costs two memory round trips per thread instead of two
 // per nonzero.  f(e, a, g) receives the tile-relative index, the value and the
 // NV gathered entries.
-template <int NV, typename VT, class G, class F>
+template <int NV, typename VT, int BS = kBlock, int TILE = kTile, class G, class F>
 __device__ __forceinline__ void tile_products(const int32_t* __restrict__ ci, const VT* __restrict__ v, int base,
                                               int count, G&& gather, F&& f) {
+  constexpr int kPer = TILE / BS;
   if (count <= 0) return;
   // Loads are unconditional (past the end they repeat the last entry, an
   // in-bounds index) so the loop body is straight-line code and every load of
@@ -80,7 +80,7 @@ __device__ __forceinline__ void tile_products(const int32_t* __restrict__ ci, co
   double a[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int e = (int)threadIdx.x + u * kBlock;
+    const int e = (int)threadIdx.x + u * BS;
     const int ee = e < count ? e : count - 1;
     col[u] = __builtin_nontemporal_load(&ci[base + ee]);
     a[u] = (double)__builtin_nontemporal_load(&v[base + ee]);
@@ -90,49 +90,57 @@ __device__ __forceinline__ void tile_products(const int32_t* __restrict__ ci, co
   for (int u = 0; u < kPer; ++u) gather(col[u], g[u]);
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int e = (int)threadIdx.x + u * kBlock;
+    const int e = (int)threadIdx.x + u * BS;
     if (e < count) f(e, a[u], g[u]);
   }
 }
 
-// Row block driver over a CSR-like structure (rp, ci, v): runs `epi(row,
-// sums)` exactly once for every row of the block.  Short rows: the products
-// val * gathered vector(s) are staged in LDS (coalesced matrix stream), then
-// each row is summed by L lanes (L = largest power of two <= 64 with
-// L * rows <= kBlock) and the group's first lane runs the epilogue.  A long
-// row: the workgroup sweeps it tile by tile (thread t takes entries t, t +
-// kBlock, ...), reduces, and thread 0 runs the epilogue.
-template <int NV, typename VT, class G, class E>
+// Row block driver over a CSR-like structure (rp, ci, v) for a workgroup of
+// BS threads and tiles of TILE nonzeros: runs `epi(row, sums)` exactly once for
+// every row of the block.  Short rows: the products val * gathered vector(s)
+// are staged in LDS (coalesced matrix stream), then each row is summed by L
+// lanes (L = largest power of two <= 64 with L * rows <= BS) and the group's
+// first lane runs the epilogue.  A long row: the workgroup sweeps it tile by
+// tile (thread t takes entries t, t + BS, ...), reduces, and thread 0 runs the
+// epilogue.
+// SPLIT > 1 loads a tile in SPLIT consecutive parts (fewer loads in flight per
+// thread, fewer registers) without changing the tile or the sums.
+template <int NV, typename VT, int BS = kBlock, int TILE = kTile, int SPLIT = 1, class G, class E>
 __device__ __forceinline__ void spmv_block(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                            const VT* __restrict__ v, const RowBlock& rb,
                                            double* __restrict__ lds, double* red, G&& gather, E&& epi) {
+  constexpr int SUB = TILE / SPLIT;
   const int r0 = rb.r0, r1 = rb.r1;
   const int e0 = rp[r0];
   const int ne = rp[r1] - e0;
-  if (ne > kTile) {
+  if (ne > TILE) {
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    for (int base = e0; base < e0 + ne; base += kTile) {
-      const int cnt = min(kTile, e0 + ne - base);
-      tile_products<NV, VT>(ci, v, base, cnt, gather, [&](int, double a, const double* g) {
+    for (int base = e0; base < e0 + ne; base += SUB) {
+      const int cnt = min(SUB, e0 + ne - base);
+      tile_products<NV, VT, BS, SUB>(ci, v, base, cnt, gather, [&](int, double a, const double* g) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) s[k] += a * g[k];
       });
     }
-    block_sum<NV>(s, red);
+    block_sum<NV, BS / 64>(s, red);
     if (threadIdx.x == 0) epi(r0, s);
     return;
   }
-  tile_products<NV, VT>(ci, v, e0, ne, gather, [&](int e, double a, const double* g) {
+  for (int h = 0; h < SPLIT; ++h) {
+    const int off = h * SUB;
+    tile_products<NV, VT, BS, SUB>(ci, v, e0 + off, min(SUB, ne - off), gather,
+                                   [&](int e, double a, const double* g) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds[k * kTile + e] = a * g[k];
-  });
+                                     for (int k = 0; k < NV; ++k) lds[k * TILE + off + e] = a * g[k];
+                                   });
+  }
   __syncthreads();
   const int nr = r1 - r0;
   int L = 64;
-  while (L > 1 && L * nr > kBlock) L >>= 1;
-  const int groups = kBlock / L;
+  while (L > 1 && L * nr > BS) L >>= 1;
+  const int groups = BS / L;
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   for (int r = grp; r < nr; r += groups) {
     const int b0 = rp[r0 + r] - e0, b1 = rp[r0 + r + 1] - e0;
@@ -141,7 +149,7 @@ __device__ __forceinline__ void spmv_block(const int32_t* __restrict__ rp, const
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     for (int e = b0 + lane; e < b1; e += L) {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) s[k] += lds[k * kTile + e];
+      for (int k = 0; k < NV; ++k) s[k] += lds[k * TILE + e];
     }
     for (int off = L >> 1; off > 0; off >>= 1) {
 #pragma unroll
