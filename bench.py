@@ -13,7 +13,8 @@ also carries:
                   against 8 TB/s;
   cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same LP
                   (its first iterations), on the host cores;
-  time_to_tol  -- wall time to rel KKT 1e-4 with the FP64 and the FP32 matrix.
+  time_to_tol  -- wall time to rel KKT 1e-4 with the FP64 and the FP32 matrix and to
+                  1e-8 with the FP64 matrix, and of the 2000 x 2000 transportation LP to 1e-6.
 """
 from __future__ import annotations
 
@@ -346,8 +347,9 @@ def main():
         ttt = {}
         import oracle
         oracle.build()
-        for name, prec in (("fp64", 0), ("fp32_matrix", 1)):
-            h = P.pdlp_create(prob, stream=stream, eps_rel=1e-4, a_precision=prec, time_limit_s=args.ttt_limit)
+        runs = [("fp64_1e-4", 0, 1e-4), ("fp32_matrix_1e-4", 1, 1e-4), ("fp64_1e-8", 0, 1e-8)]
+        for name, prec, eps in runs:
+            h = P.pdlp_create(prob, stream=stream, eps_rel=eps, a_precision=prec, time_limit_s=args.ttt_limit)
             P.pdlp_solve(h)
             x, y, rc, inf = P.pdlp_get_solution(h)
             ev = oracle.evaluate(prob, x, y)
@@ -357,8 +359,23 @@ def main():
                          "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
                          "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
                          "obj_rel_err_vs_known_optimum": abs(inf["primal_obj"] - obj_star) / (1 + abs(obj_star))}
-            log(f"time to 1e-4 ({name}): {ttt[name]}")
+            log(f"time to {eps:g} ({name}): {ttt[name]}")
             P.pdlp_destroy(h)
+        # the 2000 x 2000 transportation LP (n = 4e6, m = 4000, nnz = 8e6) to 1e-6
+        import lpgen
+        tp = lpgen.config2(0)
+        h = P.pdlp_create(tp, stream=stream, eps_rel=1e-6, time_limit_s=args.ttt_limit)
+        P.pdlp_solve(h)
+        x, y, rc, inf = P.pdlp_get_solution(h)
+        ev = oracle.evaluate(tp, x, y)
+        ttt["transport_2000x2000_1e-6"] = {
+            "status": inf["status_name"], "iterations": inf["iterations"], "attempts": inf["attempts"],
+            "restarts": inf["restarts"], "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
+            "iters_per_s": round(inf["iterations"] / max(inf["solve_s"], 1e-9), 1),
+            "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
+            "primal_obj": inf["primal_obj"], "layout_k_kt": [inf["layout_k"], inf["layout_kt"]]}
+        log(f"transportation to 1e-6: {ttt['transport_2000x2000_1e-6']}")
+        P.pdlp_destroy(h)
 
     batch = None
     if not args.no_batch:

@@ -23,6 +23,13 @@ constexpr int kBB = 512;    // threads of a batch workgroup (8 wavefronts): one 
 constexpr int kBT = 4096;   // nonzeros per LDS tile of the batched sweeps (8 per thread)
 constexpr int kBW = kBB / 64;
 
+// Row pointers of an LP from an LDS copy (global row index r).
+struct LdsRowPtr {
+  const int* p;
+  int base;
+  __device__ int operator[](int r) const { return p[r - base]; }
+};
+
 // Gather from an LDS copy of an LP's slice of a vector (global index i).
 struct LdsGather {
   const double* v;
@@ -37,10 +44,9 @@ struct OpGather {
 
 // Row sweep of one LP's rows [rb, re) with L lanes per row; epi runs on the
 // group's first lane.
-template <int NV, typename VT, class G, class E>
-__device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                          const VT* __restrict__ v, int rb, int re, int L, const G& gather,
-                                          const E& epi) {
+template <int NV, typename VT, class RP, class G, class E>
+__device__ __forceinline__ void lane_rows(const RP& rp, const int32_t* __restrict__ ci, const VT* __restrict__ v,
+                                          int rb, int re, int L, const G& gather, const E& epi) {
   const int groups = kBB / L;
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   for (int r = rb + grp; r < re; r += groups) {
@@ -66,43 +72,63 @@ __device__ __forceinline__ void lane_rows(const int32_t* __restrict__ rp, const 
 // One pass over an LP's rows: its LDS-tiled row blocks [b0, b1) when L = 0
 // (the single-LP sweep at batch width), else rows [rb, re) with L lanes per
 // row.  Ends with a workgroup barrier.
-template <int NV, typename VT, class G, class E>
-__device__ __forceinline__ void sweep(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                      const VT* __restrict__ v, const RowBlock* __restrict__ blocks, int b0, int b1,
-                                      int rb, int re, int L, const G& gather, const E& epi, double* lds,
-                                      double* red) {
+// An LP's view of one matrix: its rows [rb, re), its row blocks, and where
+// its row pointers and block descriptors are read from (LDS copies when the
+// LP fits, else global memory).
+struct LpMat {
+  const int32_t* grp;       // global row pointers
+  const int* lrp;           // LDS copy of rp[rb .. re] (nullptr: use grp)
+  const RowBlock* blocks;   // block descriptors (LDS copy or global), blocks [0, nb)
+  int nb, rb, re;
+};
+
+template <int NV, typename VT, class RP, class G, class E>
+__device__ __forceinline__ void sweep_rp(const RP& rp, const LpMat& L_, const int32_t* __restrict__ ci,
+                                         const VT* __restrict__ v, int L, const G& gather, const E& epi, double* lds,
+                                         double* red) {
   if (L == 0) {
-    for (int j = b0; j < b1; ++j) {
+    for (int j = 0; j < L_.nb; ++j) {
       // two gathered vectors (the evaluations): load each tile in two halves
-      spmv_block<NV, VT, kBB, kBT, NV>(rp, ci, v, blocks[j], lds, red, gather, epi);
+      spmv_block<NV, VT, kBB, kBT, NV>(rp, ci, v, L_.blocks[j], lds, red, gather, epi);
       __syncthreads();
     }
   } else {
-    lane_rows<NV, VT>(rp, ci, v, rb, re, L, gather, epi);
+    lane_rows<NV, VT>(rp, ci, v, L_.rb, L_.re, L, gather, epi);
     __syncthreads();
   }
 }
 
+// One pass over an LP's rows: its LDS-tiled row blocks when L = 0 (the
+// single-LP sweep at batch width), else its rows with L lanes per row.  Ends
+// with a workgroup barrier.
+template <bool LV, int NV, typename VT, class G, class E>
+__device__ __forceinline__ void sweep(const LpMat& M, const int32_t* __restrict__ ci, const VT* __restrict__ v, int L,
+                                      const G& gather, const E& epi, double* lds, double* red) {
+  if constexpr (LV) sweep_rp<NV, VT>(LdsRowPtr{M.lrp, M.rb}, M, ci, v, L, gather, epi, lds, red);
+  else sweep_rp<NV, VT>(M.grp, M, ci, v, L, gather, epi, lds, red);
+}
+
 // Steps of one attempt with the gathered vector taken from global memory
 // (the op's own gather) or from the LP's LDS copy.
-template <typename VT, class Op>
-__device__ __forceinline__ void step_sweep(const DevCsr& M, const VT* v, const RowBlock* blocks, int b0, int b1,
-                                           int rb, int re, int L, const Op& op, double* acc, const double* lvec,
-                                           int lbase, double* lds, double* red) {
+template <bool LV, typename VT, class Op>
+__device__ __forceinline__ void step_sweep(const LpMat& M, const int32_t* ci, const VT* v, int L, const Op& op,
+                                           double* acc, const double* lvec, int lbase, double* lds, double* red) {
   const auto epi = [&](int r, const double* s) { op.epi(r, s, acc); };
-  if (lvec) sweep<1, VT>(M.rp, M.ci, v, blocks, b0, b1, rb, re, L, LdsGather{lvec, lbase}, epi, lds, red);
-  else sweep<1, VT>(M.rp, M.ci, v, blocks, b0, b1, rb, re, L, OpGather<Op>{op}, epi, lds, red);
+  if constexpr (LV) sweep<LV, 1, VT>(M, ci, v, L, LdsGather{lvec, lbase}, epi, lds, red);
+  else sweep<LV, 1, VT>(M, ci, v, L, OpGather<Op>{op}, epi, lds, red);
 }
 
-template <int NV, class Op>
-__device__ __forceinline__ void plain_sweep(const DevCsr& M, const RowBlock* blocks, int b0, int b1, int rb, int re,
-                                            int L, const Op& op, double* acc, double* lds, double* red) {
-  sweep<NV, double>(M.rp, M.ci, M.v, blocks, b0, b1, rb, re, L, OpGather<Op>{op},
-                    [&](int r, const double* s) { op.epi(r, s, acc); }, lds, red);
+template <bool LV, int NV, class Op>
+__device__ __forceinline__ void plain_sweep(const LpMat& M, const DevCsr& D, int L, const Op& op, double* acc,
+                                            double* lds, double* red) {
+  sweep<LV, NV, double>(M, D.ci, D.v, L, OpGather<Op>{op}, [&](int r, const double* s) { op.epi(r, s, acc); },
+                        lds, red);
 }
 
+template <bool LV>
 __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red,
-                                double* E, double* lds, double* ly, double* ldx) {
+                                double* E, double* lds, double* ly, double* ldx, int* lrk, int* lrt, RowBlock* lbk,
+                                RowBlock* lbt) {
   const int r0 = bp.row_off[b], r1 = bp.row_off[b + 1];
   const int c0 = bp.col_off[b], c1 = bp.col_off[b + 1];
   const int LK = bp.lanes[2 * b], LT = bp.lanes[2 * b + 1];
@@ -110,8 +136,18 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   const Trace tr = b == bp.trace_lp ? p.tr : Trace{};
   const double qn0 = sqrt(bp.norms[4 * b]), cn0 = sqrt(bp.norms[4 * b + 1]);
   const bool f32 = p.use_f32 != 0;
-  // LDS copies of the gathered step vectors when the LP fits (else nullptr)
-  const bool lv = ly != nullptr && r1 - r0 <= bp.lds_m && c1 - c0 <= bp.lds_n;
+  // LDS copies of the gathered step vectors, row pointers and block
+  // descriptors when the LP fits (else everything is read from global memory)
+  // (LV: the launch sized the LDS for the batch's largest LP, so every LP fits)
+  constexpr bool lv = LV;
+  if (lv) {
+    for (int i = threadIdx.x; i <= r1 - r0; i += kBB) lrk[i] = p.K.rp[r0 + i];
+    for (int j = threadIdx.x; j <= c1 - c0; j += kBB) lrt[j] = p.KT.rp[c0 + j];
+    for (int q = threadIdx.x; q < k1 - k0; q += kBB) lbk[q] = bp.bk[k0 + q];
+    for (int q = threadIdx.x; q < t1 - t0; q += kBB) lbt[q] = bp.bt[t0 + q];
+  }
+  const LpMat mk{p.K.rp, lv ? lrk : nullptr, lv ? lbk : bp.bk + k0, k1 - k0, r0, r1};
+  const LpMat mt{p.KT.rp, lv ? lrt : nullptr, lv ? lbt : bp.bt + t0, t1 - t0, c0, c1};
   if (threadIdx.x == 0) {
     DevState z{};
     *S = z;
@@ -193,7 +229,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] = 0.0;
         const EvalRowsOp op(p, S);
-        plain_sweep<2>(p.K, bp.bk, k0, k1, r0, r1, LK, op, acc, lds, red);
+        plain_sweep<LV, 2>(mk, p.K, LK, op, acc, lds, red);
         block_sum<8, kBW>(acc, red);
         if (threadIdx.x == 0)
           for (int k = 0; k < 8; ++k) E[4 + k] = acc[k];
@@ -203,7 +239,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
 #pragma unroll
         for (int k = 0; k < 6; ++k) acc[k] = 0.0;
         const EvalColsOp op(p, S);
-        plain_sweep<2>(p.KT, bp.bt, t0, t1, c0, c1, LT, op, acc, lds, red);
+        plain_sweep<LV, 2>(mt, p.KT, LT, op, acc, lds, red);
         block_sum<6, kBW>(acc, red);
         if (threadIdx.x == 0) {
           for (int k = 0; k < 6; ++k) E[12 + k] = acc[k];
@@ -224,8 +260,8 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         const RestartYOp op(p, S);
         double dummy[1];
         const auto epi = [&](int r, const double* s) { op.epi(r, s, dummy); };
-        if (f32) sweep<1, float>(p.K.rp, p.K.ci, p.K.vf, bp.bk, k0, k1, r0, r1, LK, OpGather<RestartYOp>{op}, epi, lds, red);
-        else sweep<1, double>(p.K.rp, p.K.ci, p.K.v, bp.bk, k0, k1, r0, r1, LK, OpGather<RestartYOp>{op}, epi, lds, red);
+        if (f32) sweep<LV, 1, float>(mk, p.K.ci, p.K.vf, LK, OpGather<RestartYOp>{op}, epi, lds, red);
+        else sweep<LV, 1, double>(mk, p.K.ci, p.K.v, LK, OpGather<RestartYOp>{op}, epi, lds, red);
         if (threadIdx.x == 0) S->restart_flag = 0;
       }
     } else {
@@ -238,8 +274,8 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
       }
       {
         const PrimalOp op(p, S);
-        if (f32) step_sweep(p.KT, p.KT.vf, bp.bt, t0, t1, c0, c1, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
-        else step_sweep(p.KT, p.KT.v, bp.bt, t0, t1, c0, c1, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
+        if (f32) step_sweep<LV>(mt, p.KT.ci, p.KT.vf, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
+        else step_sweep<LV>(mt, p.KT.ci, p.KT.v, LT, op, acc, lv ? ly : nullptr, r0, lds, red);
       }
       if (lv) {   // dx = x' - x, gathered by the dual sweep
         for (int j = c0 + threadIdx.x; j < c1; j += kBB) ldx[j - c0] = p.dx[j];
@@ -247,8 +283,8 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
       }
       {
         const DualOp op(p, S);
-        if (f32) step_sweep(p.K, p.K.vf, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
-        else step_sweep(p.K, p.K.v, bp.bk, k0, k1, r0, r1, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
+        if (f32) step_sweep<LV>(mk, p.K.ci, p.K.vf, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
+        else step_sweep<LV>(mk, p.K.ci, p.K.v, LK, op, acc + 1, lv ? ldx : nullptr, c0, lds, red);
       }
       block_sum<3, kBW>(acc, red);
       if (threadIdx.x == 0) {
@@ -274,7 +310,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   {
     const OutputOp op(p, S);
     double dummy[1];
-    plain_sweep<1>(p.KT, bp.bt, t0, t1, c0, c1, LT, op, dummy, lds, red);
+    plain_sweep<LV, 1>(mt, p.KT, LT, op, dummy, lds, red);
     const int cur = S->cur, ra = S->ret_avg;
     const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
     for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
@@ -288,8 +324,10 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
 
 // Persistent batch solver: every workgroup takes LPs from the queue until it
 // is empty, so the launch ends when every LP has been solved.  Dynamic LDS:
-// the tile staging (2 x kBT doubles), then (when bp.lds_m + bp.lds_n > 0)
-// room for an LP's y (lds_m doubles) and dx (lds_n doubles).
+// the tile staging (2 x kBT doubles), then (when bp.lds_m > 0) room for an
+// LP's y (lds_m doubles), dx (lds_n doubles), row pointers of K~ and K~'
+// (lds_m + 1, lds_n + 1 ints) and block descriptors (lds_bk, lds_bt).
+template <bool LV>
 __global__ __launch_bounds__(kBB) void k_batch(Params p, BatchParams bp) {
   extern __shared__ double dyn[];
   __shared__ DevState S;
@@ -297,15 +335,19 @@ __global__ __launch_bounds__(kBB) void k_batch(Params p, BatchParams bp) {
   __shared__ double E[18];
   __shared__ int slot;
   double* lds = dyn;
-  double* ly = bp.lds_m + bp.lds_n > 0 ? dyn + 2 * kBT : nullptr;
+  double* ly = bp.lds_m > 0 ? dyn + 2 * kBT : nullptr;
   double* ldx = ly ? ly + bp.lds_m : nullptr;
+  int* lrk = ly ? reinterpret_cast<int*>(ldx + bp.lds_n) : nullptr;
+  int* lrt = ly ? lrk + bp.lds_m + 1 : nullptr;
+  RowBlock* lbk = ly ? reinterpret_cast<RowBlock*>(lrt + bp.lds_n + 1) : nullptr;
+  RowBlock* lbt = ly ? lbk + bp.lds_bk : nullptr;
   for (;;) {
     if (threadIdx.x == 0) slot = (int)atomicAdd(bp.queue, 1u);
     __syncthreads();
     const int q = slot;
     __syncthreads();
     if (q >= bp.count) break;
-    batch_solve_one(p, bp, bp.order[q], &S, red, E, lds, ly, ldx);
+    batch_solve_one<LV>(p, bp, bp.order[q], &S, red, E, lds, ly, ldx, lrk, lrt, lbk, lbt);
   }
 }
 
@@ -345,22 +387,30 @@ __global__ void k_seg_absmax(int nlp, const int32_t* __restrict__ row_off, const
 // ---------------------------------------------------------------------------- launchers
 
 size_t batch_lds_bytes(const BatchParams& bp) {
-  return sizeof(double) * (2 * (size_t)kBT + (size_t)bp.lds_m + (size_t)bp.lds_n);
+  size_t b = sizeof(double) * 2 * (size_t)kBT;
+  if (bp.lds_m > 0)
+    b += sizeof(double) * ((size_t)bp.lds_m + bp.lds_n) + sizeof(int) * ((size_t)bp.lds_m + bp.lds_n + 2) +
+         sizeof(RowBlock) * ((size_t)bp.lds_bk + bp.lds_bt);
+  return b;
 }
 
 hipError_t batch_prepare(size_t lds_bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds_bytes);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch<false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batch<true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, const_cast<uint64_t*>(bp.t0));
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), batch_lds_bytes(bp), s, p, bp);
+  if (bp.lds_m > 0) hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(kBB), batch_lds_bytes(bp), s, p, bp);
+  else hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(kBB), batch_lds_bytes(bp), s, p, bp);
 }
 
 int batch_occupancy(size_t lds_bytes) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBB, lds_bytes) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true>, kBB, lds_bytes) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -368,7 +418,7 @@ int batch_tile() { return kBT; }
 
 int batch_static_lds() {
   hipFuncAttributes a{};
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_batch)) != hipSuccess) return 4096;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_batch<true>)) != hipSuccess) return 4096;
   return (int)a.sharedSizeBytes;
 }
 

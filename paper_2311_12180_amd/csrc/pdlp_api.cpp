@@ -236,7 +236,9 @@ struct pdlp_handle {
   uint32_t* queue = nullptr;
   uint64_t* t0 = nullptr;
   double tick_hz = 0.0;
-  int32_t lds_m = 0, lds_n = 0;   // LDS room for an LP's y and dx in the batched kernel
+  int32_t lds_m = 0, lds_n = 0;   // LDS room for an LP's vectors and row pointers in the batched kernel
+  int32_t lds_bk = 0, lds_bt = 0; // ... and its block descriptors
+  int32_t max_bk = 0, max_bt = 0; // most row blocks of one LP
   size_t lds_bytes = 0;
 
   template <typename T>
@@ -1181,6 +1183,8 @@ static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter,
   bp.max_reject = 1000;
   bp.lds_m = h->lds_m;
   bp.lds_n = h->lds_n;
+  bp.lds_bk = h->lds_bk;
+  bp.lds_bt = h->lds_bt;
   bp.eps_rel = eps_rel;
   bp.max_iter = max_iter;
   bp.eps_zero = h->opt.eps_zero;
@@ -1359,6 +1363,7 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
       std::vector<RowBlock> bk, bt;
       std::vector<int32_t> bko(1, 0), bto(1, 0);
       for (int32_t k = 0; k < count; ++k) {
+        const size_t nk0 = bk.size(), nt0 = bt.size();
         const int tile = batch_tile();
         for (const RowBlock& r : partition_rows(H.rp.data(), row_off[(size_t)k], row_off[(size_t)k + 1], tile))
           bk.push_back(r);
@@ -1366,6 +1371,8 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
           bt.push_back(r);
         bko.push_back((int32_t)bk.size());
         bto.push_back((int32_t)bt.size());
+        h->max_bk = std::max(h->max_bk, (int32_t)(bk.size() - nk0));
+        h->max_bt = std::max(h->max_bt, (int32_t)(bt.size() - nt0));
       }
       h->bk = h->dalloc<RowBlock>(bk.size());
       h->bt = h->dalloc<RowBlock>(bt.size());
@@ -1404,14 +1411,20 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
         throw HipFail{hipErrorInvalidConfiguration, "the batched kernel's LDS tile exceeds the per-workgroup limit"};
       q.lds_m = mmax;
       q.lds_n = nmax;
+      q.lds_bk = h->max_bk;
+      q.lds_bt = h->max_bt;
       if (batch_lds_bytes(q) + stat <= limit && batch_prepare(batch_lds_bytes(q)) == hipSuccess) {
         h->lds_m = mmax;
         h->lds_n = nmax;
+        h->lds_bk = h->max_bk;
+        h->lds_bt = h->max_bt;
       } else {
         check(batch_prepare(base), "batch LDS attribute");
       }
       q.lds_m = h->lds_m;
       q.lds_n = h->lds_n;
+      q.lds_bk = h->lds_bk;
+      q.lds_bt = h->lds_bt;
       h->lds_bytes = batch_lds_bytes(q);
     }
     check(hipStreamSynchronize(s), "setup sync");

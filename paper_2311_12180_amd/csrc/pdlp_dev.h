@@ -160,7 +160,8 @@ struct BatchParams {
   const uint64_t* t0;       // wall-clock stamp taken just before the launch
   uint64_t ticks;           // time limit in wall-clock ticks (0: none)
   int64_t max_reject;       // consecutive rejected attempts that count as a numerical failure
-  int32_t lds_m, lds_n;     // LDS room for an LP's y and dx (0, 0: the steps gather from global memory)
+  int32_t lds_m, lds_n;     // LDS room for an LP's y, dx and row pointers (0, 0: all from global memory)
+  int32_t lds_bk, lds_bt;   // LDS room for an LP's block descriptors of K~, K~'
   double eps_rel;
   int64_t max_iter;
   double eps_zero;

@@ -105,8 +105,9 @@ __device__ __forceinline__ void tile_products(const int32_t* __restrict__ ci, co
 // epilogue.
 // SPLIT > 1 loads a tile in SPLIT consecutive parts (fewer loads in flight per
 // thread, fewer registers) without changing the tile or the sums.
-template <int NV, typename VT, int BS = kBlock, int TILE = kTile, int SPLIT = 1, class G, class E>
-__device__ __forceinline__ void spmv_block(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+// `rp` is the row-pointer array, or any object with rp[r] (an LDS copy).
+template <int NV, typename VT, int BS = kBlock, int TILE = kTile, int SPLIT = 1, class RP, class G, class E>
+__device__ __forceinline__ void spmv_block(const RP& rp, const int32_t* __restrict__ ci,
                                            const VT* __restrict__ v, const RowBlock& rb,
                                            double* __restrict__ lds, double* red, G&& gather, E&& epi) {
   constexpr int SUB = TILE / SPLIT;
