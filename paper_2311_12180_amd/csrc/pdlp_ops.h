@@ -145,13 +145,34 @@ __device__ __forceinline__ void spmv_block(const RP& rp, const int32_t* __restri
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   for (int r = grp; r < nr; r += groups) {
     const int b0 = rp[r0 + r] - e0, b1 = rp[r0 + r + 1] - e0;
+    // U independent partial sums per lane (8 for one gathered vector, 4 for
+    // two), so the LDS reads of a lane overlap; added pairwise in a fixed order
+    constexpr int U = NV == 1 ? 8 : 4;
+    double p[U][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) p[u][k] = 0.0;
+    int e = b0 + lane;
+    for (; e + (U - 1) * L < b1; e += U * L) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) p[u][k] += lds[k * TILE + e + u * L];
+    }
+    for (; e < b1; e += L) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) p[0][k] += lds[k * TILE + e];
+    }
+#pragma unroll
+    for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) p[u][k] += p[u + w][k];
     double s[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    for (int e = b0 + lane; e < b1; e += L) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) s[k] += lds[k * TILE + e];
-    }
+    for (int k = 0; k < NV; ++k) s[k] = p[0][k];
     for (int off = L >> 1; off > 0; off >>= 1) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) s[k] += __shfl_down(s[k], off, L);
