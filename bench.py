@@ -127,6 +127,7 @@ def batch_section(P, stream, count: int, eps: float, sample: int):
     att = np.array([i["attempts"] for i in infos], np.int64)
     ev = np.array([i["evaluations"] for i in infos], np.int64)
     status = [i["status_name"] for i in infos]
+    handed = int(sum(1 for i in infos if i["handoff_k"] > 0))
     nnz = np.array([p.nnz for p in probs], np.float64)
     mm = np.array([p.m for p in probs], np.float64)
     nn = np.array([p.n for p in probs], np.float64)
@@ -161,6 +162,7 @@ def batch_section(P, stream, count: int, eps: float, sample: int):
             "solve_s": round(solve_s, 4), "lps_per_s": round(count / solve_s, 1),
             "optimal": status.count("OPTIMAL"), "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
             "lp_iters_per_s": round(float(its.sum() / solve_s), 1),
+            "handed_off": {"after_steps": 2048, "streams": 8, "lps": handed},
             "algorithmic_GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBPS, 4),
             "schedule": {"grid": int(grid), "lanes_k_kt_counts": [[int(a), int(b), int(c)]
                                                                  for (a, b), c in zip(u.tolist(), cnt.tolist())]},

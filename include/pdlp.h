@@ -108,6 +108,13 @@ typedef struct {
                                  timing (default) */
   int32_t spmv_layout_kt;     /* -2: K' follows spmv_layout (default); -1, 0, 1, 2: as spmv_layout,
                                  for K' alone */
+  int32_t batch_handoff;      /* batch handles: an LP that has taken this many accepted steps stops
+                                 in the persistent launch at its next evaluation and is finished by
+                                 the single-LP kernels, several such LPs at once on their own
+                                 streams (same state, same iteration; default 2048, 0 = never) */
+  int32_t handoff_streams;    /* batch handles: LPs finished at once after the hand-off, each on a
+                                 stream of its own (1..16, default 8), the LPs farthest from the
+                                 tolerance first */
 } pdlp_options;
 
 typedef struct {
@@ -126,6 +133,8 @@ typedef struct {
                                    the create-time timing chose a persistent grid for the row-block
                                    kernels); for an LP of a batch: its sweeps of K and K' (see
                                    pdlp_batch_schedule) */
+  int64_t handoff_k;          /* an LP of a batch: accepted steps when the single-LP kernels took
+                                 it over (0: it ended in the persistent launch) */
 } pdlp_info;
 
 /* Scaled-space state of the current iterate (for parity checks and resume). */
@@ -231,9 +240,13 @@ int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pdlp_options*
 int pdlp_set_warm_start_batch(pdlp_handle* h, int32_t idx, const double* x0, const double* y0, double omega0);
 
 /* Solve every LP of the batch from its starting point in one persistent launch;
- * the host waits once.  time_limit_s bounds the whole launch (an LP still
- * running then ends with PDLP_TIME_LIMIT); an LP whose attempts are rejected
- * 1000 times in a row ends with PDLP_NUMERICAL_ERROR. */
+ * LPs still running after batch_handoff accepted steps are then finished by the
+ * single-LP kernels (handoff_streams at a time, each on a library-owned stream, over
+ * its own slice of the packed arrays), and the call returns when every LP has
+ * ended.  time_limit_s bounds the whole solve (an LP still running then ends
+ * with PDLP_TIME_LIMIT); an LP whose attempts are rejected 1000 times in a row
+ * in the persistent launch, or that accepts no step over 64 polls after the
+ * hand-off, ends with PDLP_NUMERICAL_ERROR. */
 int pdlp_solve_batch(pdlp_handle* h);
 
 /* Solution of LP idx (x[n_idx], y[m_idx], reduced_cost[n_idx], *info), or of

@@ -264,6 +264,12 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         else sweep<LV, 1, double>(mk, p.K.ci, p.K.v, LK, OpGather<RestartYOp>{op}, epi, lds, red);
         if (threadIdx.x == 0) S->restart_flag = 0;
       }
+      // hand a long-running LP to the single-LP kernels at this clean point
+      // (right after an evaluation, its state complete in S and global memory)
+      if (threadIdx.x == 0 && bp.pause_at > 0 && !S->done && S->k >= bp.pause_at) {
+        S->status = kPaused;
+        S->done = 1;
+      }
     } else {
       // --- one attempt of Algorithm 2
       double acc[3] = {0.0, 0.0, 0.0};
@@ -306,8 +312,9 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
     __syncthreads();
     if (S->done) break;
   }
-  // --- output of this LP (as the output op and k_output_y)
-  {
+  // --- output of this LP (as the output op and k_output_y); a paused LP gets
+  // its output from the single-LP kernels that finish it
+  if (S->status != kPaused) {
     const OutputOp op(p, S);
     double dummy[1];
     plain_sweep<LV, 1>(mt, p.KT, LT, op, dummy, lds, red);

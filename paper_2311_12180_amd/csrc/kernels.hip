@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
   const double pw = st->pending_w, se = st->sum_eta;
   const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < p.n; j += gridDim.x * kBlock) {
+  for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gridDim.x * kBlock) {
     const double xj = x[j];
     double xb = xj;
     if (!init && se > 0.0) {
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_restart_x(Params p) {
   if (!st->restart_flag) return;
   const int cur = st->cur, cand = st->cand_avg;
   double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < p.n; j += gridDim.x * kBlock) {
+  for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gridDim.x * kBlock) {
     const double xc = cand ? p.xbar[j] : x[j];
     x[j] = xc;
     p.x0[j] = xc;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_restart_x(Params p) {
 // Starting point: proj_X(x_start), proj_Y(y_start) in the scaled space; the
 // user start (if any) is unscaled: x~ = x / D2, y~ = (LE ? -y : y) / D1.
 __global__ __launch_bounds__(kBlock) void k_init_x(Params p, const double* __restrict__ xs) {
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < p.n; j += gridDim.x * kBlock) {
+  for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gridDim.x * kBlock) {
     double v = xs ? xs[j] / p.D2[j] : 0.0;
     if (v < p.l[j]) v = p.l[j];
     if (v > p.u[j]) v = p.u[j];
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_init_x(Params p, const double* __res
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_y(Params p, const double* __restrict__ ys) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < p.m; i += gridDim.x * kBlock) {
+  for (int i = p.row_base + blockIdx.x * kBlock + threadIdx.x; i < p.row_base + p.m; i += gridDim.x * kBlock) {
     double v = 0.0;
     if (ys) {
       v = (p.le[i] ? -ys[i] : ys[i]) / p.D1[i];
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_output_y(Params p) {
   const DevState* st = p.st;
   const int cur = st->cur, ra = st->ret_avg;
   const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < p.m; i += gridDim.x * kBlock) {
+  for (int i = p.row_base + blockIdx.x * kBlock + threadIdx.x; i < p.row_base + p.m; i += gridDim.x * kBlock) {
     const double v = p.D1[i] * y[i];
     p.yo[i] = p.le[i] ? -v : v;
   }

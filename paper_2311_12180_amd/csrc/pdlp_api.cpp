@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pdlp.h"
@@ -240,6 +241,20 @@ struct pdlp_handle {
   int32_t lds_bk = 0, lds_bt = 0; // ... and its block descriptors
   int32_t max_bk = 0, max_bt = 0; // most row blocks of one LP
   size_t lds_bytes = 0;
+  // hand-off: every LP's row blocks in the single-LP tiling (kTile), and the
+  // streams on which LPs paused by the persistent launch are finished
+  RowBlock *hk = nullptr, *ht = nullptr;
+  std::vector<int32_t> hk_off, ht_off;
+  int32_t max_hk = 1, max_ht = 1;
+  std::vector<double> norms_h;
+  std::vector<int64_t> handoff_h;
+  struct Lane {
+    hipStream_t s = nullptr;
+    double *pa = nullptr, *pb = nullptr, *pe0 = nullptr, *pe1 = nullptr, *pe2 = nullptr;
+    DevState* hst[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+  };
+  std::vector<Lane> lanes_ho;
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -260,6 +275,14 @@ struct pdlp_handle {
     graph = nullptr;
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e), e = nullptr;
+    for (Lane& L : lanes_ho) {
+      if (L.s) (void)hipStreamSynchronize(L.s);
+      for (auto& e : L.ev)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+      if (L.s) (void)hipStreamDestroy(L.s);
+      L.s = nullptr;
+    }
+    lanes_ho.clear();
     if (stream) (void)hipStreamSynchronize(stream);
     for (void* p : dev_allocs) (void)hipFree(p);
     dev_allocs.clear();
@@ -302,6 +325,8 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->spmv_layout_kt = -2;
   o->batch_lanes = 0;
   o->batch_grid = 0;
+  o->batch_handoff = 2048;
+  o->handoff_streams = 8;
   return PDLP_OK;
 }
 
@@ -327,6 +352,8 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
+  if (o.batch_handoff < 0) return why = "batch_handoff must be >= 0", -1;
+  if (o.handoff_streams < 1 || o.handoff_streams > 16) return why = "handoff_streams must be in 1..16", -1;
   return 0;
 }
 
@@ -1156,7 +1183,8 @@ int size_class(int32_t rows) { return rows < 256 ? 0 : (rows < 1024 ? 1 : 2); }
 
 }  // namespace
 
-static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
+static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s,
+                               int64_t pause_at = 0) {
   hipStream_t s = h->stream;
   BatchParams bp{};
   bp.count = h->count;
@@ -1181,6 +1209,7 @@ static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter,
   const double ticks = time_limit_s * h->tick_hz;
   bp.ticks = ticks >= 1.8e19 ? 0 : (uint64_t)std::max(1.0, ticks);
   bp.max_reject = 1000;
+  bp.pause_at = pause_at;
   bp.lds_m = h->lds_m;
   bp.lds_n = h->lds_n;
   bp.lds_bk = h->lds_bk;
@@ -1382,6 +1411,30 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
       if (!bt.empty()) check(hipMemcpy(h->bt, bt.data(), bt.size() * sizeof(RowBlock), kind), "upload blocks");
       check(hipMemcpy(h->bk_off, bko.data(), bko.size() * 4, kind), "upload block offsets");
       check(hipMemcpy(h->bt_off, bto.data(), bto.size() * 4, kind), "upload block offsets");
+      // the same rows in the tiling of the single-LP kernels (for the hand-off);
+      // an LP without rows gets one empty block
+      bk.clear();
+      bt.clear();
+      h->hk_off.assign(1, 0);
+      h->ht_off.assign(1, 0);
+      for (int32_t k = 0; k < count; ++k) {
+        const int32_t i0 = row_off[(size_t)k], i1 = row_off[(size_t)k + 1];
+        const int32_t j0 = col_off[(size_t)k], j1 = col_off[(size_t)k + 1];
+        std::vector<RowBlock> a = partition_rows(H.rp.data(), i0, i1);
+        if (a.empty()) a.push_back(RowBlock{i0, i0});
+        std::vector<RowBlock> c = partition_rows(hrpT.data(), j0, j1);
+        if (c.empty()) c.push_back(RowBlock{j0, j0});
+        bk.insert(bk.end(), a.begin(), a.end());
+        bt.insert(bt.end(), c.begin(), c.end());
+        h->hk_off.push_back((int32_t)bk.size());
+        h->ht_off.push_back((int32_t)bt.size());
+        h->max_hk = std::max(h->max_hk, (int32_t)a.size());
+        h->max_ht = std::max(h->max_ht, (int32_t)c.size());
+      }
+      h->hk = h->dalloc<RowBlock>(bk.size());
+      h->ht = h->dalloc<RowBlock>(bt.size());
+      check(hipMemcpy(h->hk, bk.data(), bk.size() * sizeof(RowBlock), kind), "upload blocks");
+      check(hipMemcpy(h->ht, bt.data(), bt.size() * sizeof(RowBlock), kind), "upload blocks");
     }
     // queue order: most nonzeros first, so that the long solves start early
     std::vector<int32_t> ord((size_t)count);
@@ -1429,6 +1482,9 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     }
     check(hipStreamSynchronize(s), "setup sync");
     check(hipGetLastError(), "setup kernels");
+    h->norms_h.resize(4 * (size_t)count);
+    check(hipMemcpy(h->norms_h.data(), h->norms, h->norms_h.size() * 8, hipMemcpyDeviceToHost), "read norms");
+    h->handoff_h.assign((size_t)count, 0);
     tune_batch(h);
   } catch (const HipFail& f) {
     return create_failed(h, f);
@@ -1467,6 +1523,192 @@ extern "C" int pdlp_set_warm_start_batch(pdlp_handle* h, int32_t idx, const doub
   return PDLP_OK;
 }
 
+// ---------------------------------------------------------------------------- hand-off
+
+// Params of the single-LP kernels for LP b of a batch: the packed arrays, this
+// LP's row blocks, its row and column ranges, its state and partials.
+static Params handoff_params(const pdlp_handle* h, int32_t b, const pdlp_handle::Lane& L) {
+  Params sp = h->P;
+  const int32_t i0 = h->row_off_h[(size_t)b], i1 = h->row_off_h[(size_t)b + 1];
+  const int32_t j0 = h->col_off_h[(size_t)b], j1 = h->col_off_h[(size_t)b + 1];
+  const int32_t nk = h->hk_off[(size_t)b + 1] - h->hk_off[(size_t)b];
+  const int32_t nt = h->ht_off[(size_t)b + 1] - h->ht_off[(size_t)b];
+  sp.m = i1 - i0;
+  sp.n = j1 - j0;
+  sp.row_base = i0;
+  sp.col_base = j0;
+  sp.K.blocks = h->hk + h->hk_off[(size_t)b];
+  sp.K.nblocks = nk;
+  sp.K.nred = nk;
+  sp.K.nrows = sp.m;
+  sp.K.layout = sp.K.remap = sp.K.grid = 0;
+  sp.K.rows_grid = elem_grid(sp.m);
+  sp.KT.blocks = h->ht + h->ht_off[(size_t)b];
+  sp.KT.nblocks = nt;
+  sp.KT.nred = nt;
+  sp.KT.nrows = sp.n;
+  sp.KT.layout = sp.KT.remap = sp.KT.grid = 0;
+  sp.KT.rows_grid = elem_grid(sp.n);
+  sp.partA = L.pa;
+  sp.partB = L.pb;
+  sp.partE0 = L.pe0;
+  sp.partE1 = L.pe1;
+  sp.partE2 = L.pe2;
+  sp.st = h->bst + b;
+  if (!(h->opt.trace > 0 && b == 0)) sp.tr = Trace{};
+  sp.qnorm0 = std::sqrt(h->norms_h[4 * (size_t)b]);
+  sp.cnorm0 = std::sqrt(h->norms_h[4 * (size_t)b + 1]);
+  return sp;
+}
+
+static void handoff_lanes(pdlp_handle* h, size_t want) {
+  while (h->lanes_ho.size() < want) {
+    h->lanes_ho.emplace_back();
+    pdlp_handle::Lane& L = h->lanes_ho.back();
+    check(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking), "hipStreamCreate");
+    L.pa = h->dalloc<double>((size_t)h->max_ht);
+    L.pb = h->dalloc<double>(2 * (size_t)h->max_hk);
+    L.pe0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
+    L.pe1 = h->dalloc<double>(8 * (size_t)h->max_hk);
+    L.pe2 = h->dalloc<double>(6 * (size_t)h->max_ht);
+    for (int k = 0; k < 2; ++k) {
+      void* hp = nullptr;
+      check(hipHostMalloc(&hp, sizeof(DevState), hipHostMallocDefault), "hipHostMalloc");
+      h->host_allocs.push_back(hp);
+      L.hst[k] = static_cast<DevState*>(hp);
+      check(hipEventCreateWithFlags(&L.ev[k], hipEventDisableTiming), "hipEventCreate");
+    }
+  }
+  if (h->opt.graph && !h->cap_stream)
+    check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+}
+
+// Finish the LPs that the persistent launch paused (status kPaused, state in
+// bst) with the single-LP kernels: the same state, ops and decisions, each LP
+// on one of up to handoff_streams streams, polled as in pdlp_solve.
+static void run_handoff(pdlp_handle* h, const std::vector<int32_t>& paused, double t0) {
+  const size_t nl = std::min<size_t>(paused.size(), (size_t)h->opt.handoff_streams);
+  handoff_lanes(h, nl);
+  const int P = h->opt.eval_period;
+  const int slots = P + std::max(2, P / 8), rounds = std::max(1, 64 / P);
+  const int per = h->opt.poll_every;
+  struct Run {
+    int32_t b = -1;
+    Params sp{};
+    int front = 0;          // status slot of the oldest poll batch in flight
+    int64_t last_k = -1;
+    int stalls = 0;
+  };
+  std::vector<Run> run(nl);
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs(nl, nullptr);
+  auto cleanup = [&]() {
+    for (auto& L : h->lanes_ho) (void)hipStreamSynchronize(L.s);
+    for (hipGraphExec_t g : execs)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (hipGraph_t g : graphs) (void)hipGraphDestroy(g);
+  };
+  auto step_round = [&](size_t l, hipStream_t s) {
+    for (int r = 0; r < rounds; ++r) {
+      for (int k = 0; k < slots; ++k) {
+        launch_primal(run[l].sp, s);
+        launch_dual(run[l].sp, s);
+        launch_decide(run[l].sp, s);
+      }
+      launch_eval(run[l].sp, s);
+    }
+  };
+  auto enqueue = [&](size_t l, int slot) {
+    pdlp_handle::Lane& L = h->lanes_ho[l];
+    for (int i = 0; i < per; ++i) {
+      if (execs[l]) check(hipGraphLaunch(execs[l], L.s), "hipGraphLaunch");
+      else step_round(l, L.s);
+    }
+    check(hipGetLastError(), "hand-off launches");
+    check(hipMemcpyAsync(L.hst[slot], run[l].sp.st, 16, hipMemcpyDeviceToHost, L.s), "read status");
+    check(hipEventRecord(L.ev[slot], L.s), "hipEventRecord");
+  };
+  auto start = [&](size_t l, int32_t b) {
+    pdlp_handle::Lane& L = h->lanes_ho[l];
+    if (execs[l]) {
+      // the previous LP's graph may still be in flight on this stream
+      check(hipStreamSynchronize(L.s), "hand-off sync");
+      check(hipGraphExecDestroy(execs[l]), "hipGraphExecDestroy");
+      execs[l] = nullptr;
+    }
+    run[l] = Run{};
+    run[l].b = b;
+    run[l].sp = handoff_params(h, b, L);
+    h->handoff_h[(size_t)b] = h->bst_h[(size_t)b].k;
+    DevState* hs = L.hst[0];
+    *hs = h->bst_h[(size_t)b];
+    hs->status = 0;
+    hs->done = 0;
+    check(hipMemcpyAsync(run[l].sp.st, hs, sizeof(DevState), hipMemcpyHostToDevice, L.s), "resume state");
+    check(hipStreamSynchronize(L.s), "resume sync");
+    if (h->opt.graph) {
+      hipGraph_t g = nullptr;
+      check(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      step_round(l, h->cap_stream);
+      check(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+      graphs.push_back(g);
+      check(hipGraphInstantiate(&execs[l], g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    enqueue(l, 0);
+    enqueue(l, 1);
+    run[l].front = 0;
+  };
+  try {
+    size_t next = 0;
+    for (size_t l = 0; l < nl; ++l) start(l, paused[next++]);
+    size_t active = nl;
+    while (active > 0) {
+      bool any = false;
+      for (size_t l = 0; l < nl; ++l) {
+        Run& R = run[l];
+        if (R.b < 0) continue;
+        pdlp_handle::Lane& L = h->lanes_ho[l];
+        const hipError_t q = hipEventQuery(L.ev[R.front]);
+        if (q == hipErrorNotReady) continue;
+        check(q, "hipEventQuery");
+        any = true;
+        const DevState* hs = L.hst[R.front];
+        bool fin = hs->done != 0;
+        if (!fin) {
+          if (hs->k == R.last_k) {
+            if (++R.stalls >= 64) {
+              launch_set_limit(R.sp.st, PDLP_NUMERICAL_ERROR, L.s);
+              fin = true;
+            }
+          } else {
+            R.stalls = 0;
+            R.last_k = hs->k;
+          }
+        }
+        if (!fin && now_s() - t0 > h->opt.time_limit_s) {
+          launch_set_limit(R.sp.st, PDLP_TIME_LIMIT, L.s);
+          fin = true;
+        }
+        if (!fin) {
+          enqueue(l, R.front);
+          R.front ^= 1;
+          continue;
+        }
+        launch_output(R.sp, L.s);
+        check(hipGetLastError(), "hand-off output");
+        R.b = -1;
+        if (next < paused.size()) start(l, paused[next++]);
+        else --active;
+      }
+      if (!any) std::this_thread::yield();
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
 extern "C" int pdlp_solve_batch(pdlp_handle* h) {
   if (!h) return PDLP_ERR_ARG;
   if (!h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve_batch on a single-LP handle");
@@ -1477,11 +1719,26 @@ extern "C" int pdlp_solve_batch(pdlp_handle* h) {
     check(hipMemcpyAsync(h->warm, h->warm_h.data(), cnt, hipMemcpyHostToDevice, s), "upload warm flags");
     check(hipMemcpyAsync(h->omega_warm, h->omega_warm_h.data(), cnt * 8, hipMemcpyHostToDevice, s),
           "upload warm omegas");
-    launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, h->opt.time_limit_s);
+    launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, h->opt.time_limit_s, h->opt.batch_handoff);
     h->bst_h.resize(cnt);
     check(hipMemcpyAsync(h->bst_h.data(), h->bst, cnt * sizeof(DevState), hipMemcpyDeviceToHost, s), "read states");
     check(hipStreamSynchronize(s), "batch sync");
     check(hipGetLastError(), "batch kernels");
+    h->handoff_h.assign(cnt, 0);
+    std::vector<int32_t> paused;
+    for (size_t b = 0; b < cnt; ++b)
+      if (h->bst_h[b].status == kPaused) paused.push_back((int32_t)b);
+    if (!paused.empty()) {
+      // farthest from the tolerance first (likely the longest to finish), so
+      // that those do not wait for a free stream
+      std::stable_sort(paused.begin(), paused.end(), [&](int32_t a, int32_t c) {
+        return h->bst_h[(size_t)a].rel_kkt > h->bst_h[(size_t)c].rel_kkt;
+      });
+      run_handoff(h, paused, t0);
+      check(hipMemcpyAsync(h->bst_h.data(), h->bst, cnt * sizeof(DevState), hipMemcpyDeviceToHost, s),
+            "read states");
+      check(hipStreamSynchronize(s), "hand-off sync");
+    }
   } catch (const HipFail& f) {
     return fail(h, PDLP_ERR_HIP, hip_msg(f));
   }
@@ -1528,6 +1785,7 @@ extern "C" int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, d
       I.solve_s = h->info.solve_s;
       I.layout_k = h->lanes_h[2 * (size_t)b];
       I.layout_kt = h->lanes_h[2 * (size_t)b + 1];
+      I.handoff_k = h->handoff_h[(size_t)b];
     }
   }
   return PDLP_OK;

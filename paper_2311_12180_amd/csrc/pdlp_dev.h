@@ -104,6 +104,9 @@ struct Params {
   int32_t m, n;
   int32_t use_f32;
   int32_t pad0;
+  // first row / column of the elementwise passes (0; an LP of a batch continued
+  // on these kernels works on its slice of the packed vectors)
+  int32_t row_base, col_base;
   // iterates (double-buffered where a step writes a new one)
   double* x[2];
   double* y[2];
@@ -137,6 +140,8 @@ struct Params {
   double qnorm0, cnorm0;
 };
 
+constexpr int32_t kPaused = 5;   // internal status of a batched LP handed to the single-LP kernels
+
 // Batched solve (many independent LPs packed block-diagonally into one Params).
 struct BatchParams {
   int32_t count;            // LPs in the queue
@@ -160,6 +165,8 @@ struct BatchParams {
   const uint64_t* t0;       // wall-clock stamp taken just before the launch
   uint64_t ticks;           // time limit in wall-clock ticks (0: none)
   int64_t max_reject;       // consecutive rejected attempts that count as a numerical failure
+  int64_t pause_at;         // accepted steps after which an LP stops at its next evaluation with
+                            // status kPaused, to be continued by the single-LP kernels (0: never)
   int32_t lds_m, lds_n;     // LDS room for an LP's y, dx and row pointers (0, 0: all from global memory)
   int32_t lds_bk, lds_bt;   // LDS room for an LP's block descriptors of K~, K~'
   double eps_rel;

@@ -54,7 +54,8 @@ class pdlp_options(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
                 ("kkt_omega_power", C.c_int32), ("trace", C.c_int32), ("poll_every", C.c_int32),
                 ("graph", C.c_int32), ("spmv_layout", C.c_int32), ("batch_lanes", C.c_int32),
-                ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32)]
+                ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32),
+                ("batch_handoff", C.c_int32), ("handoff_streams", C.c_int32)]
 
 
 class pdlp_info(C.Structure):
@@ -63,7 +64,8 @@ class pdlp_info(C.Structure):
                 ("rel_kkt", C.c_double), ("rel_gap", C.c_double), ("rel_pres", C.c_double),
                 ("rel_dres", C.c_double), ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("omega", C.c_double), ("eta_hat", C.c_double), ("setup_s", C.c_double),
-                ("solve_s", C.c_double), ("layout_k", C.c_int32), ("layout_kt", C.c_int32)]
+                ("solve_s", C.c_double), ("layout_k", C.c_int32), ("layout_kt", C.c_int32),
+                ("handoff_k", C.c_int64)]
 
 
 class pdlp_iter_state(C.Structure):

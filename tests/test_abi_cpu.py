@@ -127,6 +127,9 @@ def test_batch_rejects_bad_members_and_options(P):
                                     ([good], P.PDLP_ERR_ARG, "batch_lanes", {"batch_lanes": 3}),
                                     ([good], P.PDLP_ERR_ARG, "batch_lanes", {"batch_lanes": 128}),
                                     ([good], P.PDLP_ERR_ARG, "batch_grid", {"batch_grid": -2}),
+                                    ([good], P.PDLP_ERR_ARG, "batch_handoff", {"batch_handoff": -1}),
+                                    ([good], P.PDLP_ERR_ARG, "handoff_streams", {"handoff_streams": 0}),
+                                    ([good], P.PDLP_ERR_ARG, "handoff_streams", {"handoff_streams": 17}),
                                     ([], P.PDLP_ERR_ARG, "count", {})]:
         with pytest.raises(P.PdlpError) as e:
             P.pdlp_create_batch(probs, **opts)

@@ -9,7 +9,10 @@ Bars (as for the single-LP path):
     oracle's, the returned point passes the oracle's FP64 evaluator, and at
     1e-8 the objective is within 1e-6 of the LP's constructed optimum;
   * an LP's result does not depend on the other LPs of the batch or on which
-    workgroup ran it: bitwise equal alone and inside the batch, and run to run.
+    workgroup ran it: bitwise equal alone and inside the batch, and run to run;
+  * every bar holds as well when LPs are handed from the persistent launch to
+    the single-LP kernels part way (a small batch_handoff): the hand-off moves
+    the state, it does not change the method.
 """
 import numpy as np
 import pytest
@@ -101,14 +104,18 @@ def _oracle_spread(orc, p, opts, trace=False, copies=3):
     return a, sx, so, se, bool(stable)
 
 
-def test_first_100_steps_match_oracle(P, orc):
+@pytest.mark.parametrize("handoff", [0, 1])
+def test_first_100_steps_match_oracle(P, orc, handoff):
     """Per LP: the same attempts and restarts, the returned point within
     max(1e-10, 100 x the oracle's own rounding-order spread); LP 0's trace:
     the same decisions, step sizes within the same kind of bar (the step
-    bound's denominator dy'K dx cancels, which amplifies rounding)."""
+    bound's denominator dy'K dx cancels, which amplifies rounding).  With
+    handoff 1 every LP leaves the persistent launch at its first evaluation
+    after step 0 (step 64) and takes its last 36 steps on the single-LP
+    kernels, 8 LPs at a time."""
     probs = _small_batch(16)
     opts = dict(eps_rel=0.0, max_iter=100)
-    h = P.pdlp_create_batch(probs, time_limit_s=60.0, trace=4096, **opts)
+    h = P.pdlp_create_batch(probs, time_limit_s=60.0, trace=4096, batch_handoff=handoff, **opts)
     P.pdlp_solve_batch(h)
     x, y, rc, infos = P.pdlp_get_solution_batch(h, -1)
     xs, ys = _split(h, x, False), _split(h, y, True)
@@ -118,6 +125,7 @@ def test_first_100_steps_match_oracle(P, orc):
         r, sx, so, se, stable = _oracle_spread(orc, p, opts, trace=(k == 0))
         I = infos[k]
         assert I["status_name"] == "ITER_LIMIT" and I["iterations"] == 100
+        assert I["handoff_k"] == (64 if handoff == 1 else 0), (k, I["handoff_k"])
         if not stable:
             rows.append(f"LP {k}: oracle decisions change under renumbering, not compared")
             continue
@@ -137,20 +145,28 @@ def test_first_100_steps_match_oracle(P, orc):
     assert compared >= len(probs) // 2
 
 
-@pytest.mark.parametrize("eps", [1e-4, 1e-8])
-def test_end_to_end_matches_oracle(P, orc, eps):
+@pytest.mark.parametrize("eps,handoff", [(1e-4, 2048), (1e-8, 0), (1e-8, 64)])
+def test_end_to_end_matches_oracle(P, orc, eps, handoff):
     """Objective within max(1e-6, 10 x the oracle's own spread under
     renumbering) of the oracle's when the run followed the oracle's decisions;
     at rel KKT 1e-4 the stopping point, and with it the objective, moves by up
     to ~1e-4 relative with the summation order alone on some of these LPs, so
-    a run whose decisions differ is held to 2 eps."""
+    a run whose decisions differ is held to 2 eps.  Handoff 64: every LP still
+    running at its first evaluation after step 64 is finished by the
+    single-LP kernels, 3 at a time (more such LPs than hand-off streams)."""
     probs = _mixed_batch() + _small_batch(10, seed=4)
     opts = dict(eps_rel=eps, max_iter=200000)
-    h = P.pdlp_create_batch(probs, time_limit_s=120.0, **opts)
+    h = P.pdlp_create_batch(probs, time_limit_s=120.0, batch_handoff=handoff, handoff_streams=3, **opts)
     P.pdlp_solve_batch(h)
+    handed = 0
     for k, p in enumerate(probs):
         x, y, rc, I = P.pdlp_get_solution_batch(h, k)
         r, _, so, _, _ = _oracle_spread(orc, p, opts)
+        if I["handoff_k"]:
+            handed += 1
+            assert handoff <= I["handoff_k"] <= I["iterations"], (k, I["handoff_k"])
+        elif handoff:
+            assert I["iterations"] < handoff + 64, (k, I["iterations"])
         assert I["status_name"] == "OPTIMAL" and r.status == "OPTIMAL", (k, p.name, I["status_name"])
         assert I["rel_kkt"] <= eps
         obj = I["primal_obj"]
@@ -167,6 +183,8 @@ def test_end_to_end_matches_oracle(P, orc, eps):
             ref = box_lp_optimum(p.c, p.l, p.u)[0] if p.name == "box" else p.obj_star()
             if ref is not None:
                 assert abs(obj - ref) <= 1e-6 * (1 + abs(ref)), (k, p.name)
+    if handoff == 64:
+        assert handed > 3
 
 
 @pytest.mark.parametrize("lanes", [-1, 1, 2, 8, 64])
@@ -189,10 +207,12 @@ def test_any_lanes_per_row(P, orc, lanes):
         assert _rel_inf(x, r.x) <= tol and _rel_inf(y, r.y) <= tol, (k, tol)
 
 
-def test_member_result_independent_of_batch(P):
-    """Bitwise: LP k alone, LP k inside the batch, and a second solve."""
+@pytest.mark.parametrize("handoff", [0, 64])
+def test_member_result_independent_of_batch(P, handoff):
+    """Bitwise: LP k alone, LP k inside the batch, and a second solve (also
+    when the LPs are finished by the single-LP kernels after a hand-off)."""
     probs = _small_batch(12, seed=9)
-    kw = dict(eps_rel=1e-6, batch_lanes=8, batch_grid=5, time_limit_s=60.0)
+    kw = dict(eps_rel=1e-6, batch_lanes=8, batch_grid=5, time_limit_s=60.0, batch_handoff=handoff)
     h = P.pdlp_create_batch(probs, **kw)
     P.pdlp_solve_batch(h)
     a = P.pdlp_get_solution_batch(h, -1)
@@ -208,6 +228,7 @@ def test_member_result_independent_of_batch(P):
         np.testing.assert_array_equal(x1, x)
         np.testing.assert_array_equal(y1, y)
         assert I1["iterations"] == I["iterations"]
+        assert I1["handoff_k"] == I["handoff_k"]
 
 
 def test_schedule_autotuned(P):
@@ -245,9 +266,11 @@ def test_warm_start_batch(P, orc):
         [i["iterations"] for k, i in enumerate(cold) if k != 3]
 
 
-def test_time_limit_ends_every_lp(P):
+@pytest.mark.parametrize("handoff", [0, 64])
+def test_time_limit_ends_every_lp(P, handoff):
     probs = _small_batch(8, seed=15, m_lo=300, m_hi=400)
-    h = P.pdlp_create_batch(probs, eps_rel=0.0, max_iter=10**9, time_limit_s=0.05, batch_lanes=8, batch_grid=4)
+    h = P.pdlp_create_batch(probs, eps_rel=0.0, max_iter=10**9, time_limit_s=0.05, batch_lanes=8, batch_grid=4,
+                            batch_handoff=handoff)
     P.pdlp_solve_batch(h)
     infos = P.pdlp_get_solution_batch(h, -1)[3]
     assert all(i["status_name"] == "TIME_LIMIT" for i in infos)
