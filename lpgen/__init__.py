@@ -18,6 +18,11 @@ Families (all values float64, indices int32, row types int8):
   transportation -- S sources x T sinks, 2 unit entries per column.
   tiny_dense_lp  -- dense boxed LPs small enough for vertex enumeration.
   batch_lps      -- many random_lp instances of uneven size.
+  infeasible_lp / bound_infeasible_lp / unbounded_lp -- a random_lp with a
+                    planted contradiction (two rows asking a'x >= beta + gap
+                    and a'x <= beta; one row no point of the box reaches) or a
+                    planted improving ray (a new unbounded column that only
+                    relaxes LE rows), with the planted certificate attached.
 """
 from __future__ import annotations
 
@@ -421,3 +426,66 @@ def gnn_init(seed: int, shapes) -> np.ndarray:
             w = np.zeros(shape)
         out.append(w.astype(np.float32).astype(np.float64).reshape(-1))
     return np.concatenate(out)
+
+
+def _append_rows(p: Problem, rows_cols, rows_vals, b_new, rt_new, name: str) -> Problem:
+    """p with extra rows (lists of column indices / values) appended at the end."""
+    A = p.to_scipy().tocoo()
+    r = [A.row]; cc = [A.col]; v = [A.data]
+    for k, (cols, vals) in enumerate(zip(rows_cols, rows_vals)):
+        r.append(np.full(len(cols), p.m + k)); cc.append(np.asarray(cols)); v.append(np.asarray(vals, float))
+    m = p.m + len(rows_cols)
+    row_ptr, col_idx, val = _csr_from_coo(m, p.n, np.concatenate(r), np.concatenate(cc), np.concatenate(v))
+    return Problem(m, p.n, row_ptr, col_idx, val, p.c.copy(), np.concatenate([p.b, b_new]), p.l.copy(),
+                   p.u.copy(), np.concatenate([p.row_type, np.asarray(rt_new, np.int8)]), name)
+
+
+def infeasible_lp(seed: int = 0, m: int = 200, gap: float = 1.0) -> Problem:
+    """random_lp (m rows, n = 2m) plus the rows a'x >= beta + gap and
+    a'x <= beta for a random sparse a: no x satisfies both.  The planted dual
+    ray (user orientation) is y = 1 on the GE row, -1 on the LE row, 0 elsewhere."""
+    base = batch_lp(seed, 0, m)
+    rng = np.random.Generator(np.random.PCG64([seed, 0x1F5]))
+    cols = np.sort(rng.choice(base.n, 8, replace=False))
+    vals = rng.standard_normal(8)
+    beta = float(rng.uniform(-5, 5))
+    p = _append_rows(base, [cols, cols], [vals, vals], [beta + gap, beta], [ROW_GE, ROW_LE],
+                     f"infeasible_lp(seed={seed},m={m})")
+    yr = np.zeros(p.m); yr[-2] = 1.0; yr[-1] = -1.0
+    p.y_star = yr      # the planted ray, not an optimum
+    return p
+
+
+def bound_infeasible_lp(seed: int = 0, m: int = 200) -> Problem:
+    """random_lp (x in [0, 10]) plus a GE row with positive coefficients whose
+    right-hand side exceeds the row's maximum over the box by 1."""
+    base = batch_lp(seed, 0, m)
+    rng = np.random.Generator(np.random.PCG64([seed, 0xB0D]))
+    cols = np.sort(rng.choice(base.n, 8, replace=False))
+    vals = rng.uniform(0.5, 2.0, 8)
+    rhs = float(np.sum(vals * base.u[cols])) + 1.0
+    p = _append_rows(base, [cols], [vals], [rhs], [ROW_GE], f"bound_infeasible_lp(seed={seed},m={m})")
+    yr = np.zeros(p.m); yr[-1] = 1.0
+    p.y_star = yr
+    return p
+
+
+def unbounded_lp(seed: int = 0, m: int = 200) -> Problem:
+    """random_lp (feasible) plus a column x_new >= 0 without upper bound, cost
+    -1, entering three LE rows with coefficient -1 (raising it only relaxes
+    them) and no other row: c'x -> -inf along e_new."""
+    base = batch_lp(seed, 0, m)
+    rng = np.random.Generator(np.random.PCG64([seed, 0xDB1]))
+    le_rows = np.flatnonzero(base.row_type == ROW_LE)
+    rows = np.sort(rng.choice(le_rows, 3, replace=False))
+    A = base.to_scipy().tocoo()
+    n = base.n + 1
+    row_ptr, col_idx, val = _csr_from_coo(base.m, n, np.concatenate([A.row, rows]),
+                                          np.concatenate([A.col, np.full(3, base.n)]),
+                                          np.concatenate([A.data, -np.ones(3)]))
+    p = Problem(base.m, n, row_ptr, col_idx, val, np.concatenate([base.c, [-1.0]]), base.b.copy(),
+                np.concatenate([base.l, [0.0]]), np.concatenate([base.u, [np.inf]]), base.row_type.copy(),
+                f"unbounded_lp(seed={seed},m={m})")
+    xr = np.zeros(n); xr[-1] = 1.0
+    p.x_star = xr      # the planted ray, not an optimum
+    return p

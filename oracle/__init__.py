@@ -25,7 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdlp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-STATUS = {0: "NONE", 1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL_ERROR"}
+STATUS = {0: "NONE", 1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL_ERROR",
+          5: "PRIMAL_INFEASIBLE", 6: "DUAL_INFEASIBLE"}
 
 
 def build(force: bool = False) -> str:
@@ -50,7 +51,8 @@ class _Options(C.Structure):
                 ("eval_period", C.c_int32), ("ruiz_iters", C.c_int32), ("pc_alpha", C.c_double),
                 ("pw_theta", C.c_double), ("eps_zero", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
-                ("kkt_omega_power", C.c_int32), ("threads", C.c_int32)]
+                ("kkt_omega_power", C.c_int32), ("threads", C.c_int32), ("detect_infeas", C.c_int32),
+                ("eps_infeas", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -60,7 +62,8 @@ class _Info(C.Structure):
                 ("rel_dres", C.c_double), ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("omega", C.c_double), ("eta_hat", C.c_double), ("sum_eta", C.c_double),
                 ("kkt0", C.c_double), ("setup_s", C.c_double), ("solve_s", C.c_double),
-                ("threads_used", C.c_int32)]
+                ("threads_used", C.c_int32), ("ray_source", C.c_int32), ("ray_obj", C.c_double),
+                ("ray_res", C.c_double)]
 
 
 class _Trace(C.Structure):
@@ -88,6 +91,9 @@ def lib():
         L.orc_evaluate.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_double,
                                    C.c_int32, C.c_void_p]
         L.orc_reduced_costs.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p]
+        L.orc_ray_test.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_ray_test.restype = C.c_int
         L.orc_restart_reason.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int64,
                                          C.c_double, C.c_double, C.c_double]
         L.orc_restart_reason.restype = C.c_int
@@ -144,7 +150,9 @@ class Result:
 def solve(prob, trace_cap: int = 0, **opts) -> Result:
     """Solve with the oracle.  Options: eps_rel, max_iter, time_limit_s,
     eval_period, ruiz_iters, pc_alpha, pw_theta, eps_zero, beta_suff, beta_nec,
-    beta_art, a_precision, kkt_omega_power, threads."""
+    beta_art, a_precision, kkt_omega_power, threads, detect_infeas, eps_infeas.
+    Status PRIMAL_INFEASIBLE returns a unit dual ray in y (and its multipliers
+    in rc), DUAL_INFEASIBLE a unit primal ray in x."""
     h = _Held(prob)
     o = default_options(**opts)
     m, n = int(prob.m), int(prob.n)
@@ -208,6 +216,25 @@ def evaluate(prob, x, y, omega: float = 1.0, omega_power: int = 2) -> dict:
     keys = ["rel_kkt", "rel_gap", "rel_pres", "rel_dres", "primal_obj", "dual_obj",
             "pres", "dres", "gap", "kkt_omega"]
     return dict(zip(keys, out.tolist()))
+
+
+def ray_test(prob, x_dir, y_dir, eps: float = 1e-8) -> dict:
+    """Farkas test of a candidate direction (user orientation): verdict 1 =
+    y certifies primal infeasibility, 2 = x certifies dual infeasibility,
+    0 = neither; the ray quantities after projection; the projected rays."""
+    h = _Held(prob)
+    xd = np.ascontiguousarray(x_dir, dtype=np.float64)
+    yd = np.ascontiguousarray(y_dir, dtype=np.float64)
+    out = np.zeros(8)
+    rx = np.zeros(prob.n); ry = np.zeros(prob.m); lam = np.zeros(prob.n)
+    v = lib().orc_ray_test(C.byref(h.s), _p(xd), _p(yd), float(eps), _p(out), _p(rx), _p(ry), _p(lam))
+    if v < 0:
+        raise ValueError("bad problem")
+    keys = ["dual_ray_obj", "dual_ray_res", "y_norm", "primal_ray_obj", "primal_ray_res", "x_norm",
+            "dual_ray_obj_abs", "primal_ray_obj_abs"]
+    d = dict(zip(keys, out.tolist()))
+    d.update(verdict=int(v), ray_x=rx, ray_y=ry, lam=lam)
+    return d
 
 
 def reduced_costs(prob, y) -> np.ndarray:

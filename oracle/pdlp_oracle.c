@@ -35,7 +35,21 @@
  *   - at an epoch's first evaluation the previous candidate KKT is KKT(z^{n,0});
  *   - the candidate comparison KKT(current) < KKT(average) treats a relative
  *     difference below 1e-12 as a tie, which goes to the average;
- *   - the start is proj_X(0), y = 0.
+ *   - the start is proj_X(0), y = 0;
+ *   - infeasibility detection (Section 2.2 names the two sequences and defers
+ *     the test to its citation): at every evaluation that does not terminate,
+ *     the last accepted step z - z_prev and the epoch displacement z - z^{n,0}
+ *     (the normalized iterate without its 1/t, which the scale-free tests
+ *     ignore) are each tested on the unscaled LP against Farkas' lemma:
+ *     y (inequality entries clipped at 0) with lam = proj_Lambda(-K'y) is a
+ *     dual ray when q'y + l'lam+ - u'lam- > 0 and ||K'y + lam|| <= eps times
+ *     it; x projected onto the recession cone of [l, u] is a primal ray when
+ *     c'x < 0 and the norm of Kx's violation of (=0 on EQ, >=0 on the other
+ *     rows) is <= eps |c'x|; in both, the ray objective must also exceed eps
+ *     times the sum of the magnitudes of its terms (a sign that cancellation
+ *     cannot produce: with every variable boxed, lam absorbs all of K'y and
+ *     the objective's sign is the whole test).  Primal infeasibility is tested
+ *     first, the step before the displacement; the unit-norm ray is returned.
  * Sums are taken in a fixed blocked order (blocks of 4096, serial within and
  * across blocks) so that results do not depend on the thread count.  Built
  * with -ffp-contract=off: every product and sum is rounded on its own.
@@ -404,6 +418,110 @@ static eval_t evaluate_point(const lp_t* P, const double* xh, const double* yh, 
   return e;
 }
 
+/* ---------------------------------------------------------------- infeasibility */
+
+static int check_problem(const orc_problem* p);
+
+typedef struct {
+  double dro, dro_abs, r2, ny2;  /* dual ray: q'y + l'lam+ - u'lam-, the sum of its terms' magnitudes,
+                                    ||K'y + lam||^2, ||y||^2 */
+  double pro, pro_abs, v2, nx2;  /* primal ray: c'x, sum |c_j x_j|, ||violation of Kx||^2, ||x||^2 */
+} rays_t;
+
+/* Farkas quantities of a candidate direction (xd, yd) on the unscaled
+ * >=-form LP (K0, q0, c0, l0, u0).  Dual ray: y = yd with its inequality
+ * entries clipped at 0; g = -K0'y; lam = proj_Lambda(g); residual g - lam,
+ * i.e. K0'y + lam; objective q0'y + l0'lam+ - u0'lam- (0 * inf := 0).
+ * Primal ray: x = xd projected onto the recession cone of [l0, u0] (0 where
+ * both bounds are finite, max(., 0) / min(., 0) where only l0 / only u0 is);
+ * violation of K0 x: the entry itself on EQ rows, min(entry, 0) on the other
+ * rows; objective c0'x.  xr, yr, lam receive the projected rays. */
+static rays_t ray_parts(const lp_t* P, const double* xd, const double* yd, double* xr, double* yr,
+                        double* lam, double* wm, double* wn) {
+  rays_t r;
+  int32_t m = P->m, n = P->n;
+  double* tm = (double*)xalloc((size_t)m, sizeof(double));
+  double* tn = (double*)xalloc((size_t)n, sizeof(double));
+  for (int32_t i = 0; i < m; ++i) yr[i] = (P->ineq[i] && yd[i] < 0.0) ? 0.0 : yd[i];
+  spmv(&P->K0t, yr, wn);
+  for (int32_t j = 0; j < n; ++j) {
+    double g = -wn[j];
+    lam[j] = proj_lambda(g, P->l0[j], P->u0[j]);
+    double d = g - lam[j];
+    tn[j] = d * d;
+  }
+  r.r2 = blocked_sum(n, tn);
+  for (int32_t j = 0; j < n; ++j) {
+    double lp = lam[j] > 0.0 ? lam[j] : 0.0, lm = lam[j] < 0.0 ? -lam[j] : 0.0;
+    tn[j] = (lp > 0.0 ? P->l0[j] * lp : 0.0) - (lm > 0.0 ? P->u0[j] * lm : 0.0);
+  }
+  r.dro = dot(m, P->q0, yr) + blocked_sum(n, tn);
+  for (int32_t j = 0; j < n; ++j) {
+    double lp = lam[j] > 0.0 ? lam[j] : 0.0, lm = lam[j] < 0.0 ? -lam[j] : 0.0;
+    tn[j] = (lp > 0.0 ? fabs(P->l0[j]) * lp : 0.0) + (lm > 0.0 ? fabs(P->u0[j]) * lm : 0.0);
+  }
+  for (int32_t i = 0; i < m; ++i) tm[i] = fabs(P->q0[i] * yr[i]);
+  r.dro_abs = blocked_sum(m, tm) + blocked_sum(n, tn);
+  r.ny2 = sumsq(m, yr);
+  for (int32_t j = 0; j < n; ++j) {
+    int lf = isfinite(P->l0[j]), uf = isfinite(P->u0[j]);
+    double v = xd[j];
+    if (lf && uf) v = 0.0;
+    else if (lf) v = v > 0.0 ? v : 0.0;
+    else if (uf) v = v < 0.0 ? v : 0.0;
+    xr[j] = v;
+  }
+  spmv(&P->K0, xr, wm);
+  for (int32_t i = 0; i < m; ++i) {
+    double v = wm[i];
+    if (P->ineq[i]) v = v < 0.0 ? v : 0.0;
+    tm[i] = v * v;
+  }
+  r.v2 = blocked_sum(m, tm);
+  r.pro = dot(n, P->c0, xr);
+  for (int32_t j = 0; j < n; ++j) tn[j] = fabs(P->c0[j] * xr[j]);
+  r.pro_abs = blocked_sum(n, tn);
+  r.nx2 = sumsq(n, xr);
+  free(tm); free(tn);
+  return r;
+}
+
+/* A ray's objective must exceed eps times the magnitudes it is summed from
+ * (so that cancellation cannot fake its sign) and bound its residual by the
+ * factor eps. */
+static int ray_dual_ok(rays_t r, double eps) {
+  return r.dro > eps * r.dro_abs && r.dro > 0.0 && sqrt(r.r2) <= eps * r.dro;
+}
+static int ray_primal_ok(rays_t r, double eps) {
+  return -r.pro > eps * r.pro_abs && r.pro < 0.0 && sqrt(r.v2) <= eps * -r.pro;
+}
+
+int orc_ray_test(const orc_problem* p, const double* x_dir, const double* y_dir, double eps, double* out,
+                 double* ray_x, double* ray_y, double* lam) {
+  if (check_problem(p)) return -1;
+  lp_t P;
+  if (lp_normalize(p, &P)) return -1;
+  int32_t m = P.m, n = P.n;
+  double* yd = (double*)xalloc((size_t)m, sizeof(double));
+  double* xr = (double*)xalloc((size_t)n, sizeof(double));
+  double* yr = (double*)xalloc((size_t)m, sizeof(double));
+  double* lm = (double*)xalloc((size_t)n, sizeof(double));
+  double* wm = (double*)xalloc((size_t)m, sizeof(double));
+  double* wn = (double*)xalloc((size_t)n, sizeof(double));
+  for (int32_t i = 0; i < m; ++i) yd[i] = P.le[i] ? -y_dir[i] : y_dir[i];
+  rays_t r = ray_parts(&P, x_dir, yd, xr, yr, lm, wm, wn);
+  out[0] = r.dro; out[1] = sqrt(r.r2); out[2] = sqrt(r.ny2);
+  out[3] = r.pro; out[4] = sqrt(r.v2); out[5] = sqrt(r.nx2);
+  out[6] = r.dro_abs; out[7] = r.pro_abs;
+  if (ray_x) memcpy(ray_x, xr, sizeof(double) * (size_t)n);
+  if (ray_y) for (int32_t i = 0; i < m; ++i) ray_y[i] = P.le[i] ? -yr[i] : yr[i];
+  if (lam) memcpy(lam, lm, sizeof(double) * (size_t)n);
+  int v = ray_dual_ok(r, eps) ? 1 : (ray_primal_ok(r, eps) ? 2 : 0);
+  free(yd); free(xr); free(yr); free(lm); free(wm); free(wn);
+  lp_free(&P);
+  return v;
+}
+
 int orc_restart_reason(double kc, double kkt0, double kprev, int64_t t, int64_t k,
                        double beta_suff, double beta_nec, double beta_art) {
   /* Section 3.4, restart criteria */
@@ -434,6 +552,8 @@ void orc_default_options(orc_options* o) {
   o->a_precision = 0;
   o->kkt_omega_power = 2;
   o->threads = 0;
+  o->detect_infeas = 1;
+  o->eps_infeas = 1e-8;
 }
 
 static int check_problem(const orc_problem* p) {
@@ -558,6 +678,14 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
   double* wn = (double*)xalloc((size_t)n, sizeof(double));
   double* wm2 = (double*)xalloc((size_t)m, sizeof(double));
   double* wn2 = (double*)xalloc((size_t)n, sizeof(double));
+  /* infeasibility candidates: unscaled directions and their projected rays */
+  double* cdx = (double*)xalloc((size_t)n, sizeof(double));
+  double* cdy = (double*)xalloc((size_t)m, sizeof(double));
+  double* rx[2] = {(double*)xalloc((size_t)n, sizeof(double)), (double*)xalloc((size_t)n, sizeof(double))};
+  double* ry[2] = {(double*)xalloc((size_t)m, sizeof(double)), (double*)xalloc((size_t)m, sizeof(double))};
+  double* rl[2] = {(double*)xalloc((size_t)n, sizeof(double)), (double*)xalloc((size_t)n, sizeof(double))};
+  rays_t ray = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int ray_src = 0;
 
   /* Section 4.1 initialisation: the zero vector, projected onto X */
   for (int32_t j = 0; j < n; ++j) x[j] = clampd(0.0, P.l[j], P.u[j]);
@@ -647,6 +775,24 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
     if (ec.rel.rel_kkt <= o.eps_rel || ea.rel.rel_kkt <= o.eps_rel) {
       status = 1; ret_avg = avg_better; ret_rel = avg_better ? ea.rel : ec.rel; break;
     }
+    if (o.detect_infeas) {
+      /* Section 2.2, infeasibility detection: the last accepted step z - z_prev
+       * (z_prev sits in xn, yn after the swap) and the epoch displacement z - z^{n,0} */
+      rays_t rr[2];
+      for (int sq = 0; sq < 2; ++sq) {
+        const double* xb = sq ? x0 : xn;
+        const double* yb = sq ? y0 : yn;
+        for (int32_t j = 0; j < n; ++j) cdx[j] = P.D2[j] * (x[j] - xb[j]);
+        for (int32_t i = 0; i < m; ++i) cdy[i] = P.D1[i] * (y[i] - yb[i]);
+        rr[sq] = ray_parts(&P, cdx, cdy, rx[sq], ry[sq], rl[sq], wm, wn);
+      }
+      int kind = 0;
+      for (int sq = 0; sq < 2 && !kind; ++sq)
+        if (ray_dual_ok(rr[sq], o.eps_infeas)) { kind = 5; ray_src = sq; }
+      for (int sq = 0; sq < 2 && !kind; ++sq)
+        if (ray_primal_ok(rr[sq], o.eps_infeas)) { kind = 6; ray_src = sq; }
+      if (kind) { status = kind; ray = rr[ray_src]; ret_avg = 0; ret_rel = ec.rel; break; }
+    }
     if (k >= o.max_iter) { status = 2; ret_avg = avg_better; ret_rel = avg_better ? ea.rel : ec.rel; break; }
     /* restart candidate and restart criteria */
     double kc_cur = kkt_omega(ec.scaled, omega, o.kkt_omega_power);
@@ -702,6 +848,21 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
     spmv(&P.K0t, yo, wn);
     for (int32_t j = 0; j < n; ++j) rc[j] = proj_lambda(P.c0[j] - wn[j], P.l0[j], P.u0[j]);
   }
+  /* an infeasibility certificate replaces the side it certifies (unit 2-norm);
+   * for a dual ray the reduced costs are its multipliers lam */
+  double ray_obj = 0.0, ray_res = 0.0;
+  if (status == 5 && ray.ny2 > 0.0) {
+    double sc = 1.0 / sqrt(ray.ny2);
+    if (y_user) for (int32_t i = 0; i < m; ++i) y_user[i] = (P.le[i] ? -ry[ray_src][i] : ry[ray_src][i]) * sc;
+    if (rc) for (int32_t j = 0; j < n; ++j) rc[j] = rl[ray_src][j] * sc;
+    ray_obj = ray.dro * sc;
+    ray_res = sqrt(ray.r2) * sc;
+  } else if (status == 6 && ray.nx2 > 0.0) {
+    double sc = 1.0 / sqrt(ray.nx2);
+    if (x_user) for (int32_t j = 0; j < n; ++j) x_user[j] = rx[ray_src][j] * sc;
+    ray_obj = ray.pro * sc;
+    ray_res = sqrt(ray.v2) * sc;
+  }
   if (x_hat) memcpy(x_hat, x, sizeof(double) * (size_t)n);
   if (y_hat) memcpy(y_hat, y, sizeof(double) * (size_t)m);
   if (info) {
@@ -718,10 +879,15 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
 #else
     info->threads_used = 1;
 #endif
+    info->ray_source = (status == 5 || status == 6) ? ray_src : 0;
+    info->ray_obj = ray_obj;
+    info->ray_res = ray_res;
   }
   free(yo);
   free(x); free(y); free(xn); free(yn); free(x0); free(y0); free(xs); free(ys); free(xa); free(ya);
   free(kty); free(w); free(kw); free(dx); free(dy); free(kdx); free(wm); free(wn); free(wm2); free(wn2);
+  free(cdx); free(cdy);
+  for (int sq = 0; sq < 2; ++sq) { free(rx[sq]); free(ry[sq]); free(rl[sq]); }
   lp_free(&P);
   return 0;
 }

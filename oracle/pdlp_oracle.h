@@ -44,15 +44,20 @@ typedef struct {
   int32_t a_precision;    /* 0: FP64 matrix in the steps, 1: FP32-rounded scaled matrix in the steps */
   int32_t kkt_omega_power;/* 2: weights omega^2, 1/omega^2 as printed; 1: omega, 1/omega */
   int32_t threads;        /* OpenMP threads, 0 = runtime default */
+  int32_t detect_infeas;  /* 1: test the infeasibility certificates at every evaluation */
+  double eps_infeas;      /* tolerance of the certificate tests */
 } orc_options;
 
 typedef struct {
-  int32_t status;         /* 1 optimal, 2 iteration limit, 3 time limit, 4 numerical error */
+  int32_t status;         /* 1 optimal, 2 iteration limit, 3 time limit, 4 numerical error,
+                             5 primal infeasible (y holds a dual ray), 6 dual infeasible (x holds a primal ray) */
   int32_t returned_avg;   /* 1 if the returned point is the average iterate */
   int64_t iterations, attempts, restarts, evaluations;
   double rel_kkt, rel_gap, rel_pres, rel_dres, primal_obj, dual_obj;
   double omega, eta_hat, sum_eta, kkt0, setup_s, solve_s;
   int32_t threads_used;
+  int32_t ray_source;     /* status 5/6: 0 the last accepted step, 1 the epoch displacement */
+  double ray_obj, ray_res;/* status 5/6: the ray's objective and residual norm, for the unit-norm ray */
 } orc_info;
 
 /* Optional decision trace: caller-owned arrays of the given capacities. */
@@ -88,6 +93,19 @@ int orc_pdhg_step(int32_t m, int32_t n, const int32_t* row_ptr, const int32_t* c
  *             ||r_p||, ||r_d||, |gap|, kkt_omega (with the given omega and power). */
 int orc_evaluate(const orc_problem* p, const double* x, const double* y, double omega,
                  int32_t omega_power, double* out);
+
+/* Farkas test of a candidate direction (x_dir[n], y_dir[m], user orientation)
+ * on the LP, with tolerance eps.  out[0..7] = dual-ray objective
+ * b'y + l'lam+ - u'lam-, ||A'y + lam||, ||y||, primal-ray objective c'x, norm
+ * of x's violation of the row cones, ||x||, the sums of the magnitudes of the
+ * terms of the two objectives, after the projections (y clipped to
+ * the sign of each inequality row, lam = proj_Lambda(-A'y), x projected onto
+ * the recession cone of [l, u]).  ray_x[n], ray_y[m], lam[n] (each may be
+ * NULL) receive the projected rays and multipliers.  Returns 1 when y
+ * certifies primal infeasibility, else 2 when x certifies dual infeasibility,
+ * else 0; -1 for a bad problem. */
+int orc_ray_test(const orc_problem* p, const double* x_dir, const double* y_dir, double eps, double* out,
+                 double* ray_x, double* ray_y, double* lam);
 
 /* Reduced costs lambda = proj_Lambda(c - A'y) at (user-orientation) y. */
 int orc_reduced_costs(const orc_problem* p, const double* y, double* lam);
