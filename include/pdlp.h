@@ -41,7 +41,8 @@ typedef struct pdlp_handle pdlp_handle;   /* opaque; owns every device buffer */
 enum { PDLP_ROW_EQ = 0, PDLP_ROW_GE = 1, PDLP_ROW_LE = 2 };       /* int8 row_type */
 enum { PDLP_MEM_HOST = 0, PDLP_MEM_DEVICE = 1 };                  /* where problem arrays live */
 enum { PDLP_A_FP64 = 0, PDLP_A_FP32 = 1 };                        /* matrix values in the steps */
-enum { PDLP_OPTIMAL = 1, PDLP_ITER_LIMIT = 2, PDLP_TIME_LIMIT = 3, PDLP_NUMERICAL_ERROR = 4 };
+enum { PDLP_OPTIMAL = 1, PDLP_ITER_LIMIT = 2, PDLP_TIME_LIMIT = 3, PDLP_NUMERICAL_ERROR = 4,
+       PDLP_PRIMAL_INFEASIBLE = 5, PDLP_DUAL_INFEASIBLE = 6 };
 enum {
   PDLP_OK = 0,
   PDLP_ERR_ARG = -1,          /* NULL pointer, bad size or option */
@@ -115,6 +116,17 @@ typedef struct {
   int32_t handoff_streams;    /* batch handles: LPs finished at once after the hand-off, each on a
                                  stream of its own (1..16, default 8), the LPs farthest from the
                                  tolerance first */
+  int32_t detect_infeas;      /* 1 (default): test infeasibility certificates at every evaluation
+                                 (Section 2.2): the last accepted step and the epoch displacement
+                                 z - z^{n,0} as candidate rays, Farkas' lemma on the unscaled LP;
+                                 0: never (an infeasible LP then runs to a limit) */
+  double eps_infeas;          /* tolerance of the certificate tests (default 1e-8): a dual ray y
+                                 (clipped to the sign of each inequality row, lam =
+                                 proj_Lambda(-A'y)) needs b'y + l'lam+ - u'lam- > 0 and
+                                 ||A'y + lam|| <= eps times it; a primal ray x (projected onto the
+                                 recession cone of [l, u]) needs c'x < 0 and its violation of the
+                                 row cones <= eps |c'x|; each objective must also exceed eps times
+                                 the sum of the magnitudes of its terms */
 } pdlp_options;
 
 typedef struct {
@@ -135,6 +147,12 @@ typedef struct {
                                    pdlp_batch_schedule) */
   int64_t handoff_k;          /* an LP of a batch: accepted steps when the single-LP kernels took
                                  it over (0: it ended in the persistent launch) */
+  double ray_obj, ray_res;    /* PRIMAL_INFEASIBLE: b'y + l'lam+ - u'lam- and ||A'y + lam|| of the
+                                 returned unit dual ray; DUAL_INFEASIBLE: c'x and the row-cone
+                                 violation of the returned unit primal ray; 0 otherwise */
+  int32_t ray_source;         /* the candidate that certified: 0 the last accepted step, 1 the
+                                 epoch displacement */
+  int32_t reserved;
 } pdlp_info;
 
 /* Scaled-space state of the current iterate (for parity checks and resume). */
@@ -177,7 +195,10 @@ int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, doubl
 
 /* Copy the solution of the last pdlp_solve to host buffers: x[n], y[m]
  * (user orientation) and reduced_cost[n] (lambda = proj_Lambda(c - A'y)); any
- * of them and info may be NULL.  PDLP_ERR_STATE before the first solve. */
+ * of them and info may be NULL.  After PDLP_PRIMAL_INFEASIBLE, y is the unit
+ * dual ray and reduced_cost its multipliers lam (A'y + lam ~ 0); after
+ * PDLP_DUAL_INFEASIBLE, x is the unit primal ray.  PDLP_ERR_STATE before the
+ * first solve. */
 int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* reduced_cost, pdlp_info* info);
 
 /* The current iterate in the scaled >= form (x~[n], y~[m]; NULL to skip) and

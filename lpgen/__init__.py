@@ -322,7 +322,11 @@ def permute(p: Problem, row_perm: np.ndarray, col_perm: np.ndarray) -> Problem:
     q = Problem(p.m, p.n, row_ptr, col_idx, val, p.c[col_perm], p.b[row_perm],
                 p.l[col_perm], p.u[col_perm], p.row_type[row_perm], p.name + "+perm")
     if p.x_star is not None:
-        q.x_star, q.y_star, q.lam_star = p.x_star[col_perm], p.y_star[row_perm], p.lam_star[col_perm]
+        q.x_star = p.x_star[col_perm]
+    if p.y_star is not None:
+        q.y_star = p.y_star[row_perm]
+    if p.lam_star is not None:
+        q.lam_star = p.lam_star[col_perm]
     return q
 
 

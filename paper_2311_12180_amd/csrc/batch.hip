@@ -200,8 +200,15 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         const int cur = S->cur, init = S->initial, pend = S->has_pending;
         const double pw = S->pending_w, se = S->sum_eta;
         const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+        const double* __restrict__ xp = sel(cur, p.x[1], p.x[0]);
+        const bool rays = p.infeas && !init;
         for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
           const double xj = x[j];
+          if (rays) {   // the primal candidate rays of the infeasibility test
+            const double lj = p.l[j], uj = p.u[j];
+            p.xr[0][j] = recession(xj - xp[j], lj, uj);
+            p.xr[1][j] = recession(xj - p.x0[j], lj, uj);
+          }
           double xb = xj;
           if (!init && se > 0.0) {
             double s = p.xsum[j];
@@ -241,11 +248,36 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         const EvalColsOp op(p, S);
         plain_sweep<LV, 2>(mt, p.KT, LT, op, acc, lds, red);
         block_sum<6, kBW>(acc, red);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0)
           for (int k = 0; k < 6; ++k) E[12 + k] = acc[k];
-          eval_decision(S, p, tr, E, qn0, cn0);
+      }
+      if (p.infeas && !S->initial) {
+        // Section 2.2 infeasibility certificates (the x-space rays were
+        // written above; the rows pass writes the y-space rays)
+        __syncthreads();
+        {
+          double acc[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+          const InfeasRowsOp op(p, S);
+          plain_sweep<LV, 2>(mk, p.K, LK, op, acc, lds, red);
+          block_sum<8, kBW>(acc, red);
+          if (threadIdx.x == 0)
+            for (int k = 0; k < 8; ++k) E[18 + k] = acc[k];
+        }
+        __syncthreads();
+        {
+          double acc[12];
+#pragma unroll
+          for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+          const InfeasColsOp op(p, S);
+          plain_sweep<LV, 2>(mt, p.KT, LT, op, acc, lds, red);
+          block_sum<12, kBW>(acc, red);
+          if (threadIdx.x == 0)
+            for (int k = 0; k < 12; ++k) E[26 + k] = acc[k];
         }
       }
+      if (threadIdx.x == 0) eval_decision(S, p, tr, E, qn0, cn0);
       __syncthreads();
       if (S->restart_flag) {
         const int cur = S->cur, cand = S->cand_avg;
@@ -320,8 +352,13 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
     plain_sweep<LV, 1>(mt, p.KT, LT, op, dummy, lds, red);
     const int cur = S->cur, ra = S->ret_avg;
     const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
+    double f = 1.0;
+    if (S->status == 5) {   // the unit dual ray of a primal-infeasibility certificate
+      y = p.yr[S->ray_src];
+      f = S->ray_scale;
+    }
     for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
-      const double v = p.D1[i] * y[i];
+      const double v = p.D1[i] * y[i] * f;
       p.yo[i] = p.le[i] ? -v : v;
     }
   }
@@ -338,8 +375,8 @@ template <bool LV>
 __global__ __launch_bounds__(kBB) void k_batch(Params p, BatchParams bp) {
   extern __shared__ double dyn[];
   __shared__ DevState S;
-  __shared__ double red[8 * kBW];
-  __shared__ double E[18];
+  __shared__ double red[12 * kBW];
+  __shared__ double E[38];
   __shared__ int slot;
   double* lds = dyn;
   double* ly = bp.lds_m > 0 ? dyn + 2 * kBT : nullptr;

@@ -22,7 +22,8 @@
 //   dual op   (rows of K~)  : y'_i = proj(y_i + eta*omega*(q_i - (K~x)_i - 2(K~dx)_i))
 //   k_decide                : the Algorithm 2 step-size decision on the reduced norms
 //   eval ops, k_eval_decide : averages, eq. (kkt) on current and average iterate,
-//                             Section 4.1 termination, Section 3.4 restart decision
+//                             Section 4.1 termination, Section 2.2 infeasibility
+//                             certificates, Section 3.4 restart decision
 //   restart ops             : apply the restart (new z^{n+1,0}, K~x)
 #include <math.h>
 
@@ -152,9 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
   const int cur = st->cur, init = st->initial, pend = st->has_pending;
   const double pw = st->pending_w, se = st->sum_eta;
   const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+  const double* __restrict__ xp = sel(cur, p.x[1], p.x[0]);
+  const bool rays = p.infeas && !init;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gridDim.x * kBlock) {
     const double xj = x[j];
+    if (rays) {   // the primal candidate rays of the infeasibility test
+      const double lj = p.l[j], uj = p.u[j];
+      p.xr[0][j] = recession(xj - xp[j], lj, uj);
+      p.xr[1][j] = recession(xj - p.x0[j], lj, uj);
+    }
     double xb = xj;
     if (!init && se > 0.0) {
       double s = p.xsum[j];
@@ -184,26 +192,47 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
 // Single-workgroup reduction of every evaluation partial in a fixed order,
 // then the evaluation decision.
 __global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0_blocks) {
-  __shared__ double red[18 * (kDecideBlock / 64)];
+  __shared__ double red[20 * (kDecideBlock / 64)];
+  __shared__ double E[38];
   DevState* st = p.st;
   if (eval_idle(st)) return;
-  double S[18];
+  {
+    double S[18];
 #pragma unroll
-  for (int k = 0; k < 18; ++k) S[k] = 0.0;
-  for (int i = threadIdx.x; i < n_e0_blocks; i += kDecideBlock) {
+    for (int k = 0; k < 18; ++k) S[k] = 0.0;
+    for (int i = threadIdx.x; i < n_e0_blocks; i += kDecideBlock) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) S[k] += p.partE0[4 * i + k];
+      for (int k = 0; k < 4; ++k) S[k] += p.partE0[4 * i + k];
+    }
+    for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) S[4 + k] += p.partE1[8 * i + k];
+    }
+    for (int i = threadIdx.x; i < p.KT.nred; i += kDecideBlock) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) S[12 + k] += p.partE2[6 * i + k];
+    }
+    block_sum<18, kDecideBlock / 64>(S, red);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 18; ++k) E[k] = S[k];
   }
-  for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
+  if (p.infeas && !st->initial) {
+    double T[20];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) S[4 + k] += p.partE1[8 * i + k];
-  }
-  for (int i = threadIdx.x; i < p.KT.nred; i += kDecideBlock) {
+    for (int k = 0; k < 20; ++k) T[k] = 0.0;
+    for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) S[12 + k] += p.partE2[6 * i + k];
+      for (int k = 0; k < 8; ++k) T[k] += p.partE3[8 * i + k];
+    }
+    for (int i = threadIdx.x; i < p.KT.nred; i += kDecideBlock) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) T[8 + k] += p.partE4[12 * i + k];
+    }
+    block_sum<20, kDecideBlock / 64>(T, red);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 20; ++k) E[18 + k] = T[k];
   }
-  block_sum<18, kDecideBlock / 64>(S, red);
-  if (threadIdx.x == 0) eval_decision(st, p, p.tr, S, p.qnorm0, p.cnorm0);
+  if (threadIdx.x == 0) eval_decision(st, p, p.tr, E, p.qnorm0, p.cnorm0);
 }
 
 // x-space part of a restart: z^{n+1,0} = candidate, sums cleared.  The flag
@@ -261,8 +290,13 @@ __global__ __launch_bounds__(kBlock) void k_output_y(Params p) {
   const DevState* st = p.st;
   const int cur = st->cur, ra = st->ret_avg;
   const double* __restrict__ y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
+  double f = 1.0;
+  if (st->status == 5) {   // the unit dual ray of a primal-infeasibility certificate
+    y = p.yr[st->ray_src];
+    f = st->ray_scale;
+  }
   for (int i = p.row_base + blockIdx.x * kBlock + threadIdx.x; i < p.row_base + p.m; i += gridDim.x * kBlock) {
-    const double v = p.D1[i] * y[i];
+    const double v = p.D1[i] * y[i] * f;
     p.yo[i] = p.le[i] ? -v : v;
   }
 }
@@ -315,6 +349,10 @@ void launch_eval(const Params& p, hipStream_t s) {
   hipLaunchKernelGGL(k_eval_x, dim3(ge), dim3(kBlock), 0, s, p);
   launch_op<EvalRowsOp, double>(p, p.K, s);
   launch_op<EvalColsOp, double>(p, p.KT, s);
+  if (p.infeas) {
+    launch_op<InfeasRowsOp, double>(p, p.K, s);
+    launch_op<InfeasColsOp, double>(p, p.KT, s);
+  }
   hipLaunchKernelGGL(k_eval_decide, dim3(1), dim3(kDecideBlock), 0, s, p, ge);
   hipLaunchKernelGGL(k_restart_x, dim3(ge), dim3(kBlock), 0, s, p);
   if (p.use_f32) launch_op<RestartYOp, float>(p, p.K, s);

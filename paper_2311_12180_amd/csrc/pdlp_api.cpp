@@ -250,7 +250,8 @@ struct pdlp_handle {
   std::vector<int64_t> handoff_h;
   struct Lane {
     hipStream_t s = nullptr;
-    double *pa = nullptr, *pb = nullptr, *pe0 = nullptr, *pe1 = nullptr, *pe2 = nullptr;
+    double *pa = nullptr, *pb = nullptr, *pe0 = nullptr, *pe1 = nullptr, *pe2 = nullptr, *pe3 = nullptr,
+           *pe4 = nullptr;
     DevState* hst[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
   };
@@ -327,6 +328,8 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->batch_grid = 0;
   o->batch_handoff = 2048;
   o->handoff_streams = 8;
+  o->detect_infeas = 1;
+  o->eps_infeas = 1e-8;
   return PDLP_OK;
 }
 
@@ -354,6 +357,8 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
   if (o.batch_handoff < 0) return why = "batch_handoff must be >= 0", -1;
   if (o.handoff_streams < 1 || o.handoff_streams > 16) return why = "handoff_streams must be in 1..16", -1;
+  if (o.detect_infeas != 0 && o.detect_infeas != 1) return why = "detect_infeas must be 0 or 1", -1;
+  if (!(o.eps_infeas > 0.0) || !std::isfinite(o.eps_infeas)) return why = "eps_infeas must be finite and > 0", -1;
   return 0;
 }
 
@@ -733,6 +738,14 @@ static void alloc_iterates(pdlp_handle* h) {
   P.eps_zero = opt.eps_zero;
   P.tie_rel = 1e-12;
   P.omega_power = opt.kkt_omega_power;
+  P.infeas = opt.detect_infeas;
+  P.eps_infeas = opt.eps_infeas;
+  if (P.infeas) {
+    for (int k = 0; k < 2; ++k) {
+      P.xr[k] = h->dalloc<double>(n);
+      P.yr[k] = h->dalloc<double>(m);
+    }
+  }
   h->xo = h->dalloc<double>(n);
   h->yo = h->dalloc<double>(m);
   h->rco = h->dalloc<double>(n);
@@ -836,6 +849,10 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
     P.partE1 = h->dalloc<double>(8 * redk);
     P.partE2 = h->dalloc<double>(6 * redt);
+    if (P.infeas) {
+      P.partE3 = h->dalloc<double>(8 * redk);
+      P.partE4 = h->dalloc<double>(12 * redt);
+    }
     h->st = h->dalloc<DevState>(1);
     P.st = h->st;
     P.cnorm0 = std::sqrt(hred[0]);
@@ -933,6 +950,9 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.solve_s = now_s() - t0;
   I.layout_k = (h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0)) + (h->P.K.grid > 0 ? 4 : 0);
   I.layout_kt = (h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0)) + (h->P.KT.grid > 0 ? 4 : 0);
+  I.ray_source = f->ray_src;
+  I.ray_obj = f->ray_obj;
+  I.ray_res = f->ray_res;
 }
 
 extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
@@ -1554,6 +1574,8 @@ static Params handoff_params(const pdlp_handle* h, int32_t b, const pdlp_handle:
   sp.partE0 = L.pe0;
   sp.partE1 = L.pe1;
   sp.partE2 = L.pe2;
+  sp.partE3 = L.pe3;
+  sp.partE4 = L.pe4;
   sp.st = h->bst + b;
   if (!(h->opt.trace > 0 && b == 0)) sp.tr = Trace{};
   sp.qnorm0 = std::sqrt(h->norms_h[4 * (size_t)b]);
@@ -1571,6 +1593,8 @@ static void handoff_lanes(pdlp_handle* h, size_t want) {
     L.pe0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
     L.pe1 = h->dalloc<double>(8 * (size_t)h->max_hk);
     L.pe2 = h->dalloc<double>(6 * (size_t)h->max_ht);
+    L.pe3 = h->dalloc<double>(8 * (size_t)h->max_hk);
+    L.pe4 = h->dalloc<double>(12 * (size_t)h->max_ht);
     for (int k = 0; k < 2; ++k) {
       void* hp = nullptr;
       check(hipHostMalloc(&hp, sizeof(DevState), hipHostMallocDefault), "hipHostMalloc");
@@ -1786,6 +1810,9 @@ extern "C" int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, d
       I.layout_k = h->lanes_h[2 * (size_t)b];
       I.layout_kt = h->lanes_h[2 * (size_t)b + 1];
       I.handoff_k = h->handoff_h[(size_t)b];
+      I.ray_source = f.ray_src;
+      I.ray_obj = f.ray_obj;
+      I.ray_res = f.ray_res;
     }
   }
   return PDLP_OK;

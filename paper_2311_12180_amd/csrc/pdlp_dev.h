@@ -82,12 +82,14 @@ struct DevState {
   int32_t restart_flag;   // the evaluation asked for a restart (applied by the restart kernels)
   int32_t cand_avg;       // restart candidate / returned point is the average
   int32_t ret_avg;
-  int32_t pad;
+  int32_t ray_src;        // infeasibility certificate: 0 the last accepted step, 1 the epoch displacement
   // termination parameters of this solve
   double eps_rel;
   int64_t max_iter;
   // last evaluation, returned point
   double rel_kkt, rel_gap, rel_p, rel_d, pobj, dobj;
+  // infeasibility certificate (statuses 5, 6): 1 / ||ray|| and the unit ray's objective and residual
+  double ray_scale, ray_obj, ray_res;
   int64_t n_att, n_eval;  // trace entries written
 };
 
@@ -138,9 +140,17 @@ struct Params {
   double tie_rel;         // relative band in which the candidate comparison is a tie
   int32_t omega_power;
   double qnorm0, cnorm0;
+  // infeasibility detection: candidate rays of the last evaluation (scaled
+  // space, projected), their partials, the tolerance (infeas = 0: off)
+  int32_t infeas;
+  double eps_infeas;
+  double* xr[2];          // [n] each: the last step's and the epoch displacement's x, projected
+  double* yr[2];          // [m] each: the same for y, clipped at 0 on inequality rows
+  double* partE3;         // 8 per partial of the rows of K~
+  double* partE4;         // 12 per partial of the rows of K~'
 };
 
-constexpr int32_t kPaused = 5;   // internal status of a batched LP handed to the single-LP kernels
+constexpr int32_t kPaused = 16;  // internal status of a batched LP handed to the single-LP kernels
 
 // Batched solve (many independent LPs packed block-diagonally into one Params).
 struct BatchParams {

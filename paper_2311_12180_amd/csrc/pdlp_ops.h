@@ -390,6 +390,103 @@ struct EvalColsOp {
   }
 };
 
+// ---- infeasibility detection (Section 2.2).  Two candidate rays per
+// evaluation: the last accepted step (z minus the previous iterate, which sits
+// in the other buffer) and the epoch displacement z - z^{n,0} (the normalized
+// iterate without its 1/t).  Farkas' lemma is tested on the unscaled LP; the
+// diagonal scalings are positive, so the projections below commute with them.
+
+// Projection onto the recession cone of [l, u].
+__device__ __forceinline__ double recession(double d, double l, double u) {
+  const bool lf = isfinite(l), uf = isfinite(u);
+  if (lf && uf) return 0.0;
+  if (lf) return d > 0.0 ? d : 0.0;
+  if (uf) return d < 0.0 ? d : 0.0;
+  return d;
+}
+
+// Rows of K~: gathers the two primal candidates x_r (written by the x-space
+// evaluation pass), forms the two dual candidates y_r (clipped at 0 on
+// inequality rows; written to p.yr for the column pass and the output).  Per
+// candidate: ||violation of the row cones by K x_r||^2 (unscaled: K~x_r / D1),
+// q'y_r, sum |q_i y_r,i|, ||D1 y_r||^2.
+struct InfeasRowsOp {
+  static constexpr int NV = 2, NACC = 8;
+  __device__ static bool idle(const DevState* st) { return eval_idle(st) | st->initial; }
+  __device__ static const DevCsr& mat(const Params& p) { return p.K; }
+  __device__ static double* part(const Params& p) { return p.partE3; }
+  const Params* pp;
+  const double* __restrict__ y;
+  const double* __restrict__ yp;
+  __device__ InfeasRowsOp(const Params& p, const DevState* st) : pp(&p) {
+    const int cur = st->cur;
+    y = sel(cur, p.y[0], p.y[1]);
+    yp = sel(cur, p.y[1], p.y[0]);
+  }
+  __device__ void gather(int j, double* g) const {
+    g[0] = pp->xr[0][j];
+    g[1] = pp->xr[1][j];
+  }
+  __device__ void epi(int i, const double* s, double* acc) const {
+    const Params& p = *pp;
+    const double d1 = p.D1[i], qi = p.q[i], yi = y[i];
+    const bool ie = p.ineq[i] != 0;
+    const double base[2] = {yp[i], p.y0[i]};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double kv = s[c] / d1;
+      const double v = ie ? (kv < 0.0 ? kv : 0.0) : kv;
+      acc[4 * c + 0] += v * v;
+      double r = yi - base[c];
+      if (ie && r < 0.0) r = 0.0;
+      p.yr[c][i] = r;
+      const double t = qi * r;
+      acc[4 * c + 1] += t;
+      acc[4 * c + 2] += fabs(t);
+      const double ru = d1 * r;
+      acc[4 * c + 3] += ru * ru;
+    }
+  }
+};
+
+// Rows of K~': gathers the dual candidates y_r.  Per candidate: g = -K'y_r
+// (unscaled: -K~'y_r / D2), lam = proj_Lambda(g), ||g - lam||^2,
+// l'lam+ - u'lam- and the sum of its terms' magnitudes, c'x_r, sum |c_j x_r,j|,
+// ||D2 x_r||^2.
+struct InfeasColsOp {
+  static constexpr int NV = 2, NACC = 12;
+  __device__ static bool idle(const DevState* st) { return eval_idle(st) | st->initial; }
+  __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
+  __device__ static double* part(const Params& p) { return p.partE4; }
+  const Params* pp;
+  __device__ InfeasColsOp(const Params& p, const DevState*) : pp(&p) {}
+  __device__ void gather(int i, double* g) const {
+    g[0] = pp->yr[0][i];
+    g[1] = pp->yr[1][i];
+  }
+  __device__ void epi(int j, const double* s, double* acc) const {
+    const Params& p = *pp;
+    const double d2 = p.D2[j], lj = p.l[j] * d2, uj = p.u[j] * d2, cj = p.c[j];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double g = -s[c] / d2;
+      const double lam = proj_lambda(g, lj, uj);
+      const double r = g - lam;
+      acc[6 * c + 0] += r * r;
+      const double lp = lam > 0.0 ? lam : 0.0, lm = lam < 0.0 ? -lam : 0.0;
+      const double tl = lp > 0.0 ? lj * lp : 0.0, tu = lm > 0.0 ? uj * lm : 0.0;
+      acc[6 * c + 1] += tl - tu;
+      acc[6 * c + 2] += fabs(tl) + fabs(tu);
+      const double xr = p.xr[c][j];
+      const double t = cj * xr;
+      acc[6 * c + 3] += t;
+      acc[6 * c + 4] += fabs(t);
+      const double xu = d2 * xr;
+      acc[6 * c + 5] += xu * xu;
+    }
+  }
+};
+
 // y-space part of a restart plus K~x of the new x (in the precision of the
 // steps).  The x-space part (k_restart_x) has run before.
 struct RestartYOp {
@@ -421,6 +518,9 @@ struct RestartYOp {
 };
 
 // Output over the rows of K~': x = D2 x~, lambda = D2^-1 proj_Lambda(c~ - K~'y~).
+// With a certificate of primal infeasibility (status 5) y~ is the dual ray and
+// lambda its multipliers D2^-1 proj_Lambda(-K~'y~), scaled to the unit ray;
+// with one of dual infeasibility (status 6) x is the unit primal ray.
 struct OutputOp {
   static constexpr int NV = 1, NACC = 0;
   __device__ static bool idle(const DevState*) { return false; }
@@ -429,17 +529,29 @@ struct OutputOp {
   const Params* pp;
   const double* __restrict__ x;
   const double* __restrict__ y;
+  double xs, cs, ls;
   __device__ OutputOp(const Params& p, const DevState* st) : pp(&p) {
     const int cur = st->cur, ra = st->ret_avg;
     x = ra ? p.xbar : sel(cur, p.x[0], p.x[1]);
     y = ra ? p.ybar : sel(cur, p.y[0], p.y[1]);
+    xs = 1.0;   // factor on x
+    cs = 1.0;   // weight of c in lambda
+    ls = 1.0;   // factor on lambda
+    if (st->status == 5) {
+      y = p.yr[st->ray_src];
+      cs = 0.0;
+      ls = st->ray_scale;
+    } else if (st->status == 6) {
+      x = p.xr[st->ray_src];
+      xs = st->ray_scale;
+    }
   }
   __device__ void gather(int i, double* g) const { g[0] = y[i]; }
   __device__ void epi(int j, const double* s, double*) const {
     const Params& p = *pp;
     const double d2 = p.D2[j];
-    p.xo[j] = d2 * x[j];
-    p.rco[j] = proj_lambda(p.c[j] - s[0], p.l[j], p.u[j]) / d2;
+    p.xo[j] = d2 * x[j] * xs;
+    p.rco[j] = proj_lambda(cs * p.c[j] - s[0], p.l[j], p.u[j]) / d2 * ls;
   }
 };
 
@@ -510,6 +622,7 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
                               double cnorm0) {
   // S: 0 c'x 1 c'xb 2 |x-x0|^2 3 |xb-x0|^2 | 4,5 rp2 scaled 6,7 rp2 unscaled 8,9 q'y 10,11 |y-y0|^2
   //    | 12,13 rd2 scaled 14,15 rd2 unscaled 16,17 l'lam+ - u'lam-     (pairs: current, average)
+  //    | 18 + 4c: InfeasRowsOp of candidate c | 26 + 6c: InfeasColsOp of candidate c (when p.infeas)
   const double omega = st->omega;
   double pobj[2], dobj[2], rel[2], rg[2], rpr[2], rdr[2];
   for (int it = 0; it < 2; ++it) {
@@ -562,6 +675,47 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
   if (rel[0] <= st->eps_rel || rel[1] <= st->eps_rel) {
     st->status = 1; st->ret_avg = avg_better; store(avg_better); st->done = 1;
     return;
+  }
+  if (p.infeas) {
+    // Farkas certificates: a dual ray (primal infeasibility) before a primal
+    // ray (dual infeasibility), the last step before the displacement.  A ray's
+    // objective must exceed eps times the magnitudes it is summed from.
+    const double eps = p.eps_infeas;
+    double dro[2], dres[2], dnrm[2], pro[2], pres[2], pnrm[2];
+    bool dok[2], pok[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      dro[c] = S[19 + 4 * c] + S[27 + 6 * c];
+      dres[c] = sqrt(S[26 + 6 * c]);
+      dnrm[c] = sqrt(S[21 + 4 * c]);
+      dok[c] = dro[c] > 0.0 && dro[c] > eps * (S[20 + 4 * c] + S[28 + 6 * c]) && dres[c] <= eps * dro[c];
+      pro[c] = S[29 + 6 * c];
+      pres[c] = sqrt(S[18 + 4 * c]);
+      pnrm[c] = sqrt(S[31 + 6 * c]);
+      pok[c] = pro[c] < 0.0 && -pro[c] > eps * S[30 + 6 * c] && pres[c] <= eps * -pro[c];
+    }
+    int kind = 0, src = 0;
+    if (dok[0]) { kind = 5; src = 0; }
+    else if (dok[1]) { kind = 5; src = 1; }
+    else if (pok[0]) { kind = 6; src = 0; }
+    else if (pok[1]) { kind = 6; src = 1; }
+    if (kind) {
+      // (selects rather than indexing by src, which would put the arrays in scratch)
+      const bool d = kind == 5, s1 = src == 1;
+      const double nrm = d ? (s1 ? dnrm[1] : dnrm[0]) : (s1 ? pnrm[1] : pnrm[0]);
+      const double obj = d ? (s1 ? dro[1] : dro[0]) : (s1 ? pro[1] : pro[0]);
+      const double res = d ? (s1 ? dres[1] : dres[0]) : (s1 ? pres[1] : pres[0]);
+      const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      st->status = kind;
+      st->ret_avg = 0;
+      st->ray_src = src;
+      st->ray_scale = sc;
+      st->ray_obj = obj * sc;
+      st->ray_res = res * sc;
+      store(0);
+      st->done = 1;
+      return;
+    }
   }
   if (st->k >= st->max_iter) {
     st->status = 2; st->ret_avg = avg_better; store(avg_better); st->done = 1;

@@ -21,9 +21,11 @@ PDLP_ROW_EQ, PDLP_ROW_GE, PDLP_ROW_LE = 0, 1, 2
 PDLP_MEM_HOST, PDLP_MEM_DEVICE = 0, 1
 PDLP_A_FP64, PDLP_A_FP32 = 0, 1
 PDLP_OPTIMAL, PDLP_ITER_LIMIT, PDLP_TIME_LIMIT, PDLP_NUMERICAL_ERROR = 1, 2, 3, 4
+PDLP_PRIMAL_INFEASIBLE, PDLP_DUAL_INFEASIBLE = 5, 6
 PDLP_OK, PDLP_ERR_ARG, PDLP_ERR_DATA, PDLP_ERR_HIP, PDLP_ERR_OOM, PDLP_ERR_STATE, PDLP_ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-STATUS = {0: "NONE", 1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL_ERROR"}
+STATUS = {0: "NONE", 1: "OPTIMAL", 2: "ITER_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL_ERROR",
+          5: "PRIMAL_INFEASIBLE", 6: "DUAL_INFEASIBLE"}
 ERRORS = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_DATA", -3: "PDLP_ERR_HIP", -4: "PDLP_ERR_OOM",
           -5: "PDLP_ERR_STATE", -6: "PDLP_ERR_UNSUPPORTED"}
 
@@ -55,7 +57,8 @@ class pdlp_options(C.Structure):
                 ("kkt_omega_power", C.c_int32), ("trace", C.c_int32), ("poll_every", C.c_int32),
                 ("graph", C.c_int32), ("spmv_layout", C.c_int32), ("batch_lanes", C.c_int32),
                 ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32),
-                ("batch_handoff", C.c_int32), ("handoff_streams", C.c_int32)]
+                ("batch_handoff", C.c_int32), ("handoff_streams", C.c_int32),
+                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double)]
 
 
 class pdlp_info(C.Structure):
@@ -65,7 +68,8 @@ class pdlp_info(C.Structure):
                 ("rel_dres", C.c_double), ("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("omega", C.c_double), ("eta_hat", C.c_double), ("setup_s", C.c_double),
                 ("solve_s", C.c_double), ("layout_k", C.c_int32), ("layout_kt", C.c_int32),
-                ("handoff_k", C.c_int64)]
+                ("handoff_k", C.c_int64), ("ray_obj", C.c_double), ("ray_res", C.c_double),
+                ("ray_source", C.c_int32), ("reserved", C.c_int32)]
 
 
 class pdlp_iter_state(C.Structure):
