@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--profile-attempts", type=int, default=200)
     ap.add_argument("--layout", type=int, nargs=2, default=(-1, -2), metavar=("K", "KT"),
                     help="SpMV layouts of K and K' (-1: chosen at create by timing; pin them for profiler runs)")
+    ap.add_argument("--detect-infeas", type=int, default=1, choices=(0, 1),
+                    help="infeasibility certificates at every evaluation (the library default is on)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-LP section")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-sample", type=int, default=64)
@@ -304,7 +306,7 @@ def main():
 
     stream = torch.cuda.current_stream().cuda_stream
     h = P.pdlp_create(prob, stream=stream, eps_rel=0.0, max_iter=args.warmup, time_limit_s=600.0,
-                      spmv_layout=args.layout[0], spmv_layout_kt=args.layout[1])
+                      spmv_layout=args.layout[0], spmv_layout_kt=args.layout[1], detect_infeas=args.detect_infeas)
     _, _, _, info0 = None, None, None, None
     P.pdlp_solve(h)            # warm-up: graph capture, first launches
     log(f"setup {P.pdlp_get_solution(h)[3]['setup_s']:.2f}s; warm-up {args.warmup} steps done")

@@ -116,8 +116,9 @@ typedef struct {
   int32_t handoff_streams;    /* batch handles: LPs finished at once after the hand-off, each on a
                                  stream of its own (1..16, default 8), the LPs farthest from the
                                  tolerance first */
-  int32_t detect_infeas;      /* 1 (default): test infeasibility certificates at every evaluation
-                                 (Section 2.2): the last accepted step and the epoch displacement
+  int32_t detect_infeas;      /* 1 (default): test infeasibility certificates at every
+                                 infeas_every-th evaluation (Section 2.2, "periodically"): the last
+                                 accepted step and the epoch displacement
                                  z - z^{n,0} as candidate rays, Farkas' lemma on the unscaled LP;
                                  0: never (an infeasible LP then runs to a limit) */
   double eps_infeas;          /* tolerance of the certificate tests (default 1e-8): a dual ray y
@@ -127,6 +128,8 @@ typedef struct {
                                  recession cone of [l, u]) needs c'x < 0 and its violation of the
                                  row cones <= eps |c'x|; each objective must also exceed eps times
                                  the sum of the magnitudes of its terms */
+  int32_t infeas_every;       /* evaluations per certificate test, >= 1 (default 4: the two extra
+                                 products cost ~3 % of the run when done at every evaluation) */
 } pdlp_options;
 
 typedef struct {

@@ -52,7 +52,7 @@ class _Options(C.Structure):
                 ("pw_theta", C.c_double), ("eps_zero", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
                 ("kkt_omega_power", C.c_int32), ("threads", C.c_int32), ("detect_infeas", C.c_int32),
-                ("eps_infeas", C.c_double)]
+                ("eps_infeas", C.c_double), ("infeas_every", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -150,7 +150,8 @@ class Result:
 def solve(prob, trace_cap: int = 0, **opts) -> Result:
     """Solve with the oracle.  Options: eps_rel, max_iter, time_limit_s,
     eval_period, ruiz_iters, pc_alpha, pw_theta, eps_zero, beta_suff, beta_nec,
-    beta_art, a_precision, kkt_omega_power, threads, detect_infeas, eps_infeas.
+    beta_art, a_precision, kkt_omega_power, threads, detect_infeas, eps_infeas,
+    infeas_every.
     Status PRIMAL_INFEASIBLE returns a unit dual ray in y (and its multipliers
     in rc), DUAL_INFEASIBLE a unit primal ray in x."""
     h = _Held(prob)

@@ -36,8 +36,9 @@
  *   - the candidate comparison KKT(current) < KKT(average) treats a relative
  *     difference below 1e-12 as a tie, which goes to the average;
  *   - the start is proj_X(0), y = 0;
- *   - infeasibility detection (Section 2.2 names the two sequences and defers
- *     the test to its citation): at every evaluation that does not terminate,
+ *   - infeasibility detection (Section 2.2 names the two sequences, says they
+ *     are checked periodically and defers the test to its citation): at every
+ *     infeas_every-th evaluation (default 4) that does not terminate,
  *     the last accepted step z - z_prev and the epoch displacement z - z^{n,0}
  *     (the normalized iterate without its 1/t, which the scale-free tests
  *     ignore) are each tested on the unscaled LP against Farkas' lemma:
@@ -554,6 +555,7 @@ void orc_default_options(orc_options* o) {
   o->threads = 0;
   o->detect_infeas = 1;
   o->eps_infeas = 1e-8;
+  o->infeas_every = 4;
 }
 
 static int check_problem(const orc_problem* p) {
@@ -644,7 +646,7 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
               double* rc, orc_info* info, orc_trace* tr, double* x_hat, double* y_hat) {
   orc_options o;
   if (opt) o = *opt; else orc_default_options(&o);
-  if (check_problem(p) || o.eval_period < 1 || o.max_iter < 0) return -1;
+  if (check_problem(p) || o.eval_period < 1 || o.max_iter < 0 || o.infeas_every < 1) return -1;
 #ifdef _OPENMP
   if (o.threads > 0) omp_set_num_threads(o.threads);
 #endif
@@ -775,7 +777,7 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
     if (ec.rel.rel_kkt <= o.eps_rel || ea.rel.rel_kkt <= o.eps_rel) {
       status = 1; ret_avg = avg_better; ret_rel = avg_better ? ea.rel : ec.rel; break;
     }
-    if (o.detect_infeas) {
+    if (o.detect_infeas && evals % o.infeas_every == 0) {
       /* Section 2.2, infeasibility detection: the last accepted step z - z_prev
        * (z_prev sits in xn, yn after the swap) and the epoch displacement z - z^{n,0} */
       rays_t rr[2];

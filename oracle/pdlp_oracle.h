@@ -44,8 +44,9 @@ typedef struct {
   int32_t a_precision;    /* 0: FP64 matrix in the steps, 1: FP32-rounded scaled matrix in the steps */
   int32_t kkt_omega_power;/* 2: weights omega^2, 1/omega^2 as printed; 1: omega, 1/omega */
   int32_t threads;        /* OpenMP threads, 0 = runtime default */
-  int32_t detect_infeas;  /* 1: test the infeasibility certificates at every evaluation */
+  int32_t detect_infeas;  /* 1: test the infeasibility certificates */
   double eps_infeas;      /* tolerance of the certificate tests */
+  int32_t infeas_every;   /* test at every infeas_every-th evaluation (after the first step) */
 } orc_options;
 
 typedef struct {

@@ -201,7 +201,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         const double pw = S->pending_w, se = S->sum_eta;
         const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
         const double* __restrict__ xp = sel(cur, p.x[1], p.x[0]);
-        const bool rays = p.infeas && !init;
+        const bool rays = infeas_due(p, S);
         for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
           const double xj = x[j];
           if (rays) {   // the primal candidate rays of the infeasibility test
@@ -251,7 +251,7 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
         if (threadIdx.x == 0)
           for (int k = 0; k < 6; ++k) E[12 + k] = acc[k];
       }
-      if (p.infeas && !S->initial) {
+      if (infeas_due(p, S)) {
         // Section 2.2 infeasibility certificates (the x-space rays were
         // written above; the rows pass writes the y-space rays)
         __syncthreads();

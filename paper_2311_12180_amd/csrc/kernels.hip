@@ -46,7 +46,7 @@ template <class Op, typename VT>
 __global__ __launch_bounds__(kBlock) void k_fused(Params p) {
   __shared__ double lds[Op::NV * kTile];
   __shared__ double red[AccSize<Op>::RED];
-  if (Op::idle(p.st)) return;
+  if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
   const DevCsr& M = Op::mat(p);
   // one block per workgroup, or a persistent grid striding over the blocks;
@@ -75,7 +75,7 @@ template <class Op, typename VT>
 __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
   __shared__ double lds[Op::NV * kTile];
   __shared__ double red[Op::NV * (kBlock / 64)];
-  if (Op::idle(p.st)) return;
+  if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
   const PanelCsr& S = Op::mat(p).pan;
   double* __restrict__ part = S.part;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_rows(Params p) {
   __shared__ double red[AccSize<Op>::RED];
-  if (Op::idle(p.st)) return;
+  if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
   const DevCsr& M = Op::mat(p);
   const PanelCsr& S = M.pan;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
   const double pw = st->pending_w, se = st->sum_eta;
   const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
   const double* __restrict__ xp = sel(cur, p.x[1], p.x[0]);
-  const bool rays = p.infeas && !init;
+  const bool rays = infeas_due(p, st);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gridDim.x * kBlock) {
     const double xj = x[j];
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0
     if (threadIdx.x == 0)
       for (int k = 0; k < 18; ++k) E[k] = S[k];
   }
-  if (p.infeas && !st->initial) {
+  if (infeas_due(p, st)) {
     double T[20];
 #pragma unroll
     for (int k = 0; k < 20; ++k) T[k] = 0.0;

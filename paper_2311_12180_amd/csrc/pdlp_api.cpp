@@ -330,6 +330,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->handoff_streams = 8;
   o->detect_infeas = 1;
   o->eps_infeas = 1e-8;
+  o->infeas_every = 4;
   return PDLP_OK;
 }
 
@@ -359,6 +360,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.handoff_streams < 1 || o.handoff_streams > 16) return why = "handoff_streams must be in 1..16", -1;
   if (o.detect_infeas != 0 && o.detect_infeas != 1) return why = "detect_infeas must be 0 or 1", -1;
   if (!(o.eps_infeas > 0.0) || !std::isfinite(o.eps_infeas)) return why = "eps_infeas must be finite and > 0", -1;
+  if (o.infeas_every < 1) return why = "infeas_every must be >= 1", -1;
   return 0;
 }
 
@@ -740,6 +742,7 @@ static void alloc_iterates(pdlp_handle* h) {
   P.omega_power = opt.kkt_omega_power;
   P.infeas = opt.detect_infeas;
   P.eps_infeas = opt.eps_infeas;
+  P.infeas_every = opt.infeas_every;
   if (P.infeas) {
     for (int k = 0; k < 2; ++k) {
       P.xr[k] = h->dalloc<double>(n);

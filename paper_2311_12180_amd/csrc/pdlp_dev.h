@@ -143,6 +143,7 @@ struct Params {
   // infeasibility detection: candidate rays of the last evaluation (scaled
   // space, projected), their partials, the tolerance (infeas = 0: off)
   int32_t infeas;
+  int32_t infeas_every;   // evaluations per certificate test
   double eps_infeas;
   double* xr[2];          // [n] each: the last step's and the epoch displacement's x, projected
   double* yr[2];          // [m] each: the same for y, clipped at 0 on inequality rows

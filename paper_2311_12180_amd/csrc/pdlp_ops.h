@@ -197,14 +197,14 @@ __device__ __forceinline__ bool eval_idle(const DevState* st) { return st->done 
 // ---------------------------------------------------------------------------- ops
 //
 // An op provides: NV (gathered vectors), NACC (reduced quantities per row
-// epilogue), idle(st), mat(p) (which CSR copy), part(p) (its partials or
+// epilogue), idle(p, st), mat(p) (which CSR copy), part(p) (its partials or
 // nullptr), gather(col, g) and epi(row, s, acc).
 
 // Primal step over the rows of K~' (x-space); adds the previously accepted x
 // to the running weighted sum.
 struct PrimalOp {
   static constexpr int NV = 1, NACC = 1;
-  __device__ static bool idle(const DevState* st) { return attempt_idle(st); }
+  __device__ static bool idle(const Params&, const DevState* st) { return attempt_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
   __device__ static double* part(const Params& p) { return p.partA; }
   const double* __restrict__ y;
@@ -252,7 +252,7 @@ struct PrimalOp {
 // K~(2x' - x) = K~x + 2 K~dx and K~x' = K~x + K~dx.
 struct DualOp {
   static constexpr int NV = 1, NACC = 2;
-  __device__ static bool idle(const DevState* st) { return attempt_idle(st); }
+  __device__ static bool idle(const Params&, const DevState* st) { return attempt_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.K; }
   __device__ static double* part(const Params& p) { return p.partB; }
   const double* __restrict__ dx;
@@ -299,7 +299,7 @@ struct DualOp {
 // q'y_bar, ||y - y0||^2, ||y_bar - y0||^2; forms y_bar (flushing the pending weight).
 struct EvalRowsOp {
   static constexpr int NV = 2, NACC = 8;
-  __device__ static bool idle(const DevState* st) { return eval_idle(st); }
+  __device__ static bool idle(const Params&, const DevState* st) { return eval_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.K; }
   __device__ static double* part(const Params& p) { return p.partE1; }
   const Params* pp;
@@ -358,7 +358,7 @@ struct EvalRowsOp {
 // l'lambda+ - u'lambda-.
 struct EvalColsOp {
   static constexpr int NV = 2, NACC = 6;
-  __device__ static bool idle(const DevState* st) { return eval_idle(st); }
+  __device__ static bool idle(const Params&, const DevState* st) { return eval_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
   __device__ static double* part(const Params& p) { return p.partE2; }
   const Params* pp;
@@ -396,6 +396,13 @@ struct EvalColsOp {
 // iterate without its 1/t).  Farkas' lemma is tested on the unscaled LP; the
 // diagonal scalings are positive, so the projections below commute with them.
 
+// Whether the evaluation about to be decided tests the certificates: every
+// infeas_every-th evaluation after the starting point's (st->evals counts the
+// earlier ones).
+__device__ __forceinline__ bool infeas_due(const Params& p, const DevState* st) {
+  return p.infeas && !st->initial && (st->evals + 1) % p.infeas_every == 0;
+}
+
 // Projection onto the recession cone of [l, u].
 __device__ __forceinline__ double recession(double d, double l, double u) {
   const bool lf = isfinite(l), uf = isfinite(u);
@@ -412,7 +419,7 @@ __device__ __forceinline__ double recession(double d, double l, double u) {
 // q'y_r, sum |q_i y_r,i|, ||D1 y_r||^2.
 struct InfeasRowsOp {
   static constexpr int NV = 2, NACC = 8;
-  __device__ static bool idle(const DevState* st) { return eval_idle(st) | st->initial; }
+  __device__ static bool idle(const Params& p, const DevState* st) { return eval_idle(st) || !infeas_due(p, st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.K; }
   __device__ static double* part(const Params& p) { return p.partE3; }
   const Params* pp;
@@ -455,7 +462,7 @@ struct InfeasRowsOp {
 // ||D2 x_r||^2.
 struct InfeasColsOp {
   static constexpr int NV = 2, NACC = 12;
-  __device__ static bool idle(const DevState* st) { return eval_idle(st) | st->initial; }
+  __device__ static bool idle(const Params& p, const DevState* st) { return eval_idle(st) || !infeas_due(p, st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
   __device__ static double* part(const Params& p) { return p.partE4; }
   const Params* pp;
@@ -491,7 +498,7 @@ struct InfeasColsOp {
 // steps).  The x-space part (k_restart_x) has run before.
 struct RestartYOp {
   static constexpr int NV = 1, NACC = 0;
-  __device__ static bool idle(const DevState* st) { return !st->restart_flag; }
+  __device__ static bool idle(const Params&, const DevState* st) { return !st->restart_flag; }
   __device__ static const DevCsr& mat(const Params& p) { return p.K; }
   __device__ static double* part(const Params&) { return nullptr; }
   const Params* pp;
@@ -523,7 +530,7 @@ struct RestartYOp {
 // with one of dual infeasibility (status 6) x is the unit primal ray.
 struct OutputOp {
   static constexpr int NV = 1, NACC = 0;
-  __device__ static bool idle(const DevState*) { return false; }
+  __device__ static bool idle(const Params&, const DevState*) { return false; }
   __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
   __device__ static double* part(const Params&) { return nullptr; }
   const Params* pp;
@@ -559,7 +566,7 @@ struct OutputOp {
 template <int WHICH>
 struct ProbeOp {
   static constexpr int NV = 1, NACC = 0;
-  __device__ static bool idle(const DevState*) { return false; }
+  __device__ static bool idle(const Params&, const DevState*) { return false; }
   __device__ static const DevCsr& mat(const Params& p) { return WHICH ? p.KT : p.K; }
   __device__ static double* part(const Params&) { return nullptr; }
   const double* __restrict__ in;
@@ -665,6 +672,7 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
     st->cand_avg = 0;
     return;
   }
+  const bool due = infeas_due(p, st);
   st->evals++;
   st->k_last_eval = st->k;
   const int avg_better = rel[1] < rel[0];
@@ -676,7 +684,7 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
     st->status = 1; st->ret_avg = avg_better; store(avg_better); st->done = 1;
     return;
   }
-  if (p.infeas) {
+  if (due) {
     // Farkas certificates: a dual ray (primal infeasibility) before a primal
     // ray (dual infeasibility), the last step before the displacement.  A ray's
     // objective must exceed eps times the magnitudes it is summed from.

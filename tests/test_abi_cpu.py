@@ -130,6 +130,9 @@ def test_batch_rejects_bad_members_and_options(P):
                                     ([good], P.PDLP_ERR_ARG, "batch_handoff", {"batch_handoff": -1}),
                                     ([good], P.PDLP_ERR_ARG, "handoff_streams", {"handoff_streams": 0}),
                                     ([good], P.PDLP_ERR_ARG, "handoff_streams", {"handoff_streams": 17}),
+                                    ([good], P.PDLP_ERR_ARG, "detect_infeas", {"detect_infeas": 2}),
+                                    ([good], P.PDLP_ERR_ARG, "eps_infeas", {"eps_infeas": 0.0}),
+                                    ([good], P.PDLP_ERR_ARG, "infeas_every", {"infeas_every": 0}),
                                     ([], P.PDLP_ERR_ARG, "count", {})]:
         with pytest.raises(P.PdlpError) as e:
             P.pdlp_create_batch(probs, **opts)

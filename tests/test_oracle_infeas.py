@@ -130,6 +130,16 @@ def test_planted_families(gen, seed):
     assert r.info["ray_source"] in (0, 1)
 
 
+def test_tests_only_every_infeas_every_th_evaluation():
+    """The unbounded column is certified at the first test: the first
+    evaluation with infeas_every = 1, the fourth (step 256) by default, the
+    third with infeas_every = 3."""
+    p = lpgen.unbounded_lp(0, 200)
+    for every, k in ((1, 64), (4, 256), (3, 192)):
+        r = oracle.solve(p, eps_rel=1e-8, max_iter=200000, infeas_every=every)
+        assert r.status == "DUAL_INFEASIBLE" and r.info["iterations"] == k, (every, r.info["iterations"])
+
+
 def test_detection_off_runs_to_the_limit():
     p = lpgen.infeasible_lp(0, 200)
     r = oracle.solve(p, eps_rel=1e-8, max_iter=2000, detect_infeas=0)
