@@ -110,9 +110,13 @@ typedef struct {
   int32_t spmv_layout_kt;     /* -2: K' follows spmv_layout (default); -1, 0, 1, 2: as spmv_layout,
                                  for K' alone */
   int32_t batch_handoff;      /* batch handles: an LP that has taken this many accepted steps stops
-                                 in the persistent launch at its next evaluation and is finished by
-                                 the single-LP kernels, several such LPs at once on their own
-                                 streams (same state, same iteration; default 2048, 0 = never) */
+                                 in the persistent launch at its next evaluation (default 2048, 0 =
+                                 never).  If at most 8 x handoff_streams LPs stopped, the
+                                 single-LP kernels finish them, handoff_streams at a time on
+                                 streams of their own (same state, same iteration); otherwise
+                                 they continue in a new persistent launch with the threshold
+                                 doubled (the same arithmetic as if they had not stopped), and so
+                                 on until few enough remain */
   int32_t handoff_streams;    /* batch handles: LPs finished at once after the hand-off, each on a
                                  stream of its own (1..16, default 8), the LPs farthest from the
                                  tolerance first */
@@ -263,11 +267,12 @@ int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pdlp_options*
  * PDLP_ERR_ARG for idx out of range, PDLP_ERR_DATA for non-finite values. */
 int pdlp_set_warm_start_batch(pdlp_handle* h, int32_t idx, const double* x0, const double* y0, double omega0);
 
-/* Solve every LP of the batch from its starting point in one persistent launch;
- * LPs still running after batch_handoff accepted steps are then finished by the
- * single-LP kernels (handoff_streams at a time, each on a library-owned stream, over
- * its own slice of the packed arrays), and the call returns when every LP has
- * ended.  time_limit_s bounds the whole solve (an LP still running then ends
+/* Solve every LP of the batch from its starting point in one persistent launch
+ * (or a few: see batch_handoff); the last LPs still running after
+ * batch_handoff (or a multiple of it) accepted steps are finished by the
+ * single-LP kernels (handoff_streams at a time, each on a library-owned stream,
+ * over its own slice of the packed arrays), and the call returns when every LP
+ * has ended.  time_limit_s bounds the whole solve (an LP still running then ends
  * with PDLP_TIME_LIMIT); an LP whose attempts are rejected 1000 times in a row
  * in the persistent launch, or that accepts no step over 64 polls after the
  * hand-off, ends with PDLP_NUMERICAL_ERROR. */

@@ -148,45 +148,54 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
   }
   const LpMat mk{p.K.rp, lv ? lrk : nullptr, lv ? lbk : bp.bk + k0, k1 - k0, r0, r1};
   const LpMat mt{p.KT.rp, lv ? lrt : nullptr, lv ? lbt : bp.bt + t0, t1 - t0, c0, c1};
-  if (threadIdx.x == 0) {
-    DevState z{};
-    *S = z;
-    const double km = bp.kmax[b];
-    S->eta = S->eta_hat = km > 0.0 ? 1.0 / km : 1.0;
-    const double cn = sqrt(bp.norms[4 * b + 2]), qn = sqrt(bp.norms[4 * b + 3]);
-    const double w0 = (cn > bp.eps_zero && qn > bp.eps_zero) ? cn / qn : 1.0;
-    S->omega = bp.omega_warm[b] > 0.0 ? bp.omega_warm[b] : w0;
-    S->initial = 1;
-    S->need_eval = 1;
-    S->eps_rel = bp.eps_rel;
-    S->max_iter = bp.max_iter;
-  }
-  // starting point (as k_init_x / k_init_y)
-  const bool warm = bp.warm[b] != 0;
-  for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
-    double v = warm ? bp.wx[j] / p.D2[j] : 0.0;
-    if (v < p.l[j]) v = p.l[j];
-    if (v > p.u[j]) v = p.u[j];
-    p.x[0][j] = v;
-    p.x[1][j] = v;
-    p.xsum[j] = 0.0;
-    p.xbar[j] = v;
-    p.x0[j] = v;
-    p.dx[j] = 0.0;
-  }
-  for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
-    double v = 0.0;
-    if (warm) {
-      v = (p.le[i] ? -bp.wy[i] : bp.wy[i]) / p.D1[i];
-      if (p.ineq[i] && v < 0.0) v = 0.0;
+  if (bp.resume) {
+    // a paused LP: its state block and vectors are where the pause left them
+    if (threadIdx.x == 0) {
+      *S = bp.st[b];
+      S->status = 0;
+      S->done = 0;
     }
-    p.y[0][i] = v;
-    p.y[1][i] = v;
-    p.ysum[i] = 0.0;
-    p.ybar[i] = v;
-    p.y0[i] = v;
-    p.kx[0][i] = 0.0;
-    p.kx[1][i] = 0.0;
+  } else {
+    if (threadIdx.x == 0) {
+      DevState z{};
+      *S = z;
+      const double km = bp.kmax[b];
+      S->eta = S->eta_hat = km > 0.0 ? 1.0 / km : 1.0;
+      const double cn = sqrt(bp.norms[4 * b + 2]), qn = sqrt(bp.norms[4 * b + 3]);
+      const double w0 = (cn > bp.eps_zero && qn > bp.eps_zero) ? cn / qn : 1.0;
+      S->omega = bp.omega_warm[b] > 0.0 ? bp.omega_warm[b] : w0;
+      S->initial = 1;
+      S->need_eval = 1;
+      S->eps_rel = bp.eps_rel;
+      S->max_iter = bp.max_iter;
+    }
+    // starting point (as k_init_x / k_init_y)
+    const bool warm = bp.warm[b] != 0;
+    for (int j = c0 + threadIdx.x; j < c1; j += kBB) {
+      double v = warm ? bp.wx[j] / p.D2[j] : 0.0;
+      if (v < p.l[j]) v = p.l[j];
+      if (v > p.u[j]) v = p.u[j];
+      p.x[0][j] = v;
+      p.x[1][j] = v;
+      p.xsum[j] = 0.0;
+      p.xbar[j] = v;
+      p.x0[j] = v;
+      p.dx[j] = 0.0;
+    }
+    for (int i = r0 + threadIdx.x; i < r1; i += kBB) {
+      double v = 0.0;
+      if (warm) {
+        v = (p.le[i] ? -bp.wy[i] : bp.wy[i]) / p.D1[i];
+        if (p.ineq[i] && v < 0.0) v = 0.0;
+      }
+      p.y[0][i] = v;
+      p.y[1][i] = v;
+      p.ysum[i] = 0.0;
+      p.ybar[i] = v;
+      p.y0[i] = v;
+      p.kx[0][i] = 0.0;
+      p.kx[1][i] = 0.0;
+    }
   }
   __syncthreads();
   int64_t k_seen = 0, rejected = 0;  // thread 0: accepted steps at the last attempt, rejections since

@@ -228,6 +228,7 @@ struct pdlp_handle {
   std::vector<DevState> bst_h;
   int32_t grid = 0;
   int32_t *row_off = nullptr, *col_off = nullptr, *order = nullptr;
+  int32_t* order2 = nullptr;   // queue order of a relaunch over paused LPs
   uint8_t* lanes = nullptr;
   RowBlock *bk = nullptr, *bt = nullptr;
   int32_t *bk_off = nullptr, *bt_off = nullptr;
@@ -1206,13 +1207,17 @@ int size_class(int32_t rows) { return rows < 256 ? 0 : (rows < 1024 ? 1 : 2); }
 
 }  // namespace
 
+// One persistent launch over `count` LPs taken in the order of `order` (all
+// LPs by default); resume = 1 continues LPs that an earlier launch paused.
 static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s,
-                               int64_t pause_at = 0) {
+                               int64_t pause_at = 0, const int32_t* order = nullptr, int32_t count = -1,
+                               int32_t resume = 0) {
   hipStream_t s = h->stream;
   BatchParams bp{};
-  bp.count = h->count;
+  bp.count = count >= 0 ? count : h->count;
   bp.trace_lp = h->opt.trace > 0 ? 0 : -1;
-  bp.order = h->order;
+  bp.order = order ? order : h->order;
+  bp.resume = resume;
   bp.row_off = h->row_off;
   bp.col_off = h->col_off;
   bp.lanes = h->lanes;
@@ -1464,6 +1469,7 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     for (int32_t k = 0; k < count; ++k) ord[(size_t)k] = k;
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return nnz_b[(size_t)a] > nnz_b[(size_t)b]; });
     h->order = h->dalloc<int32_t>((size_t)count);
+    h->order2 = h->dalloc<int32_t>((size_t)count);
     check(hipMemcpyAsync(h->order, ord.data(), ord.size() * 4, kind, s), "upload queue order");
     int dev = 0, khz = 0;
     check(hipGetDevice(&dev), "hipGetDevice");
@@ -1746,7 +1752,8 @@ extern "C" int pdlp_solve_batch(pdlp_handle* h) {
     check(hipMemcpyAsync(h->warm, h->warm_h.data(), cnt, hipMemcpyHostToDevice, s), "upload warm flags");
     check(hipMemcpyAsync(h->omega_warm, h->omega_warm_h.data(), cnt * 8, hipMemcpyHostToDevice, s),
           "upload warm omegas");
-    launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, h->opt.time_limit_s, h->opt.batch_handoff);
+    int64_t pause_at = h->opt.batch_handoff;
+    launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, h->opt.time_limit_s, pause_at);
     h->bst_h.resize(cnt);
     check(hipMemcpyAsync(h->bst_h.data(), h->bst, cnt * sizeof(DevState), hipMemcpyDeviceToHost, s), "read states");
     check(hipStreamSynchronize(s), "batch sync");
@@ -1755,6 +1762,28 @@ extern "C" int pdlp_solve_batch(pdlp_handle* h) {
     std::vector<int32_t> paused;
     for (size_t b = 0; b < cnt; ++b)
       if (h->bst_h[b].status == kPaused) paused.push_back((int32_t)b);
+    // Too many long-running LPs for the streams: continue them in the
+    // persistent kernel (the same arithmetic as if they had never paused) with
+    // a doubled threshold, until few enough remain for the hand-off.
+    const size_t few = 8 * (size_t)h->opt.handoff_streams;
+    while (paused.size() > few) {
+      std::stable_sort(paused.begin(), paused.end(), [&](int32_t a, int32_t c) {
+        return h->nnz_h[(size_t)a] > h->nnz_h[(size_t)c];
+      });
+      check(hipMemcpyAsync(h->order2, paused.data(), paused.size() * 4, hipMemcpyHostToDevice, s),
+            "upload queue order");
+      pause_at *= 2;
+      const double left = std::max(1e-6, h->opt.time_limit_s - (now_s() - t0));
+      launch_batch_solve(h, h->opt.eps_rel, h->opt.max_iter, left, pause_at, h->order2, (int32_t)paused.size(), 1);
+      check(hipMemcpyAsync(h->bst_h.data(), h->bst, cnt * sizeof(DevState), hipMemcpyDeviceToHost, s),
+            "read states");
+      check(hipStreamSynchronize(s), "batch sync");
+      check(hipGetLastError(), "batch kernels");
+      std::vector<int32_t> still;
+      for (int32_t b : paused)
+        if (h->bst_h[(size_t)b].status == kPaused) still.push_back(b);
+      paused.swap(still);
+    }
     if (!paused.empty()) {
       // farthest from the tolerance first (likely the longest to finish), so
       // that those do not wait for a free stream

@@ -177,7 +177,9 @@ struct BatchParams {
   uint64_t ticks;           // time limit in wall-clock ticks (0: none)
   int64_t max_reject;       // consecutive rejected attempts that count as a numerical failure
   int64_t pause_at;         // accepted steps after which an LP stops at its next evaluation with
-                            // status kPaused, to be continued by the single-LP kernels (0: never)
+                            // status kPaused (0: never)
+  int32_t resume;           // 1: the queued LPs were paused; continue each from its state in st
+  int32_t pad1;
   int32_t lds_m, lds_n;     // LDS room for an LP's y, dx and row pointers (0, 0: all from global memory)
   int32_t lds_bk, lds_bt;   // LDS room for an LP's block descriptors of K~, K~'
   double eps_rel;

@@ -187,6 +187,40 @@ def test_end_to_end_matches_oracle(P, orc, eps, handoff):
         assert handed > 3
 
 
+def test_relaunch_then_handoff(P, orc):
+    """More paused LPs than 8 x handoff_streams: they continue in new
+    persistent launches with the threshold doubled (64, 128, 256, ...) --
+    the same arithmetic as if they had never stopped -- until at most 8
+    remain, which the single-LP kernels finish.  End-to-end bars as above,
+    bitwise run to run."""
+    probs = _small_batch(24, seed=21)
+    eps = 1e-8
+    opts = dict(eps_rel=eps, max_iter=200000)
+    h = P.pdlp_create_batch(probs, time_limit_s=120.0, batch_handoff=64, handoff_streams=1, **opts)
+    P.pdlp_solve_batch(h)
+    a = P.pdlp_get_solution_batch(h, -1)
+    P.pdlp_solve_batch(h)
+    b = P.pdlp_get_solution_batch(h, -1)
+    for u, v in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(u, v)
+    infos = a[3]
+    ks = [i["handoff_k"] for i in infos if i["handoff_k"]]
+    print("hand-off steps:", sorted(ks), "iterations:", sorted(i["iterations"] for i in infos))
+    assert 0 < len(ks) <= 8
+    # every hand-off happened at the first evaluation at or after a threshold 64 * 2^j > 64
+    assert all(k >= 128 for k in ks)
+    for k, p in enumerate(probs):
+        x, y, rc, I = P.pdlp_get_solution_batch(h, k)
+        r, _, so, _, _ = _oracle_spread(orc, p, opts)
+        assert I["status_name"] == "OPTIMAL" and r.status == "OPTIMAL", (k, I["status_name"])
+        same_path = I["attempts"] == r.info["attempts"] and I["iterations"] == r.info["iterations"]
+        tol = max(1e-6, 10 * so) if same_path else max(1e-6, 10 * so, 2 * eps)
+        assert abs(I["primal_obj"] - r.info["primal_obj"]) <= tol * (1 + abs(r.info["primal_obj"])), k
+        assert orc.evaluate(p, x, y)["rel_kkt"] <= eps * (1 + 1e-6), k
+        ref = p.obj_star()
+        assert abs(I["primal_obj"] - ref) <= 1e-6 * (1 + abs(ref)), k
+
+
 @pytest.mark.parametrize("lanes", [-1, 1, 2, 8, 64])
 def test_any_lanes_per_row(P, orc, lanes):
     """Every sweep of the schedule (LDS-tiled row blocks, or 1..64 lanes per
