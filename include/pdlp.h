@@ -134,6 +134,14 @@ typedef struct {
                                  the sum of the magnitudes of its terms */
   int32_t infeas_every;       /* evaluations per certificate test, >= 1 (default 4: the two extra
                                  products cost ~3 % of the run when done at every evaluation) */
+  int32_t presolve;           /* single-LP handles: 1 = presolve-lite at pdlp_create (fixed and
+                                 empty columns, empty and singleton rows, until none applies) and
+                                 the exact postsolve in pdlp_get_solution; the device solves the
+                                 reduced LP (its relative errors are the reduced LP's; objectives
+                                 are reported for the user's LP).  An LP that presolve finds
+                                 infeasible or reduces to no column is solved as given.
+                                 pdlp_get_iterate and pdlp_get_scaling return
+                                 PDLP_ERR_UNSUPPORTED then.  Default 0; batch handles: 0 only */
 } pdlp_options;
 
 typedef struct {
@@ -159,6 +167,7 @@ typedef struct {
                                  violation of the returned unit primal ray; 0 otherwise */
   int32_t ray_source;         /* the candidate that certified: 0 the last accepted step, 1 the
                                  epoch displacement */
+  int32_t m_solved, n_solved; /* rows and columns of the LP the device solved (after presolve) */
   int32_t reserved;
 } pdlp_info;
 
@@ -199,6 +208,18 @@ int pdlp_solve(pdlp_handle* h);
  * accepted steps, time_limit_s > 0 (same meaning as in pdlp_options).
  * PDLP_ERR_ARG for values out of range; the handle keeps its old values then. */
 int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s);
+
+/* The reductions pdlp_create makes with presolve = 1, computed on the host
+ * (no device needed; for inspection and tests): keep_row[m], keep_col[n] (1
+ * kept, 0 removed); every column's final bounds lo[n], hi[n] and, for a
+ * removed column, its value x_fixed[n]; the right-hand sides b_reduced[m]
+ * after the reductions (meaningful for kept rows); *offset, the objective of
+ * the removed columns.  *status = 0, or PDLP_PRIMAL_INFEASIBLE /
+ * PDLP_DUAL_INFEASIBLE when presolve itself finds the LP so (the outputs then
+ * hold the state at that point).  Any output may be NULL.  Returns PDLP_OK or
+ * the error of pdlp_create's validation. */
+int pdlp_presolve(const pdlp_problem* p, int32_t* status, uint8_t* keep_row, uint8_t* keep_col, double* lo,
+                  double* hi, double* x_fixed, double* b_reduced, double* offset);
 
 /* Copy the solution of the last pdlp_solve to host buffers: x[n], y[m]
  * (user orientation) and reduced_cost[n] (lambda = proj_Lambda(c - A'y)); any

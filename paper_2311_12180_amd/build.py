@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpdlp_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "batch.hip", "setup.hip", "pdlp_api.cpp", "gnn.hip", "gnn_api.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "setup.hip", "pdlp_api.cpp", "presolve.cpp", "gnn.hip", "gnn_api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -257,6 +257,11 @@ struct pdlp_handle {
     hipEvent_t ev[2] = {nullptr, nullptr};
   };
   std::vector<Lane> lanes_ho;
+  // presolve (single-LP handles): the device holds the reduced LP; orig is the
+  // user's LP for the postsolve and the warm-start mapping
+  bool presolved = false;
+  Presolve pre;
+  HostLP orig;
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -332,6 +337,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->detect_infeas = 1;
   o->eps_infeas = 1e-8;
   o->infeas_every = 4;
+  o->presolve = 0;
   return PDLP_OK;
 }
 
@@ -362,6 +368,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.detect_infeas != 0 && o.detect_infeas != 1) return why = "detect_infeas must be 0 or 1", -1;
   if (!(o.eps_infeas > 0.0) || !std::isfinite(o.eps_infeas)) return why = "eps_infeas must be finite and > 0", -1;
   if (o.infeas_every < 1) return why = "infeas_every must be >= 1", -1;
+  if (o.presolve != 0 && o.presolve != 1) return why = "presolve must be 0 or 1", -1;
   return 0;
 }
 
@@ -779,6 +786,20 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   const double t0 = now_s();
   HostLP H;
   if (int rc = load_problem(p, hip_stream, H, why)) return fail(nullptr, rc, why);
+  Presolve pre;
+  HostLP orig;
+  bool presolved = false;
+  if (opt.presolve) {
+    // the reduced LP replaces the user's; an LP that presolve finds infeasible,
+    // or reduces to no column, is solved as given (the method then returns
+    // its certificate, or the postsolve would have nothing to run)
+    HostLP R;
+    if (presolve_lp(H, R, pre) == 0 && R.n >= 1) {
+      orig = std::move(H);
+      H = std::move(R);
+      presolved = true;
+    }
+  }
   const int32_t m = H.m, n = H.n;
   const int64_t nnz = H.nnz;
 
@@ -791,6 +812,11 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   h->nnz = nnz;
   h->opt = opt;
   h->stream = (hipStream_t)hip_stream;
+  h->presolved = presolved;
+  if (presolved) {
+    h->pre = std::move(pre);
+    h->orig = std::move(orig);
+  }
   try {
     check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hipStream_t s = h->stream;
@@ -886,15 +912,50 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   return PDLP_OK;
 }
 
+extern "C" int pdlp_presolve(const pdlp_problem* p, int32_t* status, uint8_t* keep_row, uint8_t* keep_col,
+                             double* lo, double* hi, double* x_fixed, double* b_reduced, double* offset) {
+  if (!p) return fail(nullptr, PDLP_ERR_ARG, "NULL problem");
+  std::string why;
+  HostLP H;
+  if (int rc = load_problem(p, nullptr, H, why)) return fail(nullptr, rc, why);
+  Presolve P;
+  HostLP R;
+  const int st = presolve_lp(H, R, P);
+  if (status) *status = st;
+  const size_t m = (size_t)H.m, n = (size_t)H.n;
+  if (keep_row) for (size_t i = 0; i < m && i < P.row_on.size(); ++i) keep_row[i] = P.row_on[i];
+  if (keep_col) for (size_t j = 0; j < n && j < P.col_on.size(); ++j) keep_col[j] = P.col_on[j];
+  if (lo) std::memcpy(lo, P.lo.data(), n * 8);
+  if (hi) std::memcpy(hi, P.hi.data(), n * 8);
+  if (x_fixed) std::memcpy(x_fixed, P.xfix.data(), n * 8);
+  if (b_reduced && !P.b.empty()) std::memcpy(b_reduced, P.b.data(), m * 8);
+  if (offset) *offset = P.offset;
+  return PDLP_OK;
+}
+
 extern "C" int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const double* y0, double omega0) {
   if (!h) return PDLP_ERR_ARG;
   if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_set_warm_start on a batch handle (use the _batch entry points)");
+  const int32_t un = h->presolved ? h->orig.n : h->n, um = h->presolved ? h->orig.m : h->m;
   if (x0)
-    for (int32_t j = 0; j < h->n; ++j)
+    for (int32_t j = 0; j < un; ++j)
       if (!std::isfinite(x0[j])) return fail(h, PDLP_ERR_DATA, "warm-start x0 is not finite");
   if (y0)
-    for (int32_t i = 0; i < h->m; ++i)
+    for (int32_t i = 0; i < um; ++i)
       if (!std::isfinite(y0[i])) return fail(h, PDLP_ERR_DATA, "warm-start y0 is not finite");
+  // with presolve, the kept columns' and rows' entries start the reduced LP
+  std::vector<double> rx, ry;
+  if (h->presolved) {
+    if (x0) {
+      for (int32_t j : h->pre.cols) rx.push_back(x0[j]);
+      x0 = rx.data();
+    }
+    if (y0) {
+      for (int32_t i : h->pre.rows) ry.push_back(y0[i]);
+      ry.push_back(0.0);
+      y0 = ry.data();
+    }
+  }
   if (std::isnan(omega0) || std::isinf(omega0)) return fail(h, PDLP_ERR_DATA, "warm-start omega0 is not finite");
   try {
     // x0 == NULL: zero start for x; y0 == NULL: zero start for y
@@ -957,6 +1018,8 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.ray_source = f->ray_src;
   I.ray_obj = f->ray_obj;
   I.ray_res = f->ray_res;
+  I.m_solved = h->m;
+  I.n_solved = h->n;
 }
 
 extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_iter, double time_limit_s) {
@@ -1045,6 +1108,50 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
   if (!h) return PDLP_ERR_ARG;
   if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution on a batch handle (use the _batch entry points)");
   if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution before pdlp_solve");
+  if (h->presolved) {
+    // the reduced LP's solution, postsolved to the user's LP
+    const HostLP& O = h->orig;
+    std::vector<double> xr((size_t)h->n), yr((size_t)std::max(h->m, 1)), lr((size_t)h->n);
+    std::vector<double> xo((size_t)O.n), yo((size_t)std::max(O.m, 1)), lo((size_t)O.n);
+    try {
+      check(hipMemcpy(xr.data(), h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
+      if (h->m) check(hipMemcpy(yr.data(), h->yo, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y");
+      check(hipMemcpy(lr.data(), h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
+    } catch (const HipFail& f) {
+      return fail(h, PDLP_ERR_HIP, hip_msg(f));
+    }
+    const int st = h->info.status;
+    pdlp_info I = h->info;
+    if (st == PDLP_PRIMAL_INFEASIBLE) {
+      // y, lambda: the dual ray extended to the user's LP (unit 2-norm again);
+      // x: the current point
+      std::vector<double> sx((size_t)O.n), sy((size_t)std::max(O.m, 1)), sl((size_t)O.n);
+      postsolve_lp(O, h->pre, xr.data(), yr.data(), lr.data(), sx.data(), yo.data(), lo.data(), true);
+      postsolve_lp(O, h->pre, xr.data(), yr.data(), lr.data(), xo.data(), sy.data(), sl.data(), false);
+      double nr = 0.0;
+      for (int32_t i = 0; i < O.m; ++i) nr += yo[(size_t)i] * yo[(size_t)i];
+      nr = std::sqrt(nr);
+      const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
+      for (int32_t i = 0; i < O.m; ++i) yo[(size_t)i] *= sc;
+      for (int32_t j = 0; j < O.n; ++j) lo[(size_t)j] *= sc;
+      I.ray_obj *= sc;
+      I.ray_res *= sc;
+    } else if (st == PDLP_DUAL_INFEASIBLE) {
+      // x: the primal ray (removed columns cannot move); y, lambda: as solved
+      std::vector<double> sx((size_t)O.n), sy((size_t)std::max(O.m, 1)), sl((size_t)O.n);
+      postsolve_lp(O, h->pre, xr.data(), yr.data(), lr.data(), xo.data(), sy.data(), sl.data(), true);
+      postsolve_lp(O, h->pre, xr.data(), yr.data(), lr.data(), sx.data(), yo.data(), lo.data(), false);
+    } else {
+      postsolve_lp(O, h->pre, xr.data(), yr.data(), lr.data(), xo.data(), yo.data(), lo.data(), false);
+      I.primal_obj += h->pre.offset;
+      I.dual_obj += h->pre.offset;
+    }
+    if (x) std::memcpy(x, xo.data(), (size_t)O.n * 8);
+    if (y && O.m) std::memcpy(y, yo.data(), (size_t)O.m * 8);
+    if (rc) std::memcpy(rc, lo.data(), (size_t)O.n * 8);
+    if (info) *info = I;
+    return PDLP_OK;
+  }
   try {
     if (x) check(hipMemcpy(x, h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
     if (y && h->m) check(hipMemcpy(y, h->yo, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y");
@@ -1060,6 +1167,7 @@ extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pd
   if (!h) return PDLP_ERR_ARG;
   if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_iterate on a batch handle (use the _batch entry points)");
   if (!h->solved) return fail(h, PDLP_ERR_STATE, "pdlp_get_iterate before pdlp_solve");
+  if (h->presolved) return fail(h, PDLP_ERR_UNSUPPORTED, "pdlp_get_iterate on a presolved handle (the iterate is the reduced LP's)");
   try {
     DevState f;
     check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
@@ -1083,6 +1191,7 @@ extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pd
 
 extern "C" int pdlp_get_scaling(pdlp_handle* h, double* D1, double* D2, double* val_scaled) {
   if (!h) return PDLP_ERR_ARG;
+  if (h->presolved) return fail(h, PDLP_ERR_UNSUPPORTED, "pdlp_get_scaling on a presolved handle (the scaling is the reduced LP's)");
   try {
     if (D1 && h->m) check(hipMemcpy(D1, h->D1, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download D1");
     if (D2) check(hipMemcpy(D2, h->D2, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download D2");
@@ -1363,6 +1472,7 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
   else pdlp_default_options(&opt);
   std::string why;
   if (check_options(opt, why)) return fail(nullptr, PDLP_ERR_ARG, why);
+  if (opt.presolve) return fail(nullptr, PDLP_ERR_UNSUPPORTED, "presolve is not available for batch handles");
   const double t0 = now_s();
   HostLP H;
   std::vector<int32_t> row_off, col_off;

@@ -201,6 +201,25 @@ struct HostLP {
 int pack_problems(const pdlp_problem* ps, int32_t count, void* hip_stream, HostLP& H, std::vector<int32_t>& row_off,
                   std::vector<int32_t>& col_off, std::vector<int64_t>& nnz_b, std::string& why);
 
+// Presolve-lite record (presolve.cpp): what was removed and how to undo it.
+struct Presolve {
+  int status = 0;                      // 0, or PDLP_PRIMAL_INFEASIBLE / PDLP_DUAL_INFEASIBLE found by presolve
+  std::vector<uint8_t> row_on, col_on; // kept rows / columns
+  std::vector<int32_t> rows, cols;     // their indices, ascending
+  std::vector<double> xfix;            // values of the removed columns
+  std::vector<double> lo, hi;          // final bounds
+  std::vector<int32_t> lo_row, hi_row; // singleton row that set each bound (-1: the column's own)
+  std::vector<int32_t> order;          // removed columns in removal order
+  double offset = 0.0;                 // objective of the removed columns
+  std::vector<double> b;               // right-hand sides after the reductions (kept rows)
+  std::vector<int32_t> cp, cr;         // the original matrix by columns
+  std::vector<double> cv;
+};
+
+int presolve_lp(const HostLP& H, HostLP& R, Presolve& P);
+void postsolve_lp(const HostLP& H, const Presolve& P, const double* xr, const double* yr, const double* lamr,
+                  double* x, double* y, double* lam, bool ray);
+
 hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
                            int32_t* rpT, int32_t* ciT, double* vT, int32_t* rowidT, int32_t* perm_out,
                            hipStream_t s);

@@ -32,8 +32,8 @@ ERRORS = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_DATA", -3: "PDLP_ERR_HIP", -4: "PDLP
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_set_warm_start", "pdlp_set_termination", "pdlp_solve",
             "pdlp_get_solution", "pdlp_get_iterate", "pdlp_get_scaling", "pdlp_get_trace",
             "pdlp_profile_attempts", "pdlp_step_bytes", "pdlp_create_batch", "pdlp_set_warm_start_batch",
-            "pdlp_solve_batch", "pdlp_get_solution_batch", "pdlp_batch_schedule", "pdlp_last_error",
-            "pdlp_destroy"]
+            "pdlp_solve_batch", "pdlp_get_solution_batch", "pdlp_batch_schedule", "pdlp_presolve",
+            "pdlp_last_error", "pdlp_destroy"]
 
 
 class PdlpError(RuntimeError):
@@ -58,7 +58,8 @@ class pdlp_options(C.Structure):
                 ("graph", C.c_int32), ("spmv_layout", C.c_int32), ("batch_lanes", C.c_int32),
                 ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32),
                 ("batch_handoff", C.c_int32), ("handoff_streams", C.c_int32),
-                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double), ("infeas_every", C.c_int32)]
+                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double), ("infeas_every", C.c_int32),
+                ("presolve", C.c_int32)]
 
 
 class pdlp_info(C.Structure):
@@ -69,7 +70,8 @@ class pdlp_info(C.Structure):
                 ("omega", C.c_double), ("eta_hat", C.c_double), ("setup_s", C.c_double),
                 ("solve_s", C.c_double), ("layout_k", C.c_int32), ("layout_kt", C.c_int32),
                 ("handoff_k", C.c_int64), ("ray_obj", C.c_double), ("ray_res", C.c_double),
-                ("ray_source", C.c_int32), ("reserved", C.c_int32)]
+                ("ray_source", C.c_int32), ("m_solved", C.c_int32), ("n_solved", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class pdlp_iter_state(C.Structure):
@@ -102,6 +104,8 @@ def lib() -> C.CDLL:
         L.pdlp_profile_attempts.argtypes = [vp, i32, C.POINTER(dbl), C.POINTER(dbl)]
         L.pdlp_step_bytes.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl)]
         L.pdlp_create_batch.argtypes = [C.POINTER(pdlp_problem), i32, C.POINTER(pdlp_options), vp, C.POINTER(vp)]
+        L.pdlp_presolve.argtypes = [C.POINTER(pdlp_problem), C.POINTER(i32), vp, vp, vp, vp, vp, vp,
+                                    C.POINTER(dbl)]
         L.pdlp_set_warm_start_batch.argtypes = [vp, i32, vp, vp, dbl]
         L.pdlp_solve_batch.argtypes = [vp]
         L.pdlp_get_solution_batch.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -283,6 +287,24 @@ def pdlp_batch_schedule(h: BatchHandle):
     g = C.c_int32()
     _check(lib().pdlp_batch_schedule(h.ptr, _ptr(lanes), C.byref(g)), h)
     return lanes.reshape(h.count, 2), g.value
+
+
+def pdlp_presolve(problem) -> dict:
+    """The reductions of presolve = 1 on the host (no device needed): status
+    name, keep_row[m], keep_col[n] (bool), lo[n], hi[n], x_fixed[n],
+    b_reduced[m], offset."""
+    a = _host_arrays(problem)
+    m, n = int(problem.m), int(problem.n)
+    nnz = int(a["row_ptr"][-1]) if len(a["row_ptr"]) else 0
+    ps = pdlp_problem(m, n, nnz, PDLP_MEM_HOST, *[_ptr(a[k]) for k in
+                                                  ("row_ptr", "col_idx", "val", "c", "b", "l", "u", "row_type")])
+    st = C.c_int32()
+    kr = np.zeros(max(m, 1), np.uint8); kc = np.zeros(n, np.uint8)
+    lo = np.zeros(n); hi = np.zeros(n); xf = np.zeros(n); br = np.zeros(max(m, 1)); off = C.c_double()
+    _check(lib().pdlp_presolve(C.byref(ps), C.byref(st), _ptr(kr), _ptr(kc), _ptr(lo), _ptr(hi), _ptr(xf),
+                               _ptr(br), C.byref(off)))
+    return dict(status=STATUS.get(st.value, "OK") if st.value else "OK", keep_row=kr[:m].astype(bool),
+                keep_col=kc.astype(bool), lo=lo, hi=hi, x_fixed=xf, b_reduced=br[:m], offset=off.value)
 
 
 def pdlp_set_warm_start(h: Handle, x0=None, y0=None, omega0: float = 0.0):
