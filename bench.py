@@ -351,9 +351,11 @@ def main():
         ttt = {}
         import oracle
         oracle.build()
-        runs = [("fp64_1e-4", 0, 1e-4), ("fp32_matrix_1e-4", 1, 1e-4), ("fp64_1e-8", 0, 1e-8)]
-        for name, prec, eps in runs:
-            h = P.pdlp_create(prob, stream=stream, eps_rel=eps, a_precision=prec, time_limit_s=args.ttt_limit)
+        runs = [("fp64_1e-4", 0, 1e-4, 0), ("fp32_matrix_1e-4", 1, 1e-4, 0), ("fp64_1e-8", 0, 1e-8, 0),
+                ("fp64_presolve_1e-4", 0, 1e-4, 1), ("fp64_presolve_1e-8", 0, 1e-8, 1)]
+        for name, prec, eps, pre in runs:
+            h = P.pdlp_create(prob, stream=stream, eps_rel=eps, a_precision=prec, time_limit_s=args.ttt_limit,
+                              presolve=pre)
             P.pdlp_solve(h)
             x, y, rc, inf = P.pdlp_get_solution(h)
             ev = oracle.evaluate(prob, x, y)
@@ -363,6 +365,8 @@ def main():
                          "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
                          "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
                          "obj_rel_err_vs_known_optimum": abs(inf["primal_obj"] - obj_star) / (1 + abs(obj_star))}
+            if pre:
+                ttt[name]["solved_m_n"] = [inf["m_solved"], inf["n_solved"]]
             log(f"time to {eps:g} ({name}): {ttt[name]}")
             P.pdlp_destroy(h)
         # the 2000 x 2000 transportation LP (n = 4e6, m = 4000, nnz = 8e6) to 1e-6
