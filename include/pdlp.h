@@ -142,6 +142,15 @@ typedef struct {
                                  infeasible or reduces to no column is solved as given.
                                  pdlp_get_iterate and pdlp_get_scaling return
                                  PDLP_ERR_UNSUPPORTED then.  Default 0; batch handles: 0 only */
+  int32_t restart_metric;     /* 0 (default): KKT_omega restarts (Section 3.4, the paper's);
+                                 1: PDLP's normalized duality gap rho_r(z) = max {L(x, yh) -
+                                 L(xh, y) : zh in Z, ||zh - z||_omega <= r} / r, the metric the
+                                 paper's KKT restarts replace; its trust-region problem is solved
+                                 at each evaluation by 24 passes over the vectors (a multiplier
+                                 search), for both candidates at once.  The candidates, criteria,
+                                 betas and primal weight update are those of the KKT scheme, the
+                                 reference value being the restart point's rho (+inf before the
+                                 first restart).  Termination is unchanged (Section 4.1) */
 } pdlp_options;
 
 typedef struct {

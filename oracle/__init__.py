@@ -52,7 +52,7 @@ class _Options(C.Structure):
                 ("pw_theta", C.c_double), ("eps_zero", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("a_precision", C.c_int32),
                 ("kkt_omega_power", C.c_int32), ("threads", C.c_int32), ("detect_infeas", C.c_int32),
-                ("eps_infeas", C.c_double), ("infeas_every", C.c_int32)]
+                ("eps_infeas", C.c_double), ("infeas_every", C.c_int32), ("restart_metric", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -94,6 +94,9 @@ def lib():
         L.orc_ray_test.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_ray_test.restype = C.c_int
+        L.orc_normalized_gap.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
+                                         C.c_double, C.c_double]
+        L.orc_normalized_gap.restype = C.c_double
         L.orc_restart_reason.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int64,
                                          C.c_double, C.c_double, C.c_double]
         L.orc_restart_reason.restype = C.c_int
@@ -151,7 +154,7 @@ def solve(prob, trace_cap: int = 0, **opts) -> Result:
     """Solve with the oracle.  Options: eps_rel, max_iter, time_limit_s,
     eval_period, ruiz_iters, pc_alpha, pw_theta, eps_zero, beta_suff, beta_nec,
     beta_art, a_precision, kkt_omega_power, threads, detect_infeas, eps_infeas,
-    infeas_every.
+    infeas_every, restart_metric.
     Status PRIMAL_INFEASIBLE returns a unit dual ray in y (and its multipliers
     in rc), DUAL_INFEASIBLE a unit primal ray in x."""
     h = _Held(prob)
@@ -236,6 +239,18 @@ def ray_test(prob, x_dir, y_dir, eps: float = 1e-8) -> dict:
     d = dict(zip(keys, out.tolist()))
     d.update(verdict=int(v), ray_x=rx, ray_y=ry, lam=lam)
     return d
+
+
+def normalized_gap(prob, x_scaled, y_scaled, omega: float, r: float, ruiz_iters: int = 10,
+                   pc_alpha: float = 1.0) -> float:
+    """rho_r of the scaled LP at a scaled point (x~, y~ in the >=-form space)."""
+    h = _Held(prob)
+    xs = np.ascontiguousarray(x_scaled, dtype=np.float64)
+    ys = np.ascontiguousarray(y_scaled, dtype=np.float64)
+    v = lib().orc_normalized_gap(C.byref(h.s), ruiz_iters, pc_alpha, _p(xs), _p(ys), float(omega), float(r))
+    if v < 0:
+        raise ValueError("bad problem")
+    return v
 
 
 def reduced_costs(prob, y) -> np.ndarray:

@@ -50,7 +50,22 @@
  *     times the sum of the magnitudes of its terms (a sign that cancellation
  *     cannot produce: with every variable boxed, lam absorbs all of K'y and
  *     the objective's sign is the whole test).  Primal infeasibility is tested
- *     first, the step before the displacement; the unit-norm ray is returned.
+ *     first, the step before the displacement; the unit-norm ray is returned;
+ *   - restart_metric = 1 replaces KKT_omega in the restart scheme by the
+ *     normalized duality gap of PDLP, which Section 3.4 says the KKT error
+ *     replaces: rho_r(z) = max { L(x, yh) - L(xh, y) : zh in Z,
+ *     ||zh - z||_omega <= r } / r on the scaled LP, with
+ *     ||d||_omega^2 = omega ||dx||^2 + ||dy||^2 / omega.  The objective is
+ *     linear in d = zh - z with gradient g = (K'y - c, q - Kx); its maximiser
+ *     is d(lam) = proj_{Z - z}(W^-1 g / lam), W = diag(omega, 1/omega), for the
+ *     lam at which ||d(lam)||_omega = r (or the box corner when the ball does
+ *     not bind).  lam is found in log space between hi = ||W^-1 g||_omega / r
+ *     (where ||d|| <= r) and lo = 1e-12 hi by 22 passes of 4-point
+ *     multisection.  The candidate is the iterate with the smaller
+ *     rho_{||z - z^{n,0}||}(z) (ties to the average); criteria (i)-(iii) as for
+ *     KKT with rho in place of KKT, the reference value being the restart
+ *     point's rho (the candidate's at the restart, with the radius to the
+ *     previous restart point), +inf before the first restart.
  * Sums are taken in a fixed blocked order (blocks of 4096, serial within and
  * across blocks) so that results do not depend on the thread count.  Built
  * with -ffp-contract=off: every product and sum is rounded on its own.
@@ -523,6 +538,110 @@ int orc_ray_test(const orc_problem* p, const double* x_dir, const double* y_dir,
   return v;
 }
 
+/* ---------------------------------------------------------------- normalized duality gap */
+
+#define GAP_POINTS 4    /* lambda values per multisection pass */
+#define GAP_PASSES 22
+
+/* omega ||dx||^2 + ||dy||^2 / omega and g'd at d(lam) (see the description above) */
+static void gap_sums(const lp_t* P, const double* x, const double* y, const double* gx, const double* gy,
+                     double omega, double lam, double* N, double* G) {
+  int32_t m = P->m, n = P->n;
+  double* tn = (double*)xalloc((size_t)n, sizeof(double));
+  double* tg = (double*)xalloc((size_t)n, sizeof(double));
+  double* tm = (double*)xalloc((size_t)m, sizeof(double));
+  double* tq = (double*)xalloc((size_t)m, sizeof(double));
+  /* d = W^-1 g / lam: x-part g_x / (omega lam), y-part g_y omega / lam */
+  double sx = 1.0 / (omega * lam), sy = omega / lam, iom = 1.0 / omega;
+  for (int32_t j = 0; j < n; ++j) {
+    double d = gx[j] * sx;
+    double lo = P->l[j] - x[j], hi = P->u[j] - x[j];
+    if (d < lo) d = lo;
+    if (d > hi) d = hi;
+    tn[j] = omega * (d * d);
+    tg[j] = gx[j] * d;
+  }
+  for (int32_t i = 0; i < m; ++i) {
+    double d = gy[i] * sy;
+    if (P->ineq[i] && d < -y[i]) d = -y[i];
+    tm[i] = (d * d) * iom;
+    tq[i] = gy[i] * d;
+  }
+  *N = blocked_sum(n, tn) + blocked_sum(m, tm);
+  *G = blocked_sum(n, tg) + blocked_sum(m, tq);
+  free(tn); free(tg); free(tm); free(tq);
+}
+
+/* rho_r at the scaled point (x, y) with K~x = kx, K~'y = kty */
+static double normalized_gap(const lp_t* P, const double* x, const double* y, const double* kx,
+                             const double* kty, double omega, double r) {
+  if (!(r > 0.0)) return 0.0;
+  int32_t m = P->m, n = P->n;
+  double* gx = (double*)xalloc((size_t)n, sizeof(double));
+  double* gy = (double*)xalloc((size_t)m, sizeof(double));
+  double* t1 = (double*)xalloc((size_t)n, sizeof(double));
+  double* t2 = (double*)xalloc((size_t)m, sizeof(double));
+  for (int32_t j = 0; j < n; ++j) {
+    gx[j] = kty[j] - P->c[j];
+    t1[j] = (gx[j] * gx[j]) / omega;
+  }
+  for (int32_t i = 0; i < m; ++i) {
+    gy[i] = P->q[i] - kx[i];
+    t2[i] = omega * (gy[i] * gy[i]);
+  }
+  double gn2 = blocked_sum(n, t1) + blocked_sum(m, t2);
+  double rho = 0.0;
+  if (gn2 > 0.0) {
+    double r2 = r * r, N, G;
+    double hi = sqrt(gn2) / r, lo = hi * 1e-12;
+    gap_sums(P, x, y, gx, gy, omega, lo, &N, &G);
+    if (N > r2) {
+      for (int it = 0; it < GAP_PASSES; ++it) {
+        double q = exp(log(hi / lo) / (GAP_POINTS + 1));
+        double lam[GAP_POINTS], Nk[GAP_POINTS];
+        double v = lo;
+        for (int k = 0; k < GAP_POINTS; ++k) {
+          v = v * q;
+          lam[k] = v;
+          gap_sums(P, x, y, gx, gy, omega, v, &Nk[k], &G);
+        }
+        /* N is nonincreasing in lam: keep N(lo) > r2 >= N(hi) */
+        int k = 0;
+        while (k < GAP_POINTS && Nk[k] > r2) ++k;
+        double nlo = k > 0 ? lam[k - 1] : lo;
+        double nhi = k < GAP_POINTS ? lam[k] : hi;
+        lo = nlo;
+        hi = nhi;
+      }
+      gap_sums(P, x, y, gx, gy, omega, hi, &N, &G);
+    }
+    rho = G / r;
+  }
+  free(gx); free(gy); free(t1); free(t2);
+  return rho;
+}
+
+static double weighted_dist(int32_t n, int32_t m, const double* x, const double* x0, const double* y,
+                            const double* y0, double omega) {
+  return sqrt(omega * dist2(n, x, x0) + dist2(m, y, y0) / omega);
+}
+
+double orc_normalized_gap(const orc_problem* p, int32_t ruiz_iters, double pc_alpha, const double* x,
+                          const double* y, double omega, double r) {
+  if (check_problem(p)) return -1.0;
+  lp_t P;
+  if (lp_normalize(p, &P)) return -1.0;
+  lp_scale(&P, ruiz_iters, pc_alpha);
+  double* kx = (double*)xalloc((size_t)P.m, sizeof(double));
+  double* kty = (double*)xalloc((size_t)P.n, sizeof(double));
+  spmv(&P.K, x, kx);
+  spmv(&P.Kt, y, kty);
+  double rho = normalized_gap(&P, x, y, kx, kty, omega, r);
+  free(kx); free(kty);
+  lp_free(&P);
+  return rho;
+}
+
 int orc_restart_reason(double kc, double kkt0, double kprev, int64_t t, int64_t k,
                        double beta_suff, double beta_nec, double beta_art) {
   /* Section 3.4, restart criteria */
@@ -556,6 +675,7 @@ void orc_default_options(orc_options* o) {
   o->detect_infeas = 1;
   o->eps_infeas = 1e-8;
   o->infeas_every = 4;
+  o->restart_metric = 0;
 }
 
 static int check_problem(const orc_problem* p) {
@@ -646,7 +766,8 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
               double* rc, orc_info* info, orc_trace* tr, double* x_hat, double* y_hat) {
   orc_options o;
   if (opt) o = *opt; else orc_default_options(&o);
-  if (check_problem(p) || o.eval_period < 1 || o.max_iter < 0 || o.infeas_every < 1) return -1;
+  if (check_problem(p) || o.eval_period < 1 || o.max_iter < 0 || o.infeas_every < 1 ||
+      (o.restart_metric != 0 && o.restart_metric != 1)) return -1;
 #ifdef _OPENMP
   if (o.threads > 0) omp_set_num_threads(o.threads);
 #endif
@@ -708,7 +829,8 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
 
   eval_t e0 = evaluate_point(&P, x, y, wm, wn, wm2, wn2);
   ret_rel = e0.rel;
-  double kkt0 = kkt_omega(e0.scaled, omega, o.kkt_omega_power), kkt_prev = kkt0;
+  /* the restart metric's reference value (rho: +inf before the first restart) */
+  double kkt0 = o.restart_metric == 1 ? INFINITY : kkt_omega(e0.scaled, omega, o.kkt_omega_power), kkt_prev = kkt0;
   if (!isfinite(e0.rel.rel_kkt)) status = 4;
   else if (e0.rel.rel_kkt <= o.eps_rel) status = 1;
   else if (o.max_iter == 0) status = 2;
@@ -797,8 +919,19 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
     }
     if (k >= o.max_iter) { status = 2; ret_avg = avg_better; ret_rel = avg_better ? ea.rel : ec.rel; break; }
     /* restart candidate and restart criteria */
-    double kc_cur = kkt_omega(ec.scaled, omega, o.kkt_omega_power);
-    double kc_avg = kkt_omega(ea.scaled, omega, o.kkt_omega_power);
+    double kc_cur, kc_avg;
+    if (o.restart_metric == 1) {
+      /* normalized duality gap of each iterate, radius = its distance to z^{n,0} */
+      spmv(Ks, x, wm);
+      spmv(Kts, y, wn);
+      kc_cur = normalized_gap(&P, x, y, wm, wn, omega, weighted_dist(n, m, x, x0, y, y0, omega));
+      spmv(Ks, xa, wm);
+      spmv(Kts, ya, wn);
+      kc_avg = normalized_gap(&P, xa, ya, wm, wn, omega, weighted_dist(n, m, xa, x0, ya, y0, omega));
+    } else {
+      kc_cur = kkt_omega(ec.scaled, omega, o.kkt_omega_power);
+      kc_avg = kkt_omega(ea.scaled, omega, o.kkt_omega_power);
+    }
     /* the current iterate only when clearly better; a relative difference below
      * 1e-12 is a rounding-level tie (one step into an epoch the average equals
      * the iterate) and goes to the average, the "otherwise" branch */
@@ -821,7 +954,7 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
       sum_eta = 0.0;
       t = 0;
       restarts++;
-      kkt0 = kkt_omega(cand_avg ? ea.scaled : ec.scaled, omega, o.kkt_omega_power);
+      kkt0 = o.restart_metric == 1 ? kc : kkt_omega(cand_avg ? ea.scaled : ec.scaled, omega, o.kkt_omega_power);
       kkt_prev = kkt0;
     } else {
       kkt_prev = kc;

@@ -47,6 +47,7 @@ typedef struct {
   int32_t detect_infeas;  /* 1: test the infeasibility certificates */
   double eps_infeas;      /* tolerance of the certificate tests */
   int32_t infeas_every;   /* test at every infeas_every-th evaluation (after the first step) */
+  int32_t restart_metric; /* 0: KKT error (the paper's), 1: normalized duality gap (PDLP's) */
 } orc_options;
 
 typedef struct {
@@ -107,6 +108,13 @@ int orc_evaluate(const orc_problem* p, const double* x, const double* y, double 
  * else 0; -1 for a bad problem. */
 int orc_ray_test(const orc_problem* p, const double* x_dir, const double* y_dir, double eps, double* out,
                  double* ray_x, double* ray_y, double* lam);
+
+/* Normalized duality gap rho_r(z) of the scaled LP at the scaled point
+ * (x[n], y[m]) with K~x, K~'y given (kx[m], kty[n]), primal weight omega and
+ * radius r (the restart metric of restart_metric = 1; see the solver's
+ * description of it).  Returns -1 on a bad problem. */
+double orc_normalized_gap(const orc_problem* p, int32_t ruiz_iters, double pc_alpha, const double* x,
+                          const double* y, double omega, double r);
 
 /* Reduced costs lambda = proj_Lambda(c - A'y) at (user-orientation) y. */
 int orc_reduced_costs(const orc_problem* p, const double* y, double* lam);

@@ -125,6 +125,27 @@ __device__ __forceinline__ void plain_sweep(const LpMat& M, const DevCsr& D, int
                         lds, red);
 }
 
+// One candidate's sums of a normalized-duality-gap pass over an LP's columns
+// and rows, reduced into out[0 .. 2 kGapPoints).
+template <int C>
+__device__ __forceinline__ void gap_sweep(const Params& p, const DevState* S, int c0, int c1, int r0, int r1,
+                                       double* red, double* out) {
+  const GapScale g(S->gap_lam[C], S->omega);
+  double acc[2 * kGapPoints];
+#pragma unroll
+  for (int k = 0; k < 2 * kGapPoints; ++k) acc[k] = 0.0;
+  const int cur = S->cur;
+  const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+  const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
+  for (int j = c0 + threadIdx.x; j < c1; j += kBB) gap_col<C>(p, x, g, j, acc);
+  for (int i = r0 + threadIdx.x; i < r1; i += kBB) gap_row<C>(p, y, g, i, acc);
+  block_sum<2 * kGapPoints, kBW>(acc, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 2 * kGapPoints; ++k) out[k] = acc[k];
+  __syncthreads();
+}
+
 template <bool LV>
 __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, DevState* S, double* red,
                                 double* E, double* lds, double* ly, double* ldx, int* lrk, int* lrt, RowBlock* lbk,
@@ -241,24 +262,30 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
           for (int k = 0; k < 4; ++k) E[k] = acc[k];
       }
       {
+        double acc[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+        const EvalRowsOp op(p, S);
+        plain_sweep<LV, 2>(mk, p.K, LK, op, acc, lds, red);
+        block_sum<10, kBW>(acc, red);
+        if (threadIdx.x == 0) {
+          for (int k = 0; k < 8; ++k) E[4 + k] = acc[k];
+          E[38] = acc[8];
+          E[39] = acc[9];
+        }
+      }
+      {
         double acc[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-        const EvalRowsOp op(p, S);
-        plain_sweep<LV, 2>(mk, p.K, LK, op, acc, lds, red);
-        block_sum<8, kBW>(acc, red);
-        if (threadIdx.x == 0)
-          for (int k = 0; k < 8; ++k) E[4 + k] = acc[k];
-      }
-      {
-        double acc[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) acc[k] = 0.0;
         const EvalColsOp op(p, S);
         plain_sweep<LV, 2>(mt, p.KT, LT, op, acc, lds, red);
-        block_sum<6, kBW>(acc, red);
-        if (threadIdx.x == 0)
+        block_sum<8, kBW>(acc, red);
+        if (threadIdx.x == 0) {
           for (int k = 0; k < 6; ++k) E[12 + k] = acc[k];
+          E[40] = acc[6];
+          E[41] = acc[7];
+        }
       }
       if (infeas_due(p, S)) {
         // Section 2.2 infeasibility certificates (the x-space rays were
@@ -288,6 +315,19 @@ __device__ void batch_solve_one(const Params& p, const BatchParams& bp, int b, D
       }
       if (threadIdx.x == 0) eval_decision(S, p, tr, E, qn0, cn0);
       __syncthreads();
+      if (S->gap_active) {
+        // normalized duality gap: the multiplier search's passes over this LP,
+        // then the restart decision (in gap_step after the last pass)
+        __syncthreads();   // (the K~x / K~'y products of the evaluation are in global memory)
+        // (one candidate at a time, to keep the registers of this loop few;
+        // E, no longer needed, collects the pass's sums)
+        while (S->gap_active) {
+          gap_sweep<0>(p, S, c0, c1, r0, r1, red, E);
+          gap_sweep<1>(p, S, c0, c1, r0, r1, red, E + 2 * kGapPoints);
+          if (threadIdx.x == 0) gap_step(S, p, tr, E);
+          __syncthreads();
+        }
+      }
       if (S->restart_flag) {
         const int cur = S->cur, cand = S->cand_avg;
         double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
@@ -385,7 +425,7 @@ __global__ __launch_bounds__(kBB) void k_batch(Params p, BatchParams bp) {
   extern __shared__ double dyn[];
   __shared__ DevState S;
   __shared__ double red[12 * kBW];
-  __shared__ double E[38];
+  __shared__ double E[42];
   __shared__ int slot;
   double* lds = dyn;
   double* ly = bp.lds_m > 0 ? dyn + 2 * kBT : nullptr;

@@ -192,29 +192,36 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
 // Single-workgroup reduction of every evaluation partial in a fixed order,
 // then the evaluation decision.
 __global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0_blocks) {
-  __shared__ double red[20 * (kDecideBlock / 64)];
-  __shared__ double E[38];
+  __shared__ double red[22 * (kDecideBlock / 64)];
+  __shared__ double E[42];
   DevState* st = p.st;
   if (eval_idle(st)) return;
   {
-    double S[18];
+    double S[22];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) S[k] = 0.0;
+    for (int k = 0; k < 22; ++k) S[k] = 0.0;
     for (int i = threadIdx.x; i < n_e0_blocks; i += kDecideBlock) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) S[k] += p.partE0[4 * i + k];
     }
     for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) S[4 + k] += p.partE1[8 * i + k];
+      for (int k = 0; k < 10; ++k) S[4 + k] += p.partE1[10 * i + k];
     }
     for (int i = threadIdx.x; i < p.KT.nred; i += kDecideBlock) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) S[12 + k] += p.partE2[6 * i + k];
+      for (int k = 0; k < 8; ++k) S[14 + k] += p.partE2[8 * i + k];
     }
-    block_sum<18, kDecideBlock / 64>(S, red);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 18; ++k) E[k] = S[k];
+    block_sum<22, kDecideBlock / 64>(S, red);
+    // partials order: rows 8 + 2 (gap), columns 6 + 2 (gap); E keeps the gap sums at 38..41
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < 12; ++k) E[k] = S[k];
+      E[38] = S[12];
+      E[39] = S[13];
+      for (int k = 0; k < 6; ++k) E[12 + k] = S[14 + k];
+      E[40] = S[20];
+      E[41] = S[21];
+    }
   }
   if (infeas_due(p, st)) {
     double T[20];
@@ -233,6 +240,56 @@ __global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0
       for (int k = 0; k < 20; ++k) E[18 + k] = T[k];
   }
   if (threadIdx.x == 0) eval_decision(st, p, p.tr, E, p.qnorm0, p.cnorm0);
+}
+
+// Normalized duality gap (restart metric 1): one pass of the multiplier
+// search over the columns (blocks [0, gn)) and the rows (blocks [gn, ...)),
+// both candidates, kGapPoints multiplier values each; one partial of kGapAcc
+// sums per workgroup.
+__global__ __launch_bounds__(kBlock) void k_gap_pass(Params p, int gn) {
+  __shared__ double red[kGapAcc * (kBlock / 64)];
+  const DevState* st = p.st;
+  if (!st->gap_active) return;
+  const GapScale g0(st->gap_lam[0], st->omega), g1(st->gap_lam[1], st->omega);
+  double acc[kGapAcc];
+#pragma unroll
+  for (int k = 0; k < kGapAcc; ++k) acc[k] = 0.0;
+  const int cur = st->cur;
+  if ((int)blockIdx.x < gn) {
+    const double* __restrict__ x = sel(cur, p.x[0], p.x[1]);
+    for (int j = p.col_base + blockIdx.x * kBlock + threadIdx.x; j < p.col_base + p.n; j += gn * kBlock) {
+      gap_col<0>(p, x, g0, j, acc);
+      gap_col<1>(p, x, g1, j, acc + 2 * kGapPoints);
+    }
+  } else {
+    const int gm = gridDim.x - gn;
+    const double* __restrict__ y = sel(cur, p.y[0], p.y[1]);
+    for (int i = p.row_base + (blockIdx.x - gn) * kBlock + threadIdx.x; i < p.row_base + p.m; i += gm * kBlock) {
+      gap_row<0>(p, y, g0, i, acc);
+      gap_row<1>(p, y, g1, i, acc + 2 * kGapPoints);
+    }
+  }
+  block_sum<kGapAcc>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kGapAcc; ++k) p.partG[kGapAcc * blockIdx.x + k] = acc[k];
+  }
+}
+
+// Single workgroup: the pass's partials in a fixed order, then gap_step.
+__global__ __launch_bounds__(kDecideBlock) void k_gap_step(Params p, int nparts) {
+  __shared__ double red[kGapAcc * (kDecideBlock / 64)];
+  DevState* st = p.st;
+  if (!st->gap_active) return;
+  double R[kGapAcc];
+#pragma unroll
+  for (int k = 0; k < kGapAcc; ++k) R[k] = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kDecideBlock) {
+#pragma unroll
+    for (int k = 0; k < kGapAcc; ++k) R[k] += p.partG[kGapAcc * i + k];
+  }
+  block_sum<kGapAcc, kDecideBlock / 64>(R, red);
+  if (threadIdx.x == 0) gap_step(st, p, p.tr, R);
 }
 
 // x-space part of a restart: z^{n+1,0} = candidate, sums cleared.  The flag
@@ -354,6 +411,13 @@ void launch_eval(const Params& p, hipStream_t s) {
     launch_op<InfeasColsOp, double>(p, p.KT, s);
   }
   hipLaunchKernelGGL(k_eval_decide, dim3(1), dim3(kDecideBlock), 0, s, p, ge);
+  if (p.gap) {
+    const int gn = elem_grid(p.n), gm = elem_grid(p.m);
+    for (int ph = 0; ph < kGapPasses + 2; ++ph) {
+      hipLaunchKernelGGL(k_gap_pass, dim3(gn + gm), dim3(kBlock), 0, s, p, gn);
+      hipLaunchKernelGGL(k_gap_step, dim3(1), dim3(kDecideBlock), 0, s, p, gn + gm);
+    }
+  }
   hipLaunchKernelGGL(k_restart_x, dim3(ge), dim3(kBlock), 0, s, p);
   if (p.use_f32) launch_op<RestartYOp, float>(p, p.K, s);
   else launch_op<RestartYOp, double>(p, p.K, s);

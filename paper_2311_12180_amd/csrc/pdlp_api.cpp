@@ -252,7 +252,7 @@ struct pdlp_handle {
   struct Lane {
     hipStream_t s = nullptr;
     double *pa = nullptr, *pb = nullptr, *pe0 = nullptr, *pe1 = nullptr, *pe2 = nullptr, *pe3 = nullptr,
-           *pe4 = nullptr;
+           *pe4 = nullptr, *pg = nullptr;
     DevState* hst[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
   };
@@ -338,6 +338,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->eps_infeas = 1e-8;
   o->infeas_every = 4;
   o->presolve = 0;
+  o->restart_metric = 0;
   return PDLP_OK;
 }
 
@@ -369,6 +370,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (!(o.eps_infeas > 0.0) || !std::isfinite(o.eps_infeas)) return why = "eps_infeas must be finite and > 0", -1;
   if (o.infeas_every < 1) return why = "infeas_every must be >= 1", -1;
   if (o.presolve != 0 && o.presolve != 1) return why = "presolve must be 0 or 1", -1;
+  if (o.restart_metric != 0 && o.restart_metric != 1) return why = "restart_metric must be 0 or 1", -1;
   return 0;
 }
 
@@ -751,6 +753,14 @@ static void alloc_iterates(pdlp_handle* h) {
   P.infeas = opt.detect_infeas;
   P.eps_infeas = opt.eps_infeas;
   P.infeas_every = opt.infeas_every;
+  P.gap = opt.restart_metric == 1;
+  if (P.gap) {
+    for (int k = 0; k < 2; ++k) {
+      P.kxe[k] = h->dalloc<double>(m);
+      P.ktye[k] = h->dalloc<double>(n);
+    }
+    P.partG = h->dalloc<double>((size_t)kGapAcc * 2 * kElemBlocks);
+  }
   if (P.infeas) {
     for (int k = 0; k < 2; ++k) {
       P.xr[k] = h->dalloc<double>(n);
@@ -877,8 +887,8 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     P.partA = h->dalloc<double>(redt);
     P.partB = h->dalloc<double>(2 * redk);
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
-    P.partE1 = h->dalloc<double>(8 * redk);
-    P.partE2 = h->dalloc<double>(6 * redt);
+    P.partE1 = h->dalloc<double>(10 * redk);
+    P.partE2 = h->dalloc<double>(8 * redt);
     if (P.infeas) {
       P.partE3 = h->dalloc<double>(8 * redk);
       P.partE4 = h->dalloc<double>(12 * redt);
@@ -1695,6 +1705,7 @@ static Params handoff_params(const pdlp_handle* h, int32_t b, const pdlp_handle:
   sp.partE2 = L.pe2;
   sp.partE3 = L.pe3;
   sp.partE4 = L.pe4;
+  sp.partG = L.pg;
   sp.st = h->bst + b;
   if (!(h->opt.trace > 0 && b == 0)) sp.tr = Trace{};
   sp.qnorm0 = std::sqrt(h->norms_h[4 * (size_t)b]);
@@ -1710,8 +1721,9 @@ static void handoff_lanes(pdlp_handle* h, size_t want) {
     L.pa = h->dalloc<double>((size_t)h->max_ht);
     L.pb = h->dalloc<double>(2 * (size_t)h->max_hk);
     L.pe0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
-    L.pe1 = h->dalloc<double>(8 * (size_t)h->max_hk);
-    L.pe2 = h->dalloc<double>(6 * (size_t)h->max_ht);
+    L.pe1 = h->dalloc<double>(10 * (size_t)h->max_hk);
+    L.pe2 = h->dalloc<double>(8 * (size_t)h->max_ht);
+    L.pg = h->dalloc<double>((size_t)kGapAcc * 2 * kElemBlocks);
     L.pe3 = h->dalloc<double>(8 * (size_t)h->max_hk);
     L.pe4 = h->dalloc<double>(12 * (size_t)h->max_ht);
     for (int k = 0; k < 2; ++k) {

@@ -15,6 +15,11 @@ constexpr int kTile = 2048;        // nonzeros staged in LDS per row block
 constexpr int kMaxRows = 1024;     // rows per row block
 constexpr int kElemBlocks = 2048;  // fixed grid of the row-wise kernels (deterministic partials)
 constexpr int kPanels = 8;         // column panels of the split layout = XCDs of the chip
+// normalized duality gap: multiplier values per pass, multisection passes, and
+// the sums a pass reduces (per candidate: ||d||^2 and g'd at each value)
+constexpr int kGapPoints = 4;
+constexpr int kGapPasses = 22;
+constexpr int kGapAcc = 2 * 2 * kGapPoints;
 
 // A row block of a CSR matrix: rows [r0, r1).  Either short rows with at most
 // kTile nonzeros in total (handled in one pass through LDS), or one long row
@@ -90,6 +95,14 @@ struct DevState {
   double rel_kkt, rel_gap, rel_p, rel_d, pobj, dobj;
   // infeasibility certificate (statuses 5, 6): 1 / ||ray|| and the unit ray's objective and residual
   double ray_scale, ray_obj, ray_res;
+  // normalized duality gap (restart metric 1): per candidate (current, average)
+  // the multiplier search of the trust-region problem, run between evaluation
+  // and restart while gap_active
+  double gap_lam[2][4];   // the multiplier values of the next pass
+  double gap_lo[2], gap_hi[2], gap_r[2], gap_rho[2];
+  double gap_dx2[2], gap_dy2[2];   // ||x_c - x0||^2, ||y_c - y0||^2 for the primal weight update
+  int32_t gap_mode[2];    // 0 searching, 1 ball not binding (multiplier lo), 2 rho = 0
+  int32_t gap_phase, gap_active;
   int64_t n_att, n_eval;  // trace entries written
 };
 
@@ -149,6 +162,12 @@ struct Params {
   double* yr[2];          // [m] each: the same for y, clipped at 0 on inequality rows
   double* partE3;         // 8 per partial of the rows of K~
   double* partE4;         // 12 per partial of the rows of K~'
+  // normalized duality gap (gap = 1): K~x, K~x_bar and K~'y, K~'y_bar of the
+  // evaluation, and 16 partials per elementwise block of the multiplier passes
+  int32_t gap;
+  double* kxe[2];
+  double* ktye[2];
+  double* partG;
 };
 
 constexpr int32_t kPaused = 16;  // internal status of a batched LP handed to the single-LP kernels

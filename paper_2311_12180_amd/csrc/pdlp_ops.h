@@ -298,7 +298,7 @@ struct DualOp {
 // residual of eq. (kkt) (scaled, and unscaled by D1^-1 for Section 4.1), q'y,
 // q'y_bar, ||y - y0||^2, ||y_bar - y0||^2; forms y_bar (flushing the pending weight).
 struct EvalRowsOp {
-  static constexpr int NV = 2, NACC = 8;
+  static constexpr int NV = 2, NACC = 10;
   __device__ static bool idle(const Params&, const DevState* st) { return eval_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.K; }
   __device__ static double* part(const Params& p) { return p.partE1; }
@@ -349,6 +349,12 @@ struct EvalRowsOp {
       acc[4 + it] += qi * yv;
       const double dd = yv - y0i;
       acc[6 + it] += dd * dd;
+      const double gy = qi - kv;   // the y-gradient of the normalized duality gap
+      acc[8 + it] += gy * gy;
+    }
+    if (p.gap) {
+      p.kxe[0][i] = s[0];
+      p.kxe[1][i] = s[1];
     }
   }
 };
@@ -357,7 +363,7 @@ struct EvalRowsOp {
 // proj_Lambda(c - K~'y), the dual residual (scaled, and unscaled by D2^-1),
 // l'lambda+ - u'lambda-.
 struct EvalColsOp {
-  static constexpr int NV = 2, NACC = 6;
+  static constexpr int NV = 2, NACC = 8;
   __device__ static bool idle(const Params&, const DevState* st) { return eval_idle(st); }
   __device__ static const DevCsr& mat(const Params& p) { return p.KT; }
   __device__ static double* part(const Params& p) { return p.partE2; }
@@ -386,6 +392,11 @@ struct EvalColsOp {
       acc[2 + it] += ru * ru;
       const double lp = lam > 0.0 ? lam : 0.0, lm = lam < 0.0 ? -lam : 0.0;
       acc[4 + it] += (lp > 0.0 ? lj * lp : 0.0) - (lm > 0.0 ? uj * lm : 0.0);
+      acc[6 + it] += g * g;   // (c - K'y)^2: the x-gradient of the normalized duality gap, squared
+    }
+    if (p.gap) {
+      p.ktye[0][j] = s[0];
+      p.ktye[1][j] = s[1];
     }
   }
 };
@@ -622,6 +633,166 @@ static __device__ void step_decision(DevState* st, const Params& p, const Trace&
   }
 }
 
+// Section 3.4 restart decision on the candidate metric values (KKT_omega or
+// the normalized duality gap) of the current and the average iterate: the
+// candidate, criteria (i)-(iii), the primal weight update (Section 2.2), the
+// restart flag; kkt0_of(cand, new omega, value) gives the next epoch's
+// reference value.
+template <class K0>
+static __device__ void restart_decision(DevState* st, const Params& p, const Trace& tr, double kc_cur, double kc_avg,
+                                        double dx2_cur, double dx2_avg, double dy2_cur, double dy2_avg,
+                                        K0&& kkt0_of) {
+  const double omega = st->omega;
+  // the current iterate only when clearly better: differences at rounding level
+  // (e.g. one step into an epoch, where the average is the iterate) go to the average
+  const int cand = !(kc_cur < kc_avg - p.tie_rel * kc_avg);
+  const double kc = cand ? kc_avg : kc_cur;
+  int reason = 0;
+  if (kc <= p.beta_suff * st->kkt0) reason = 1;
+  else if (kc <= p.beta_nec * st->kkt0 && kc > st->kkt_prev) reason = 2;
+  else if ((double)st->t >= p.beta_art * (double)st->k) reason = 3;
+  double om = omega;
+  if (reason) {
+    const double dxn = sqrt(cand ? dx2_avg : dx2_cur), dyn = sqrt(cand ? dy2_avg : dy2_cur);
+    if (dxn > p.eps_zero && dyn > p.eps_zero) om = exp(p.theta * log(dyn / dxn) + (1.0 - p.theta) * log(omega));
+    st->omega = om;
+    st->restart_flag = 1;
+    st->cand_avg = cand;
+    st->restarts++;
+    st->t = 0;
+    st->sum_eta = 0.0;
+    st->kkt0 = kkt0_of(cand, om, kc);
+    st->kkt_prev = st->kkt0;
+  } else {
+    st->kkt_prev = kc;
+  }
+  if (st->n_eval < tr.cap) {
+    const int64_t s = st->n_eval++;
+    tr.ev_k[s] = st->k;
+    tr.ev_kkt_cur[s] = kc_cur;
+    tr.ev_kkt_avg[s] = kc_avg;
+    tr.ev_cand[s] = (int8_t)cand;
+    tr.ev_reason[s] = (int8_t)reason;
+    tr.ev_omega[s] = om;
+  }
+}
+
+// ---- normalized duality gap (restart metric 1, PDLP's; Section 3.4 names it
+// as the metric the KKT error replaces).  rho_r(z) = max { L(x, yh) - L(xh, y)
+// : zh in Z, ||zh - z||_omega <= r } / r on the scaled LP, ||d||_omega^2 =
+// omega ||dx||^2 + ||dy||^2 / omega.  The objective is linear in d = zh - z
+// with gradient g = (K'y - c, q - Kx); the maximiser is
+// d(lam) = proj_{Z - z}(W^-1 g / lam), W = diag(omega, 1/omega), at the lam
+// where ||d(lam)||_omega = r (||d|| does not increase with lam), or at lo when
+// the ball does not bind there.  lam is bracketed between
+// hi = ||W^-1 g||_omega / r (where ||d|| <= r) and lo = 1e-12 hi and narrowed
+// by kGapPasses passes that each evaluate kGapPoints geometrically spaced
+// values; a last pass evaluates g'd at the result.  Both candidates (current,
+// average) are searched in the same passes.
+
+// The factors of d = W^-1 g / lam for one multiplier value: x-part
+// g_x / (omega lam) = g_x sx, y-part g_y omega / lam = g_y sy.
+struct GapScale {
+  double sx[kGapPoints], sy[kGapPoints];
+  double om, iom;
+  __device__ GapScale(const double* lam, double omega) : om(omega), iom(1.0 / omega) {
+#pragma unroll
+    for (int k = 0; k < kGapPoints; ++k) {
+      sx[k] = 1.0 / (omega * lam[k]);
+      sy[k] = omega / lam[k];
+    }
+  }
+};
+
+// Contributions of column j (x-space) to candidate C's pass sums
+// (acc[k] = ||d(lam_k)||^2 part, acc[4 + k] = g'd(lam_k) part).
+template <int C>
+__device__ __forceinline__ void gap_col(const Params& p, const double* __restrict__ x, const GapScale& g,
+                                        int j, double* acc) {
+  const double xc = C ? p.xbar[j] : x[j];
+  const double gx = p.ktye[C][j] - p.c[j];
+  const double lo = p.l[j] - xc, hi = p.u[j] - xc;
+#pragma unroll
+  for (int k = 0; k < kGapPoints; ++k) {
+    double d = gx * g.sx[k];
+    if (d < lo) d = lo;
+    if (d > hi) d = hi;
+    acc[k] += g.om * (d * d);
+    acc[4 + k] += gx * d;
+  }
+}
+
+// Contributions of row i (y-space) to candidate C's pass sums.
+template <int C>
+__device__ __forceinline__ void gap_row(const Params& p, const double* __restrict__ y, const GapScale& g,
+                                        int i, double* acc) {
+  const double yc = C ? p.ybar[i] : y[i];
+  const double gy = p.q[i] - p.kxe[C][i];
+  const bool ie = p.ineq[i] != 0;
+#pragma unroll
+  for (int k = 0; k < kGapPoints; ++k) {
+    double d = gy * g.sy[k];
+    if (ie && d < -yc) d = -yc;
+    acc[k] += (d * d) * g.iom;
+    acc[4 + k] += gy * d;
+  }
+}
+
+// One thread, after a pass: narrow each candidate's bracket (R[8c + k] =
+// ||d(lam_k)||^2, R[8c + 4 + k] = g'd(lam_k)) and set the next pass's values;
+// after the last pass, rho and the restart decision.
+static __device__ void gap_step(DevState* st, const Params& p, const Trace& tr, const double* R) {
+  const int ph = st->gap_phase;
+  const bool last = ph == kGapPasses + 1;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double r = st->gap_r[c], r2 = r * r;
+    double lo = st->gap_lo[c], hi = st->gap_hi[c];
+    if (last) {
+      st->gap_rho[c] = st->gap_mode[c] == 2 ? 0.0 : R[8 * c + 4] / r;
+      continue;
+    }
+    if (st->gap_mode[c] == 0) {
+      if (ph == 0) {
+        if (R[8 * c] <= r2) {   // the ball does not bind at lo: the multiplier is lo
+          st->gap_mode[c] = 1;
+          hi = lo;
+        }
+      } else {
+        // N decreases along the points: keep N(lo) > r^2 >= N(hi)
+        const double l0 = st->gap_lam[c][0], l1 = st->gap_lam[c][1], l2 = st->gap_lam[c][2],
+                     l3 = st->gap_lam[c][3];
+        if (R[8 * c + 0] <= r2) { hi = l0; }
+        else if (R[8 * c + 1] <= r2) { lo = l0; hi = l1; }
+        else if (R[8 * c + 2] <= r2) { lo = l1; hi = l2; }
+        else if (R[8 * c + 3] <= r2) { lo = l2; hi = l3; }
+        else { lo = l3; }
+      }
+    }
+    st->gap_lo[c] = lo;
+    st->gap_hi[c] = hi;
+    if (ph == kGapPasses || st->gap_mode[c] != 0) {
+#pragma unroll
+      for (int k = 0; k < kGapPoints; ++k) st->gap_lam[c][k] = hi;
+    } else {
+      const double q = exp(log(hi / lo) / (kGapPoints + 1));
+      double v = lo;
+#pragma unroll
+      for (int k = 0; k < kGapPoints; ++k) {
+        v = v * q;
+        st->gap_lam[c][k] = v;
+      }
+    }
+  }
+  if (last) {
+    st->gap_active = 0;
+    restart_decision(st, p, tr, st->gap_rho[0], st->gap_rho[1], st->gap_dx2[0], st->gap_dx2[1], st->gap_dy2[0],
+                     st->gap_dy2[1], [](int, double, double kc) { return kc; });
+    return;
+  }
+  st->gap_phase = ph + 1;
+}
+
 // Evaluation decision on the reduced sums S (one thread): termination
 // (Section 4.1) on both iterates, else the restart candidate and the restart
 // criteria (Section 3.4), the primal weight update (Section 2.2).
@@ -630,6 +801,7 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
   // S: 0 c'x 1 c'xb 2 |x-x0|^2 3 |xb-x0|^2 | 4,5 rp2 scaled 6,7 rp2 unscaled 8,9 q'y 10,11 |y-y0|^2
   //    | 12,13 rd2 scaled 14,15 rd2 unscaled 16,17 l'lam+ - u'lam-     (pairs: current, average)
   //    | 18 + 4c: InfeasRowsOp of candidate c | 26 + 6c: InfeasColsOp of candidate c (when p.infeas)
+  //    | 38,39 ||q - Kx||^2 | 40,41 ||c - K'y||^2 (the normalized duality gap's gradients)
   const double omega = st->omega;
   double pobj[2], dobj[2], rel[2], rg[2], rpr[2], rdr[2];
   for (int it = 0; it < 2; ++it) {
@@ -661,7 +833,8 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
   st->has_pending = 0;
   if (st->initial) {
     st->initial = 0;
-    st->kkt0 = kkt_w(0, omega);
+    // the restart metric's reference value (normalized duality gap: +inf before the first restart)
+    st->kkt0 = p.gap ? INFINITY : kkt_w(0, omega);
     st->kkt_prev = st->kkt0;
     store(0);
     st->ret_avg = 0;
@@ -730,39 +903,37 @@ static __device__ void eval_decision(DevState* st, const Params& p, const Trace&
     return;
   }
   store(avg_better);
-  const double kc_cur = kkt_w(0, omega), kc_avg = kkt_w(1, omega);
-  // the current iterate only when clearly better: differences at rounding level
-  // (e.g. one step into an epoch, where the average is the iterate) go to the average
-  const int cand = !(kc_cur < kc_avg - p.tie_rel * kc_avg);
-  const double kc = cand ? kc_avg : kc_cur;
-  int reason = 0;
-  if (kc <= p.beta_suff * st->kkt0) reason = 1;
-  else if (kc <= p.beta_nec * st->kkt0 && kc > st->kkt_prev) reason = 2;
-  else if ((double)st->t >= p.beta_art * (double)st->k) reason = 3;
-  double om = omega;
-  if (reason) {
-    const double dxn = sqrt(S[2 + cand]), dyn = sqrt(S[10 + cand]);
-    if (dxn > p.eps_zero && dyn > p.eps_zero) om = exp(p.theta * log(dyn / dxn) + (1.0 - p.theta) * log(omega));
-    st->omega = om;
-    st->restart_flag = 1;
-    st->cand_avg = cand;
-    st->restarts++;
-    st->t = 0;
-    st->sum_eta = 0.0;
-    st->kkt0 = kkt_w(cand, om);
-    st->kkt_prev = st->kkt0;
-  } else {
-    st->kkt_prev = kc;
+  if (p.gap) {
+    // normalized duality gap: set up the multiplier search of each candidate's
+    // trust-region problem; the restart decision follows the passes (gap_step)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double dx2 = S[2 + c], dy2 = S[10 + c];
+      st->gap_dx2[c] = dx2;
+      st->gap_dy2[c] = dy2;
+      const double r = sqrt(omega * dx2 + dy2 / omega);
+      const double gn2 = S[40 + c] / omega + omega * S[38 + c];
+      st->gap_r[c] = r;
+      st->gap_rho[c] = 0.0;
+      double lo = 1.0, hi = 1.0;
+      if (r > 0.0 && gn2 > 0.0) {
+        hi = sqrt(gn2) / r;
+        lo = hi * 1e-12;
+        st->gap_mode[c] = 0;
+      } else {
+        st->gap_mode[c] = 2;
+      }
+      st->gap_lo[c] = lo;
+      st->gap_hi[c] = hi;
+#pragma unroll
+      for (int k = 0; k < kGapPoints; ++k) st->gap_lam[c][k] = lo;
+    }
+    st->gap_phase = 0;
+    st->gap_active = 1;
+    return;
   }
-  if (st->n_eval < tr.cap) {
-    const int64_t s = st->n_eval++;
-    tr.ev_k[s] = st->k;
-    tr.ev_kkt_cur[s] = kc_cur;
-    tr.ev_kkt_avg[s] = kc_avg;
-    tr.ev_cand[s] = (int8_t)cand;
-    tr.ev_reason[s] = (int8_t)reason;
-    tr.ev_omega[s] = om;
-  }
+  restart_decision(st, p, tr, kkt_w(0, omega), kkt_w(1, omega), S[2], S[3], S[10], S[11],
+                   [&](int cand, double om, double) { return kkt_w(cand, om); });
 }
 
 }  // namespace pdlp

@@ -1,0 +1,139 @@
+"""GPU restarts on PDLP's normalized duality gap (restart_metric = 1) against
+the oracle (pinned in tests/test_oracle_gap.py).
+
+Bars, as for the KKT metric: over the first 200 accepted steps (three
+evaluations) the same decisions (every candidate and restart reason, the
+numbers of attempts and restarts), the gap values in the decision trace and
+the returned point within max(1e-9, 100 x) the oracle's own spread when only
+its summation order changes; end to end the objective within the
+reading-17 bars of the oracle's and the point re-checked by the FP64
+evaluator; the batched solver, also across a hand-off, the same.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2311_12180_amd import pdlp
+    pdlp.lib()
+    return pdlp
+
+
+def _rel_inf(a, b):
+    return float(np.abs(a - b).max(initial=0.0) / max(1.0, np.abs(b).max(initial=0.0)))
+
+
+def _spread(orc, p, opts, copies=3):
+    a = orc.solve(p, trace_cap=4096, **opts)
+    sx = sg = 0.0
+    stable = True
+    for s in range(copies):
+        rng = np.random.default_rng(321 + s)
+        rp, cp = rng.permutation(p.m), rng.permutation(p.n)
+        b = orc.solve(lpgen.permute(p, rp, cp), trace_cap=4096, **opts)
+        stable &= (b.info["attempts"] == a.info["attempts"] and b.info["restarts"] == a.info["restarts"]
+                   and np.array_equal(b.trace["ev_cand"], a.trace["ev_cand"])
+                   and np.array_equal(b.trace["ev_reason"], a.trace["ev_reason"]))
+        sx = max(sx, _rel_inf(b.x, a.x[cp]), _rel_inf(b.y, a.y[rp]))
+        if len(b.trace["ev_kkt_cur"]) == len(a.trace["ev_kkt_cur"]):
+            for key in ("ev_kkt_cur", "ev_kkt_avg"):
+                d = np.abs(b.trace[key] - a.trace[key]) / np.maximum(np.abs(a.trace[key]), 1e-300)
+                sg = max(sg, float(d.max(initial=0.0)))
+    return a, sx, sg, bool(stable)
+
+
+FAMILIES = [lambda: lpgen.batch_lp(0, 0, 300), lambda: lpgen.mixed_lp(1), lambda: lpgen.transportation(1, 30, 40),
+            lambda: lpgen.skewed_lp(0, m=2000, n=4000, nnz_target=40000, cap=400)]
+
+
+@pytest.mark.parametrize("k", range(len(FAMILIES)))
+def test_first_200_steps_match_oracle(P, orc, k):
+    p = FAMILIES[k]()
+    opts = dict(eps_rel=0.0, max_iter=200, restart_metric=1)
+    r, sx, sg, stable = _spread(orc, p, opts)
+    if not stable:
+        pytest.skip("the oracle's own decisions change under renumbering (a near-tie)")
+    h = P.pdlp_create(p, trace=4096, time_limit_s=60.0, **opts)
+    try:
+        P.pdlp_solve(h)
+        x, y, rc, I = P.pdlp_get_solution(h)
+        tr = P.pdlp_get_trace(h, 4096)
+    finally:
+        P.pdlp_destroy(h)
+    print(f"{p.name}: restarts {I['restarts']}, gaps {tr['ev_kkt_cur']}, spreads x {sx:.1e} gap {sg:.1e}")
+    assert I["status_name"] == "ITER_LIMIT" and I["iterations"] == 200
+    assert I["attempts"] == r.info["attempts"] and I["restarts"] == r.info["restarts"]
+    np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
+    np.testing.assert_array_equal(tr["ev_reason"], r.trace["ev_reason"])
+    for key in ("ev_kkt_cur", "ev_kkt_avg"):
+        np.testing.assert_allclose(tr[key], r.trace[key], rtol=max(1e-9, 100 * sg))
+    tol = max(1e-9, 100 * sx)
+    assert _rel_inf(x, r.x) <= tol and _rel_inf(y, r.y) <= tol
+
+
+@pytest.mark.parametrize("k", range(len(FAMILIES)))
+def test_end_to_end_matches_oracle(P, orc, k):
+    p = FAMILIES[k]()
+    eps = 1e-6
+    opts = dict(eps_rel=eps, max_iter=1_000_000, restart_metric=1)
+    r = orc.solve(p, **opts)
+    res = P.solve(p, time_limit_s=120.0, **opts)
+    I = res.info
+    assert res.status == "OPTIMAL" and r.status == "OPTIMAL"
+    e = orc.evaluate(p, res.x, res.y)
+    assert e["rel_kkt"] <= eps * (1 + 1e-6)
+    same = I["attempts"] == r.info["attempts"] and I["iterations"] == r.info["iterations"]
+    tol = 1e-6 if same else max(1e-6, 2 * eps)
+    ro = r.info["primal_obj"]
+    assert abs(I["primal_obj"] - ro) <= tol * (1 + abs(ro))
+    print(f"{p.name}: GPU {I['iterations']} steps, oracle {r.info['iterations']}, same path {same}")
+
+
+@pytest.mark.parametrize("handoff", [0, 64])
+def test_batch_with_gap_restarts(P, orc, handoff):
+    probs = [lpgen.batch_lp(11, i, 80 + 40 * i) for i in range(6)] + [lpgen.mixed_lp(3), lpgen.transportation(2, 8, 11)]
+    eps = 1e-6
+    opts = dict(eps_rel=eps, max_iter=1_000_000, restart_metric=1)
+    h = P.pdlp_create_batch(probs, time_limit_s=120.0, batch_handoff=handoff, handoff_streams=3, **opts)
+    try:
+        P.pdlp_solve_batch(h)
+        for k, p in enumerate(probs):
+            x, y, rc, I = P.pdlp_get_solution_batch(h, k)
+            r = orc.solve(p, **opts)
+            assert I["status_name"] == "OPTIMAL" and r.status == "OPTIMAL", (k, p.name)
+            assert orc.evaluate(p, x, y)["rel_kkt"] <= eps * (1 + 1e-6), k
+            same = I["attempts"] == r.info["attempts"] and I["iterations"] == r.info["iterations"]
+            tol = 1e-6 if same else max(1e-6, 2 * eps)
+            ro = r.info["primal_obj"]
+            assert abs(I["primal_obj"] - ro) <= tol * (1 + abs(ro)), (k, p.name)
+    finally:
+        P.pdlp_destroy(h)
+
+
+def test_batch_first_200_steps_trace(P, orc):
+    """LP 0 of a batch (the traced one) follows the oracle's gap decisions."""
+    probs = [lpgen.batch_lp(12, i, 150) for i in range(5)]
+    opts = dict(eps_rel=0.0, max_iter=200, restart_metric=1)
+    r, sx, sg, stable = _spread(orc, probs[0], opts)
+    if not stable:
+        pytest.skip("the oracle's own decisions change under renumbering (a near-tie)")
+    h = P.pdlp_create_batch(probs, trace=4096, time_limit_s=60.0, **opts)
+    try:
+        P.pdlp_solve_batch(h)
+        x, y, rc, I = P.pdlp_get_solution_batch(h, 0)
+        tr = P.pdlp_get_trace(h, 4096)
+    finally:
+        P.pdlp_destroy(h)
+    assert I["attempts"] == r.info["attempts"] and I["restarts"] == r.info["restarts"]
+    np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
+    np.testing.assert_array_equal(tr["ev_reason"], r.trace["ev_reason"])
+    np.testing.assert_allclose(tr["ev_kkt_cur"], r.trace["ev_kkt_cur"], rtol=max(1e-9, 100 * sg))
+    tol = max(1e-9, 100 * sx)
+    assert _rel_inf(x, r.x) <= tol and _rel_inf(y, r.y) <= tol
