@@ -351,11 +351,13 @@ def main():
         ttt = {}
         import oracle
         oracle.build()
-        runs = [("fp64_1e-4", 0, 1e-4, 0), ("fp32_matrix_1e-4", 1, 1e-4, 0), ("fp64_1e-8", 0, 1e-8, 0),
-                ("fp64_presolve_1e-4", 0, 1e-4, 1), ("fp64_presolve_1e-8", 0, 1e-8, 1)]
-        for name, prec, eps, pre in runs:
+        # (name, matrix precision, tolerance, presolve, restart metric: 0 KKT, 1 normalized duality gap)
+        runs = [("fp64_1e-4", 0, 1e-4, 0, 0), ("fp32_matrix_1e-4", 1, 1e-4, 0, 0), ("fp64_1e-8", 0, 1e-8, 0, 0),
+                ("fp64_presolve_1e-4", 0, 1e-4, 1, 0), ("fp64_presolve_1e-8", 0, 1e-8, 1, 0),
+                ("fp64_gap_restarts_1e-4", 0, 1e-4, 0, 1)]
+        for name, prec, eps, pre, metric in runs:
             h = P.pdlp_create(prob, stream=stream, eps_rel=eps, a_precision=prec, time_limit_s=args.ttt_limit,
-                              presolve=pre)
+                              presolve=pre, restart_metric=metric)
             P.pdlp_solve(h)
             x, y, rc, inf = P.pdlp_get_solution(h)
             ev = oracle.evaluate(prob, x, y)
@@ -369,21 +371,22 @@ def main():
                 ttt[name]["solved_m_n"] = [inf["m_solved"], inf["n_solved"]]
             log(f"time to {eps:g} ({name}): {ttt[name]}")
             P.pdlp_destroy(h)
-        # the 2000 x 2000 transportation LP (n = 4e6, m = 4000, nnz = 8e6) to 1e-6
+        # the 2000 x 2000 transportation LP (n = 4e6, m = 4000, nnz = 8e6) to 1e-6, both restart metrics
         import lpgen
         tp = lpgen.config2(0)
-        h = P.pdlp_create(tp, stream=stream, eps_rel=1e-6, time_limit_s=args.ttt_limit)
-        P.pdlp_solve(h)
-        x, y, rc, inf = P.pdlp_get_solution(h)
-        ev = oracle.evaluate(tp, x, y)
-        ttt["transport_2000x2000_1e-6"] = {
-            "status": inf["status_name"], "iterations": inf["iterations"], "attempts": inf["attempts"],
-            "restarts": inf["restarts"], "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
-            "iters_per_s": round(inf["iterations"] / max(inf["solve_s"], 1e-9), 1),
-            "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
-            "primal_obj": inf["primal_obj"], "layout_k_kt": [inf["layout_k"], inf["layout_kt"]]}
-        log(f"transportation to 1e-6: {ttt['transport_2000x2000_1e-6']}")
-        P.pdlp_destroy(h)
+        for name, metric in (("transport_2000x2000_1e-6", 0), ("transport_2000x2000_gap_restarts_1e-6", 1)):
+            h = P.pdlp_create(tp, stream=stream, eps_rel=1e-6, time_limit_s=args.ttt_limit, restart_metric=metric)
+            P.pdlp_solve(h)
+            x, y, rc, inf = P.pdlp_get_solution(h)
+            ev = oracle.evaluate(tp, x, y)
+            ttt[name] = {
+                "status": inf["status_name"], "iterations": inf["iterations"], "attempts": inf["attempts"],
+                "restarts": inf["restarts"], "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
+                "iters_per_s": round(inf["iterations"] / max(inf["solve_s"], 1e-9), 1),
+                "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
+                "primal_obj": inf["primal_obj"], "layout_k_kt": [inf["layout_k"], inf["layout_kt"]]}
+            log(f"transportation to 1e-6 ({name}): {ttt[name]}")
+            P.pdlp_destroy(h)
 
     batch = None
     if not args.no_batch:
