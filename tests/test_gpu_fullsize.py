@@ -1,0 +1,207 @@
+"""Parity at the workloads' full sizes, in the configuration bench.py times
+(default options: layouts chosen by timing at create, hipGraph loop), against
+the oracle where it can afford the size and otherwise on samples or on
+properties that hold at any size:
+
+  * the 1e6 x 2e6 skewed LP (nnz 2e7): the preconditioner and scaled matrix
+    bitwise equal to the oracle's; the first two accepted steps (one
+    evaluation at each) with the oracle's attempts and iterates within
+    max(1e-10, 100 x) its renumbering spread; to rel KKT 1e-4 with the FP64
+    and the FP32 matrix, the returned point re-checked by the FP64 evaluator,
+    the objective within 2e-4 of the known optimum, and bitwise run to run;
+  * the 2000 x 2000 transportation LP to 1e-6, re-checked by the evaluator;
+  * the 4,096-LP batch at 1e-6: every LP OPTIMAL and re-checked by the FP64
+    evaluator, the known optimum of every LP met to 1e-4, a sample of 12 LPs
+    against oracle solves (objective within 2 eps);
+  * the 20,000-LP warm-start family: network predictions for LPs sampled
+    across the whole family against the reference network (bar derived in
+    the test).
+"""
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2311_12180_amd import pdlp
+    pdlp.lib()
+    return pdlp
+
+
+@pytest.fixture(scope="module")
+def big():
+    return lpgen.config1(0)
+
+
+def _rel_inf(a, b):
+    return float(np.abs(a - b).max(initial=0.0) / max(1.0, np.abs(b).max(initial=0.0)))
+
+
+def test_large_lp_scaling_bitwise(P, orc, big):
+    h = P.pdlp_create(big, eps_rel=1e-4, time_limit_s=60.0)
+    try:
+        D1, D2, vs = P.pdlp_get_scaling(h)
+    finally:
+        P.pdlp_destroy(h)
+    E1, E2, ws = orc.rescale(big)
+    np.testing.assert_array_equal(D1, E1)
+    np.testing.assert_array_equal(D2, E2)
+    np.testing.assert_array_equal(vs, ws)
+
+
+def test_large_lp_first_steps(P, orc, big):
+    opts = dict(eps_rel=0.0, max_iter=2)
+    r = orc.solve(big, **opts)
+    rng = np.random.default_rng(5)
+    rp, cp = rng.permutation(big.m), rng.permutation(big.n)
+    q = orc.solve(lpgen.permute(big, rp, cp), **opts)
+    spread = max(_rel_inf(q.x, r.x[cp]), _rel_inf(q.y, r.y[rp]))
+    res = P.solve(big, time_limit_s=60.0, **opts)
+    I = res.info
+    ex, ey = _rel_inf(res.x, r.x), _rel_inf(res.y, r.y)
+    tol = max(1e-10, 100 * spread)
+    print(f"after 2 steps: x {ex:.1e} y {ey:.1e} (oracle spread {spread:.1e}); layouts {I['layout_k']} {I['layout_kt']}")
+    assert I["iterations"] == 2 and I["attempts"] == r.info["attempts"] == q.info["attempts"]
+    assert ex <= tol and ey <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_large_lp_to_1e4(P, orc, big, prec):
+    eps = 1e-4
+    a = P.solve(big, eps_rel=eps, a_precision=prec, time_limit_s=60.0)
+    b = P.solve(big, eps_rel=eps, a_precision=prec, time_limit_s=60.0)
+    assert a.status == "OPTIMAL"
+    np.testing.assert_array_equal(a.x, b.x)
+    np.testing.assert_array_equal(a.y, b.y)
+    e = orc.evaluate(big, a.x, a.y)
+    assert e["rel_kkt"] <= eps * (1 + 1e-6), e
+    assert e["primal_obj"] == pytest.approx(a.info["primal_obj"], rel=1e-12)
+    ref = big.obj_star()
+    err = abs(a.info["primal_obj"] - ref) / (1 + abs(ref))
+    print(f"precision {prec}: {a.info['iterations']} steps, objective error {err:.1e}")
+    assert err <= 2 * eps
+
+
+def test_transportation_to_1e6(P, orc):
+    tp = lpgen.config2(0)
+    res = P.solve(tp, eps_rel=1e-6, time_limit_s=120.0)
+    assert res.status == "OPTIMAL"
+    e = orc.evaluate(tp, res.x, res.y)
+    assert e["rel_kkt"] <= 1e-6 * (1 + 1e-6), e
+    np.testing.assert_allclose(res.rc, orc.reduced_costs(tp, res.y), rtol=1e-9, atol=1e-9)
+
+
+def _gen(args):
+    seed, i, m = args
+    return lpgen.batch_lp(seed, i, m)
+
+
+def test_batch_4096_sampled(P, orc):
+    count = 4096
+    ms = lpgen.batch_sizes(0, count)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(workers) as ex:
+        probs = list(ex.map(_gen, [(0, i, int(ms[i])) for i in range(count)], chunksize=16))
+    eps = 1e-6
+    h = P.pdlp_create_batch(probs, eps_rel=eps, max_iter=200000, time_limit_s=120.0)
+    try:
+        P.pdlp_solve_batch(h)
+        x, y, rc, infos = P.pdlp_get_solution_batch(h, -1)
+    finally:
+        P.pdlp_destroy(h)
+    assert all(i["status_name"] == "OPTIMAL" for i in infos)
+    objs = np.array([i["primal_obj"] for i in infos])
+    ref = np.array([p.obj_star() for p in probs])
+    col_off = np.concatenate([[0], np.cumsum([p.n for p in probs])])
+    row_off = np.concatenate([[0], np.cumsum([p.m for p in probs])])
+    # every LP's point passes the FP64 evaluator at the tolerance
+    worst = 0.0
+    for k, p in enumerate(probs):
+        e = orc.evaluate(p, x[col_off[k]:col_off[k + 1]], y[row_off[k]:row_off[k + 1]])
+        worst = max(worst, e["rel_kkt"])
+    err = np.abs(objs - ref) / (1 + np.abs(ref))
+    print(f"worst evaluator rel KKT {worst:.2e}; objective error vs the known optima: max {err.max():.2e}, "
+          f"median {np.median(err):.2e}")
+    assert worst <= eps * (1 + 1e-6)
+    # a relative KKT error of 1e-6 is not an objective bound; the known optima are met loosely
+    assert err.max() <= 1e-4
+    rng = np.random.default_rng(9)
+    for k in rng.choice(count, 12, replace=False):
+        p = probs[k]
+        r = orc.solve(p, eps_rel=eps, max_iter=200000)
+        assert abs(objs[k] - r.info["primal_obj"]) <= 2 * eps * (1 + abs(r.info["primal_obj"])), k
+
+
+def _gen_family(k):
+    return lpgen.transport_family_lp(0, k)
+
+
+def _noise_spread(G, Pm, gr, ref, amp, draws=2):
+    """How far the bfloat16-operand reference moves when its input features
+    carry relative noise of size amp: its own sensitivity to rounding
+    decisions taken on nearby values."""
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+    out = np.zeros(3)
+    for d in range(draws):
+        rng = np.random.default_rng(1000 + d)
+        g2 = dict(gr)
+        for key in ("f_v", "f_c"):
+            g2[key] = gr[key] * (1 + amp * rng.standard_normal(gr[key].shape))
+        sx, sy, so = G.predictions(g2, *G.forward(Pm, g2, bf16_ops=True)[:3])
+        out = np.maximum(out, [rel(sx, ref[0]), rel(sy, ref[1]), abs(so - ref[2]) / abs(ref[2])])
+    return out
+
+
+def test_warm_start_family_predictions_sampled():
+    """Predictions for LPs spread across the 20,000-LP family (one graph set
+    over all of them, as the warm-start run builds it) against the reference
+    network with bfloat16 operands, and against the unrounded FP64 network.
+
+    Bar: the kernels accumulate the 128-term products in FP32 (relative error
+    about sqrt(128) 2^-24 = 7e-7), so some operands round to the other
+    bfloat16 neighbour than in the FP64 reference; with 10,200 nodes and three
+    rounds these LPs have hundreds of such operands.  The bar is measured
+    rather than estimated: the reference's own displacement when its input
+    features carry 7e-7 relative noise (two draws), times 4, and at least
+    1e-4; against the unrounded network, 2e-2 (the bfloat16 unit)."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2311_12180_amd import gnn as N
+    from oracle import gnn as G
+    count = 20000
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(workers) as ex:
+        probs = list(ex.map(_gen_family, range(count), chunksize=64))
+    th = lpgen.gnn_init(1, G.PARAMS).astype(np.float32).astype(np.float64)
+    g = N.pdlp_gnn_create(probs)
+    try:
+        N.pdlp_gnn_set_params(g, th)
+        Pm = G.unflatten(th)
+        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        for first in (0, 9_968, 19_936):
+            x0, y0, om = N.pdlp_gnn_predict(g, first, 64)
+            for k in (0, 63):
+                p = probs[first + k]
+                gr = G.graph(p)
+                rx, ry, ro = G.predictions(gr, *G.forward(Pm, gr, bf16_ops=True)[:3])
+                fx, fy, _ = G.predictions(gr, *G.forward(Pm, gr, bf16_ops=False)[:3])
+                bar = np.maximum(1e-4, 4 * _noise_spread(G, Pm, gr, (rx, ry, ro), 7e-7))
+                cx = int(g.col_off[first + k] - g.col_off[first])
+                cy = int(g.row_off[first + k] - g.row_off[first])
+                gx, gy = x0[cx:cx + p.n], y0[cy:cy + p.m]
+                e = np.array([rel(gx, rx), rel(gy, ry), abs(om[k] - ro) / abs(ro)])
+                print(f"LP {first + k}: vs bf16 reference x {e[0]:.1e} y {e[1]:.1e} omega {e[2]:.1e} "
+                      f"(bars {bar[0]:.1e} {bar[1]:.1e} {bar[2]:.1e}); vs FP64 x {rel(gx, fx):.1e} y {rel(gy, fy):.1e}")
+                assert (e <= bar).all(), (first + k, e, bar)
+                assert rel(gx, fx) <= 2e-2 and rel(gy, fy) <= 2e-2, first + k
+    finally:
+        N.pdlp_gnn_destroy(g)
