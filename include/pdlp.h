@@ -151,6 +151,14 @@ typedef struct {
                                  betas and primal weight update are those of the KKT scheme, the
                                  reference value being the restart point's rho (+inf before the
                                  first restart).  Termination is unchanged (Section 4.1) */
+  int32_t row_order;          /* single-LP handles: 1 (default) = the device numbers the rows by
+                                 descending number of nonzeros, equal counts by first column
+                                 (after the scaling, so D1, D2 and K~ are unchanged): on LPs with
+                                 skewed row lengths the gathers of y and of x then hit the caches
+                                 far more often.  Only the order of floating-point sums changes;
+                                 every vector crossing this interface (y, D1, K~, warm starts)
+                                 stays in the caller's row order.  0 = the given order.  Batch
+                                 handles keep the given order */
 } pdlp_options;
 
 typedef struct {

@@ -54,6 +54,9 @@ hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s);
 hipError_t setup_fill(int64_t n, double* a, double val, hipStream_t s);
 hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
                          int32_t* pci, double* pv, float* pvf, hipStream_t s);
+hipError_t setup_rename(int64_t nnz, const int32_t* inv, int32_t* ci, hipStream_t s);
+hipError_t setup_gather_rows(int32_t m, const int32_t* perm, const double* src, double* dst, hipStream_t s);
+hipError_t setup_gather_rows_i8(int32_t m, const int32_t* perm, const int8_t* src, int8_t* dst, hipStream_t s);
 }  // namespace pdlp
 
 using namespace pdlp;
@@ -262,6 +265,18 @@ struct pdlp_handle {
   bool presolved = false;
   Presolve pre;
   HostLP orig;
+  // row renumbering (single-LP handles, row_order = 1): device row r is row
+  // rperm[r] of the LP given to the device (empty: the identity); rp_given and
+  // rp_dev are K's row pointers in the two numberings
+  std::vector<int32_t> rperm, rp_given, rp_dev;
+
+  // device row order <-> the given order, for vectors over the rows
+  void rows_to_given(const double* dev, double* given) const {
+    for (size_t r = 0; r < rperm.size(); ++r) given[rperm[r]] = dev[r];
+  }
+  void rows_to_dev(const double* given, double* dev) const {
+    for (size_t r = 0; r < rperm.size(); ++r) dev[r] = given[rperm[r]];
+  }
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -339,6 +354,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->infeas_every = 4;
   o->presolve = 0;
   o->restart_metric = 0;
+  o->row_order = 1;
   return PDLP_OK;
 }
 
@@ -371,6 +387,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.infeas_every < 1) return why = "infeas_every must be >= 1", -1;
   if (o.presolve != 0 && o.presolve != 1) return why = "presolve must be 0 or 1", -1;
   if (o.restart_metric != 0 && o.restart_metric != 1) return why = "restart_metric must be 0 or 1", -1;
+  if (o.row_order != 0 && o.row_order != 1) return why = "row_order must be 0 or 1", -1;
   return 0;
 }
 
@@ -705,6 +722,96 @@ static void scale_problem(pdlp_handle* h) {
   }
 }
 
+// Row renumbering for the locality of the gathers: rows by descending length,
+// equal lengths by their first column, then by index.  On a power-law LP the
+// few long rows that hold most nonzeros get the first entries of y (the
+// primal step's gathers of y then stay in L1 and L2), and the many short rows
+// follow their columns (gathers in increasing address order).  Done after the
+// scaling, so D1, D2 and K~ are those of the given order: K~'s entries keep
+// their place (each column is summed in the same order) with new row indices,
+// and K~'s rows move whole.  H.rp and H.ci become the new structure.
+static void renumber_rows(pdlp_handle* h, HostLP& H) {
+  const int32_t m = h->m;
+  const int64_t nnz = h->nnz;
+  if (!h->opt.row_order || m < 2) return;
+  std::vector<int32_t> perm((size_t)m);
+  for (int32_t r = 0; r < m; ++r) perm[(size_t)r] = r;
+  auto len = [&](int32_t r) { return H.rp[(size_t)r + 1] - H.rp[(size_t)r]; };
+  auto first = [&](int32_t r) { return len(r) > 0 ? H.ci[(size_t)H.rp[(size_t)r]] : INT32_MAX; };
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    const int32_t la = len(a), lb = len(b);
+    if (la != lb) return la > lb;
+    return first(a) < first(b);
+  });
+  bool ident = true;
+  for (int32_t r = 0; r < m && ident; ++r) ident = perm[(size_t)r] == r;
+  if (ident) return;
+  std::vector<int32_t> rp2((size_t)m + 1, 0), src((size_t)std::max<int64_t>(nnz, 1)), inv((size_t)m);
+  std::vector<int32_t> ci2((size_t)std::max<int64_t>(nnz, 1));
+  for (int32_t r = 0; r < m; ++r) {
+    const int32_t o = perm[(size_t)r], b = H.rp[(size_t)o], L = len(o);
+    rp2[(size_t)r + 1] = rp2[(size_t)r] + L;
+    for (int32_t k = 0; k < L; ++k) {
+      src[(size_t)rp2[(size_t)r] + k] = b + k;
+      ci2[(size_t)rp2[(size_t)r] + k] = H.ci[(size_t)b + k];
+    }
+    inv[(size_t)o] = r;
+  }
+  hipStream_t s = h->stream;
+  const hipMemcpyKind kind = hipMemcpyHostToDevice;
+  // scratch of the move, freed before returning
+  std::vector<void*> tmp;
+  auto talloc = [&](size_t bytes) {
+    void* p = nullptr;
+    check(hipMalloc(&p, std::max<size_t>(bytes, 1)), "hipMalloc");
+    tmp.push_back(p);
+    return p;
+  };
+  try {
+    int32_t* d_src = static_cast<int32_t*>(talloc((size_t)nnz * 4));
+    int32_t* d_perm = static_cast<int32_t*>(talloc((size_t)m * 4));
+    int32_t* d_inv = static_cast<int32_t*>(talloc((size_t)m * 4));
+    int32_t* t_ci = static_cast<int32_t*>(talloc((size_t)nnz * 4));
+    double* t_v = static_cast<double*>(talloc((size_t)nnz * 8));
+    float* t_vf = h->valf ? static_cast<float*>(talloc((size_t)nnz * 4)) : nullptr;
+    double* t_row = static_cast<double*>(talloc((size_t)m * 8));
+    int8_t* t_row8 = static_cast<int8_t*>(talloc((size_t)m));
+    if (nnz) check(hipMemcpyAsync(d_src, src.data(), (size_t)nnz * 4, kind, s), "upload renumbering");
+    check(hipMemcpyAsync(d_perm, perm.data(), (size_t)m * 4, kind, s), "upload renumbering");
+    check(hipMemcpyAsync(d_inv, inv.data(), (size_t)m * 4, kind, s), "upload renumbering");
+    // K~: rows moved whole
+    check(setup_permute(nnz, d_src, h->ci, h->val, h->valf, t_ci, t_v, t_vf, s), "renumber K");
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    if (nnz) {
+      check(hipMemcpyAsync(h->ci, t_ci, (size_t)nnz * 4, d2d, s), "renumber K");
+      check(hipMemcpyAsync(h->val, t_v, (size_t)nnz * 8, d2d, s), "renumber K");
+      if (h->valf) check(hipMemcpyAsync(h->valf, t_vf, (size_t)nnz * 4, d2d, s), "renumber K");
+    }
+    check(hipMemcpyAsync(h->rp, rp2.data(), ((size_t)m + 1) * 4, kind, s), "renumber K");
+    // K~': new row indices in place
+    check(setup_rename(nnz, d_inv, h->ciT, s), "renumber K'");
+    // row vectors
+    for (double* v : {h->q, h->D1, h->b0}) {
+      check(setup_gather_rows(m, d_perm, v, t_row, s), "renumber rows");
+      check(hipMemcpyAsync(v, t_row, (size_t)m * 8, d2d, s), "renumber rows");
+    }
+    for (int8_t* v : {h->ineq, h->le, h->rt}) {
+      check(setup_gather_rows_i8(m, d_perm, v, t_row8, s), "renumber rows");
+      check(hipMemcpyAsync(v, t_row8, (size_t)m, d2d, s), "renumber rows");
+    }
+    check(hipStreamSynchronize(s), "renumber sync");
+  } catch (const HipFail&) {
+    for (void* p : tmp) (void)hipFree(p);
+    throw;
+  }
+  for (void* p : tmp) (void)hipFree(p);
+  h->rp_given = H.rp;
+  h->rp_dev = rp2;
+  h->rperm = std::move(perm);
+  H.rp = std::move(rp2);
+  H.ci = std::move(ci2);
+}
+
 // Iterate, average and output buffers and the constants of Params.
 static void alloc_iterates(pdlp_handle* h) {
   const int32_t m = h->m, n = h->n;
@@ -850,6 +957,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     double kmax;
     std::memcpy(&kmax, &hred[4], sizeof kmax);
     h->eta0 = kmax > 0.0 ? 1.0 / kmax : 1.0;
+    renumber_rows(h, H);
     // --- row-block partitions and (optionally) the column-panel layouts
     std::vector<int32_t> hrpT((size_t)n + 1);
     check(hipMemcpy(hrpT.data(), h->rpT, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
@@ -970,6 +1078,10 @@ extern "C" int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const doubl
   try {
     // x0 == NULL: zero start for x; y0 == NULL: zero start for y
     std::vector<double> zx((size_t)h->n, 0.0), zy((size_t)std::max(h->m, 1), 0.0);
+    if (y0 && !h->rperm.empty()) {
+      h->rows_to_dev(y0, zy.data());
+      y0 = zy.data();
+    }
     check(hipMemcpy(h->wx, x0 ? x0 : zx.data(), (size_t)h->n * 8, hipMemcpyHostToDevice), "upload x0");
     if (h->m) check(hipMemcpy(h->wy, y0 ? y0 : zy.data(), (size_t)h->m * 8, hipMemcpyHostToDevice), "upload y0");
   } catch (const HipFail& f) {
@@ -1114,6 +1226,17 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
   return PDLP_OK;
 }
 
+// A device vector over the rows, in the given row order.
+static void download_rows(const pdlp_handle* h, double* dst, const double* dev, const char* what) {
+  if (h->rperm.empty()) {
+    check(hipMemcpy(dst, dev, (size_t)h->m * 8, hipMemcpyDeviceToHost), what);
+    return;
+  }
+  std::vector<double> t((size_t)h->m);
+  check(hipMemcpy(t.data(), dev, (size_t)h->m * 8, hipMemcpyDeviceToHost), what);
+  h->rows_to_given(t.data(), dst);
+}
+
 extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* rc, pdlp_info* info) {
   if (!h) return PDLP_ERR_ARG;
   if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution on a batch handle (use the _batch entry points)");
@@ -1129,6 +1252,10 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
       check(hipMemcpy(lr.data(), h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
     } catch (const HipFail& f) {
       return fail(h, PDLP_ERR_HIP, hip_msg(f));
+    }
+    if (!h->rperm.empty()) {
+      std::vector<double> yd(yr);
+      h->rows_to_given(yd.data(), yr.data());
     }
     const int st = h->info.status;
     pdlp_info I = h->info;
@@ -1164,7 +1291,7 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
   }
   try {
     if (x) check(hipMemcpy(x, h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
-    if (y && h->m) check(hipMemcpy(y, h->yo, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y");
+    if (y && h->m) download_rows(h, y, h->yo, "download y");
     if (rc) check(hipMemcpy(rc, h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
   } catch (const HipFail& f) {
     return fail(h, PDLP_ERR_HIP, hip_msg(f));
@@ -1182,7 +1309,7 @@ extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pd
     DevState f;
     check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
     if (x_hat) check(hipMemcpy(x_hat, h->P.x[f.cur], (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x~");
-    if (y_hat && h->m) check(hipMemcpy(y_hat, h->P.y[f.cur], (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y~");
+    if (y_hat && h->m) download_rows(h, y_hat, h->P.y[f.cur], "download y~");
     if (st) {
       st->iterations = f.k;
       st->attempts = f.attempts;
@@ -1203,10 +1330,21 @@ extern "C" int pdlp_get_scaling(pdlp_handle* h, double* D1, double* D2, double* 
   if (!h) return PDLP_ERR_ARG;
   if (h->presolved) return fail(h, PDLP_ERR_UNSUPPORTED, "pdlp_get_scaling on a presolved handle (the scaling is the reduced LP's)");
   try {
-    if (D1 && h->m) check(hipMemcpy(D1, h->D1, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download D1");
+    if (D1 && h->m) download_rows(h, D1, h->D1, "download D1");
     if (D2) check(hipMemcpy(D2, h->D2, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download D2");
-    if (val_scaled && h->nnz)
-      check(hipMemcpy(val_scaled, h->val, (size_t)h->nnz * 8, hipMemcpyDeviceToHost), "download K~");
+    if (val_scaled && h->nnz) {
+      if (h->rperm.empty()) {
+        check(hipMemcpy(val_scaled, h->val, (size_t)h->nnz * 8, hipMemcpyDeviceToHost), "download K~");
+      } else {
+        // rows back to the given order
+        std::vector<double> vd((size_t)h->nnz);
+        check(hipMemcpy(vd.data(), h->val, (size_t)h->nnz * 8, hipMemcpyDeviceToHost), "download K~");
+        for (size_t r = 0; r < h->rperm.size(); ++r) {
+          const int32_t g0 = h->rp_given[(size_t)h->rperm[r]], d0 = h->rp_dev[r], L = h->rp_dev[r + 1] - d0;
+          std::memcpy(val_scaled + g0, vd.data() + d0, (size_t)L * 8);
+        }
+      }
+    }
   } catch (const HipFail& f) {
     return fail(h, PDLP_ERR_HIP, hip_msg(f));
   }

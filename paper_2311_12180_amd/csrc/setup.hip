@@ -139,6 +139,20 @@ __global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, const i
   }
 }
 
+// Row renumbering: K~' entries keep their place and get the new row index;
+// row vectors are gathered into the new order (new row r is old row perm[r]).
+__global__ void k_rename(int64_t nnz, const int32_t* __restrict__ inv, int32_t* __restrict__ ci) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    ci[e] = inv[ci[e]];
+}
+
+template <typename T>
+__global__ void k_gather_rows(int32_t m, const int32_t* __restrict__ perm, const T* __restrict__ src,
+                              T* __restrict__ dst) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x)
+    dst[r] = src[perm[r]];
+}
+
 __global__ void k_fill(int64_t n, double* __restrict__ a, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
@@ -265,6 +279,21 @@ hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s) {
 hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
                          int32_t* pci, double* pv, float* pvf, hipStream_t s) {
   if (nnz > 0) hipLaunchKernelGGL(k_permute, grid_for(nnz), dim3(256), 0, s, nnz, perm, ci, v, vf, pci, pv, pvf);
+  return hipGetLastError();
+}
+
+hipError_t setup_rename(int64_t nnz, const int32_t* inv, int32_t* ci, hipStream_t s) {
+  if (nnz > 0) hipLaunchKernelGGL(k_rename, grid_for(nnz), dim3(256), 0, s, nnz, inv, ci);
+  return hipGetLastError();
+}
+
+hipError_t setup_gather_rows(int32_t m, const int32_t* perm, const double* src, double* dst, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_gather_rows<double>, grid_for(m), dim3(256), 0, s, m, perm, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t setup_gather_rows_i8(int32_t m, const int32_t* perm, const int8_t* src, int8_t* dst, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_gather_rows<int8_t>, grid_for(m), dim3(256), 0, s, m, perm, src, dst);
   return hipGetLastError();
 }
 

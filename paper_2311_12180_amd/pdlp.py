@@ -59,7 +59,8 @@ class pdlp_options(C.Structure):
                 ("batch_grid", C.c_int32), ("spmv_layout_kt", C.c_int32),
                 ("batch_handoff", C.c_int32), ("handoff_streams", C.c_int32),
                 ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double), ("infeas_every", C.c_int32),
-                ("presolve", C.c_int32), ("restart_metric", C.c_int32)]
+                ("presolve", C.c_int32), ("restart_metric", C.c_int32),
+                ("row_order", C.c_int32)]
 
 
 class pdlp_info(C.Structure):

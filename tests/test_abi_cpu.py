@@ -135,6 +135,7 @@ def test_batch_rejects_bad_members_and_options(P):
                                     ([good], P.PDLP_ERR_ARG, "infeas_every", {"infeas_every": 0}),
                                     ([good], P.PDLP_ERR_ARG, "presolve", {"presolve": 2}),
                                     ([good], P.PDLP_ERR_ARG, "restart_metric", {"restart_metric": 2}),
+                                    ([good], P.PDLP_ERR_ARG, "row_order", {"row_order": 2}),
                                     ([good], P.PDLP_ERR_UNSUPPORTED, "batch handles", {"presolve": 1}),
                                     ([], P.PDLP_ERR_ARG, "count", {})]:
         with pytest.raises(P.PdlpError) as e:
