@@ -36,11 +36,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-STEP_SOURCES = ("pdlp_dev.h", "pdlp_ops.h", "kernels.hip")
+# the step kernels and the sources that lay out what they read (row order,
+# row blocks, column panels)
+STEP_SOURCES = ("pdlp_dev.h", "pdlp_ops.h", "kernels.hip", "setup.hip", "pdlp_api.cpp")
 
 
 def step_kernels_hash() -> str:
-    """sha256 prefix over the sources the single-LP step kernels are built from."""
+    """sha256 prefix over the sources the single-LP step kernels and their
+    matrix layout are built from."""
     import hashlib
     h = hashlib.sha256()
     for name in STEP_SOURCES:
@@ -52,8 +55,8 @@ def _traffic_from_profiles(kernel: str):
     """Bytes between L2 and the memory fabric per launch of step `kernel`
     (primal_step / dual_step) from the committed rocprofv3 counter summary
     (lines 'step <name> fetch_bytes <F> write_bytes <W>'), or None when there is
-    none or it was taken from a different kernel source (the summary records
-    the sha256 prefix of kernels.hip)."""
+    none or it was taken from different step-kernel or layout sources (the
+    summary records the sha256 prefix of STEP_SOURCES)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "step_kernels_skewed_1e6x2e6_traffic.txt")
     if not os.path.exists(path):
