@@ -323,7 +323,7 @@ int pdlp_get_solution_batch(pdlp_handle* h, int32_t idx, double* x, double* y, d
                             pdlp_info* info);
 
 /* Schedule of the persistent launch: lanes[2*count] (the sweep of each LP's
- * rows of K and of K': 0 = LDS-tiled row blocks of up to 2048 nonzeros, L > 0
+ * rows of K and of K': 0 = LDS-tiled row blocks of up to 4096 nonzeros, L > 0
  * = L lanes per row) and the number of workgroups; NULL to skip either. */
 int pdlp_batch_schedule(pdlp_handle* h, int32_t* lanes, int32_t* grid);
 

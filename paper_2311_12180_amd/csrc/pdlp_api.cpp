@@ -527,8 +527,9 @@ static double time_probe(pdlp_handle* h, int which, int reps) {
 
 // Layout of each matrix: the option's, or (spmv_layout = -1) the fastest of
 // row blocks, row blocks with XCD-contiguous ranges, and column panels (when
-// built), timed on plain products.  An alternative replaces row blocks only
-// when it is faster by more than 5 %, so close calls stay on the default.
+// built), each with one workgroup per block or a persistent grid, timed on
+// plain products.  The fastest candidate replaces plain row blocks only when
+// it is faster by more than 5 %, so close calls stay on the default.
 static void choose_layouts(pdlp_handle* h) {
   Params& P = h->P;
   double* pin = h->dalloc<double>((size_t)std::max(h->m, h->n));
@@ -563,7 +564,8 @@ static void choose_layouts(pdlp_handle* h) {
     set(0, 0, 0);
     if (h->nnz < (1 << 20)) continue;   // small problems: row blocks
     // candidates: (layout, remap) x (one workgroup per block, persistent grid)
-    double best = time_probe(h, which, 5);
+    const double base = time_probe(h, which, 5);
+    double best = INFINITY;
     int best_l = 0, best_r = 0, best_g = 0;
     const int cands[3][2] = {{0, 0}, {0, 1}, {1, 0}};
     for (const auto& c : cands) {
@@ -572,8 +574,12 @@ static void choose_layouts(pdlp_handle* h) {
         if (c[0] == 0 && c[1] == 0 && g == 0) continue;   // the baseline, timed above
         set(c[0], c[1], g);
         const double t = time_probe(h, which, 5);
-        if (t < 0.95 * best) { best = t; best_l = c[0]; best_r = c[1]; best_g = g; }
+        if (t < best) { best = t; best_l = c[0]; best_r = c[1]; best_g = g; }
       }
+    }
+    if (!(best < 0.95 * base)) {
+      best = base;
+      best_l = best_r = best_g = 0;
     }
     set(best_l, best_r, best_g);
     h->probe_ms[which] = best;

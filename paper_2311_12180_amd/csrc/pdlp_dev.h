@@ -11,7 +11,7 @@
 namespace pdlp {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
-constexpr int kTile = 2048;        // nonzeros staged in LDS per row block
+constexpr int kTile = 3072;        // nonzeros staged in LDS per row block (12 per thread)
 constexpr int kMaxRows = 1024;     // rows per row block
 constexpr int kElemBlocks = 2048;  // fixed grid of the row-wise kernels (deterministic partials)
 constexpr int kPanels = 8;         // column panels of the split layout = XCDs of the chip

@@ -38,7 +38,7 @@ def _long_row_lp(seed=0):
     rows, cols = [], []
     for i in range(m):
         if i in (3, 150):
-            L = 7000 if i == 3 else 2049
+            L = 7000 if i == 3 else 3073     # two tiles and a bit; one more than a tile (3072)
         elif i % 37 == 0:
             L = 0
         else:
