@@ -332,7 +332,8 @@ def main():
     # a step is one kernel (row blocks) or two (column panels: segment sums, then rows)
     names = {0: "{}<{}>", 1: "k_seg<{1}> + k_rows<{1}>", 2: "{}<{}> (XCD-contiguous blocks)"}
     lk, lt = info["layout_k"], info["layout_kt"]
-    kname = lambda lay, op: names[lay & 3].format("k_fused", op) + (" (persistent grid)" if lay & 4 else "")
+    kname = lambda lay, op: (names[lay & 3].format("k_fused", op) + (" (persistent grid)" if lay & 4 else "") +
+                             (" (6144-nonzero blocks)" if lay & 8 else ""))
     kern = {"primal_step": (ms_a, by_a, kname(lt, "PrimalOp")), "dual_step": (ms_b, by_b, kname(lk, "DualOp"))}
     dom = max(kern, key=lambda k: kern[k][0])
     ms_d, by_d, kname = kern[dom]

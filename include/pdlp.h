@@ -96,18 +96,21 @@ typedef struct {
   int32_t spmv_layout;        /* -1: chosen per matrix at create by timing plain products (default);
                                  0: row blocks; 1: column panels (one per XCD) with a second pass
                                  that adds each row's panel sums; 2: row blocks with contiguous
-                                 block ranges per XCD; 4, 5, 6: 0, 1, 2 with a persistent grid
-                                 (one workgroup per 8 waves of every CU, looping over the row
-                                 blocks).  The layout changes the order of floating-point
-                                 sums; fix it for bitwise reproducibility across handles.  This
-                                 field applies to K, and to K' unless spmv_layout_kt says otherwise */
+                                 block ranges per XCD; plus 4: a persistent grid (one workgroup
+                                 per 8 waves of every CU, looping over the row blocks); plus 8:
+                                 the step passes take blocks of 6144 nonzeros instead of 3072
+                                 (the evaluation passes keep 3072).  The timing at create tries
+                                 every combination on matrices with 2^20 nonzeros or more.  The
+                                 layout changes the order of floating-point sums; fix it for
+                                 bitwise reproducibility across handles.  This field applies to
+                                 K, and to K' unless spmv_layout_kt says otherwise */
   int32_t batch_lanes;        /* batch handles: how each LP's rows are swept.  0 = chosen per LP
                                  class by timing capped solves at pdlp_create_batch (default);
                                  -1 = LDS-tiled row blocks for every LP; 1..64 (a power of two) =
                                  that many lanes per row for every row */
   int32_t batch_grid;         /* batch handles: workgroups of the persistent launch, 0 = chosen by
                                  timing (default) */
-  int32_t spmv_layout_kt;     /* -2: K' follows spmv_layout (default); -1, 0, 1, 2: as spmv_layout,
+  int32_t spmv_layout_kt;     /* -2: K' follows spmv_layout (default); otherwise as spmv_layout,
                                  for K' alone */
   int32_t batch_handoff;      /* batch handles: an LP that has taken this many accepted steps stops
                                  in the persistent launch at its next evaluation (default 2048, 0 =
@@ -173,9 +176,9 @@ typedef struct {
   double omega, eta_hat;      /* primal weight and step size at exit */
   double setup_s;             /* pdlp_create: upload, transpose, scaling, layout choice */
   double solve_s;             /* pdlp_solve wall time */
-  int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout, plus 4 when
-                                   the create-time timing chose a persistent grid for the row-block
-                                   kernels); for an LP of a batch: its sweeps of K and K' (see
+  int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout: 0, 1, 2,
+                                   plus 4 for a persistent grid, plus 8 for the wide step tiles);
+                                   for an LP of a batch: its sweeps of K and K' (see
                                    pdlp_batch_schedule) */
   int64_t handoff_k;          /* an LP of a batch: accepted steps when the single-LP kernels took
                                  it over (0: it ended in the persistent launch) */

@@ -41,10 +41,11 @@ struct AccSize {
   static constexpr int RED = (Op::NACC > Op::NV ? Op::NACC : Op::NV) * (kBlock / 64);
 };
 
-// Fused layout: row blocks, epilogue in the same kernel.
-template <class Op, typename VT>
+// Fused layout: row blocks, epilogue in the same kernel.  TILE is the
+// matrix's tiling (the blocks hold at most TILE nonzeros, or one long row).
+template <class Op, typename VT, int TILE = kTile>
 __global__ __launch_bounds__(kBlock) void k_fused(Params p) {
-  __shared__ double lds[Op::NV * kTile];
+  __shared__ double lds[Op::NV * TILE];
   __shared__ double red[AccSize<Op>::RED];
   if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(Params p) {
     double acc[AccSize<Op>::N];
 #pragma unroll
     for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
-    spmv_block<Op::NV, VT>(
+    spmv_block<Op::NV, VT, kBlock, TILE>(
         M.rp, M.ci, pick<VT>(M.v, M.vf), M.blocks[b], lds, red, [&](int c, double* g) { op.gather(c, g); },
         [&](int r, const double* s) { op.epi(r, s, acc); });
     if constexpr (Op::NACC > 0) {
@@ -71,9 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_fused(Params p) {
 }
 
 // Panel layout, phase 1: segment sums of the blocks of panel blockIdx % 8.
-template <class Op, typename VT>
+template <class Op, typename VT, int TILE = kTile>
 __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
-  __shared__ double lds[Op::NV * kTile];
+  __shared__ double lds[Op::NV * TILE];
   __shared__ double red[Op::NV * (kBlock / 64)];
   if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
   double* __restrict__ part = S.part;
   const int32_t* __restrict__ dst = S.seg_dst;
   for (int i = blockIdx.x; i < S.nsblocks; i += gridDim.x) {
-    spmv_block<Op::NV, VT>(
+    spmv_block<Op::NV, VT, kBlock, TILE>(
         S.seg_ptr, S.pci, pick<VT>(S.pv, S.pvf), S.sblocks[i], lds, red,
         [&](int c, double* g) { op.gather(c, g); },
         [&](int s, const double* sums) {
@@ -135,8 +136,8 @@ __global__ __launch_bounds__(kDecideBlock) void k_decide(Params p) {
   if (threadIdx.x == 0 && st->restart_flag) st->restart_flag = 0;
   if (attempt_idle(st)) return;
   double r[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < p.KT.nred; i += kDecideBlock) r[0] += p.partA[i];
-  for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
+  for (int i = threadIdx.x; i < p.KTs.nred; i += kDecideBlock) r[0] += p.partA[i];
+  for (int i = threadIdx.x; i < p.Ks.nred; i += kDecideBlock) {
     r[1] += p.partB[2 * i];
     r[2] += p.partB[2 * i + 1];
   }
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(kDecideBlock) void k_decide(Params p) {
 // x-space part of the evaluation: flush the pending weight into the sum,
 // form x_bar = sum / sum_eta, and reduce c'x, c'x_bar, ||x - x0||^2, ||x_bar - x0||^2.
 __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
-  __shared__ double red[4 * 4];
+  __shared__ double red[4 * (kBlock / 64)];
   const DevState* st = p.st;
   if (eval_idle(st)) return;
   const int cur = st->cur, init = st->initial, pend = st->has_pending;
@@ -374,28 +375,39 @@ static inline int elem_grid(int n) {
   return g < 1 ? 1 : g;
 }
 
-// One pass of `Op` over its matrix in the matrix's layout.
-template <class Op, typename VT>
+// One pass of `Op` over its matrix in the matrix's layout, with the
+// kernels built for the tiling of M's blocks.
+template <class Op, typename VT, int TILE = kTile>
 static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
   if (M.layout == 0) {
     const int g = M.grid > 0 && M.grid < M.nblocks ? M.grid : M.nblocks;
-    hipLaunchKernelGGL((k_fused<Op, VT>), dim3(g), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((k_fused<Op, VT, TILE>), dim3(g), dim3(kBlock), 0, s, p);
   } else {
     const int g = M.grid > 0 && M.grid < M.pan.nsblocks ? M.grid : M.pan.nsblocks;
-    hipLaunchKernelGGL((k_seg<Op, VT>), dim3(g), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((k_seg<Op, VT, TILE>), dim3(g), dim3(kBlock), 0, s, p);
     hipLaunchKernelGGL((k_rows<Op>), dim3(M.rows_grid), dim3(kBlock), 0, s, p);
   }
 }
 
-void launch_primal(const Params& p, hipStream_t s) {
-  if (p.use_f32) launch_op<PrimalOp, float>(p, p.KT, s);
-  else launch_op<PrimalOp, double>(p, p.KT, s);
+// A step pass over a step view: the view replaces the
+// matrix in the kernels' parameters, and its tiling picks the kernels.
+template <class Op, int WHICH>
+static void launch_view(const Params& p, hipStream_t s) {
+  Params q = p;
+  DevCsr& M = WHICH ? q.KT : q.K;
+  M = WHICH ? p.KTs : p.Ks;
+  if (M.tile == kTileWide) {
+    if (q.use_f32) launch_op<Op, float, kTileWide>(q, M, s);
+    else launch_op<Op, double, kTileWide>(q, M, s);
+  } else {
+    if (q.use_f32) launch_op<Op, float>(q, M, s);
+    else launch_op<Op, double>(q, M, s);
+  }
 }
 
-void launch_dual(const Params& p, hipStream_t s) {
-  if (p.use_f32) launch_op<DualOp, float>(p, p.K, s);
-  else launch_op<DualOp, double>(p, p.K, s);
-}
+void launch_primal(const Params& p, hipStream_t s) { launch_view<PrimalOp, 1>(p, s); }
+
+void launch_dual(const Params& p, hipStream_t s) { launch_view<DualOp, 0>(p, s); }
 
 void launch_decide(const Params& p, hipStream_t s) {
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideBlock), 0, s, p);
@@ -431,17 +443,6 @@ void launch_init(const Params& p, const double* xs, const double* ys, hipStream_
 void launch_output(const Params& p, hipStream_t s) {
   launch_op<OutputOp, double>(p, p.KT, s);
   hipLaunchKernelGGL(k_output_y, dim3(elem_grid(p.m)), dim3(kBlock), 0, s, p);
-}
-
-void launch_probe(const Params& p, int which, hipStream_t s) {
-  const bool f = p.use_f32 != 0;
-  if (which == 0) {
-    if (f) launch_op<ProbeOp<0>, float>(p, p.K, s);
-    else launch_op<ProbeOp<0>, double>(p, p.K, s);
-  } else {
-    if (f) launch_op<ProbeOp<1>, float>(p, p.KT, s);
-    else launch_op<ProbeOp<1>, double>(p, p.KT, s);
-  }
 }
 
 void launch_set_limit(DevState* st, int status, hipStream_t s) {

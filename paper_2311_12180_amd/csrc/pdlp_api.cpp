@@ -27,7 +27,6 @@ void launch_decide(const Params& p, hipStream_t s);
 void launch_eval(const Params& p, hipStream_t s);
 void launch_init(const Params& p, const double* xs, const double* ys, hipStream_t s);
 void launch_output(const Params& p, hipStream_t s);
-void launch_probe(const Params& p, int which, hipStream_t s);
 void launch_set_limit(DevState* st, int status, hipStream_t s);
 void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s);
 int batch_occupancy(size_t lds_bytes);
@@ -115,7 +114,7 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
 // Column-panel layout (see PanelCsr), built on the host from the structure.
 struct HostPanels {
   std::vector<int32_t> seg_ptr, seg_dst, row_seg, perm;
-  std::vector<RowBlock> sblocks;
+  std::vector<RowBlock> sblocks, sblocks_wide;   // phase-1 blocks of kTile and of kTileWide nonzeros
 };
 
 HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int ncols, const int32_t* col_ptr) {
@@ -172,16 +171,19 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
   }
   H.seg_ptr[(size_t)nseg] = (int32_t)nnz;
   // phase-1 blocks of each panel, interleaved so that block i serves panel i % kPanels
-  std::vector<std::vector<RowBlock>> pb(kPanels);
-  size_t nbmax = 0;
-  for (int p = 0; p < kPanels; ++p) {
-    pb[p] = partition_rows(H.seg_ptr.data(), (int)seg_base[p], (int)(seg_base[p] + pseg[p]));
-    nbmax = std::max(nbmax, pb[p].size());
+  for (int tile : {kTile, kTileWide}) {
+    std::vector<std::vector<RowBlock>> pb(kPanels);
+    size_t nbmax = 0;
+    for (int p = 0; p < kPanels; ++p) {
+      pb[p] = partition_rows(H.seg_ptr.data(), (int)seg_base[p], (int)(seg_base[p] + pseg[p]), tile);
+      nbmax = std::max(nbmax, pb[p].size());
+    }
+    if (nbmax == 0) nbmax = 1;
+    std::vector<RowBlock>& sb = tile == kTile ? H.sblocks : H.sblocks_wide;
+    sb.assign(nbmax * kPanels, RowBlock{0, 0});
+    for (int p = 0; p < kPanels; ++p)
+      for (size_t j = 0; j < pb[p].size(); ++j) sb[j * kPanels + p] = pb[p][j];
   }
-  if (nbmax == 0) nbmax = 1;
-  H.sblocks.assign(nbmax * kPanels, RowBlock{0, 0});
-  for (int p = 0; p < kPanels; ++p)
-    for (size_t j = 0; j < pb[p].size(); ++j) H.sblocks[j * kPanels + p] = pb[p][j];
   return H;
 }
 
@@ -215,7 +217,13 @@ struct pdlp_handle {
   int slots_per_round = 0, rounds = 0;
   double eta0 = 1.0, omega0 = 1.0;
   double probe_ms[2] = {0.0, 0.0};
+  DevState* probe_st = nullptr;   // the private state of the layout timing
   int32_t persist_grid = 2048;   // persistent grid of the row-block kernels (CUs x 8, a multiple of 8)
+  // the kTileWide tilings of K and K' (row blocks, panel phase-1 blocks) a step view may take
+  const RowBlock* wide_blocks[2] = {nullptr, nullptr};
+  int32_t wide_nblocks[2] = {0, 0};
+  const RowBlock* wide_sblocks[2] = {nullptr, nullptr};
+  int32_t wide_nsblocks[2] = {0, 0};
   std::string err = "no error";
   bool solved = false;
   pdlp_info info{};
@@ -373,10 +381,11 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.trace < 0) return why = "trace must be >= 0", -1;
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
-  auto bad_layout = [](int v) { return v < -1 || v > 6 || v == 3; };
-  if (bad_layout(o.spmv_layout)) return why = "spmv_layout must be -1, 0, 1, 2, 4, 5 or 6", -1;
+  auto bad_layout = [](int v) { return v < -1 || v > 14 || (v >= 0 && (v & 3) == 3); };
+  if (bad_layout(o.spmv_layout))
+    return why = "spmv_layout must be -1 or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles)", -1;
   if (o.spmv_layout_kt != -2 && bad_layout(o.spmv_layout_kt))
-    return why = "spmv_layout_kt must be -2, -1, 0, 1, 2, 4, 5 or 6", -1;
+    return why = "spmv_layout_kt must be -2, -1 or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles)", -1;
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
@@ -475,8 +484,8 @@ static int elem_grid(int n) {
 }
 
 // Device copy of a column-panel layout; the matrix keeps layout 0 until chosen.
-static void upload_panels(pdlp_handle* h, DevCsr& M, const HostPanels& H, int64_t nnz, const int32_t* ci,
-                          const double* v, const float* vf) {
+static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels& H, int64_t nnz,
+                          const int32_t* ci, const double* v, const float* vf) {
   hipStream_t s = h->stream;
   const hipMemcpyKind kind = hipMemcpyHostToDevice;
   PanelCsr& S = M.pan;
@@ -494,6 +503,11 @@ static void upload_panels(pdlp_handle* h, DevCsr& M, const HostPanels& H, int64_
   if (!H.seg_dst.empty()) check(hipMemcpyAsync(seg_dst, H.seg_dst.data(), H.seg_dst.size() * 4, kind, s), "upload panels");
   check(hipMemcpyAsync(row_seg, H.row_seg.data(), H.row_seg.size() * 4, kind, s), "upload panels");
   check(hipMemcpyAsync(sb, H.sblocks.data(), H.sblocks.size() * sizeof(RowBlock), kind, s), "upload panels");
+  RowBlock* sbw = h->dalloc<RowBlock>(H.sblocks_wide.size());
+  check(hipMemcpyAsync(sbw, H.sblocks_wide.data(), H.sblocks_wide.size() * sizeof(RowBlock), kind, s),
+        "upload panels");
+  h->wide_sblocks[which] = sbw;
+  h->wide_nsblocks[which] = (int32_t)H.sblocks_wide.size();
   if (nnz) check(hipMemcpyAsync(perm, H.perm.data(), (size_t)nnz * 4, kind, s), "upload panels");
   check(setup_permute(nnz, perm, ci, v, vf, pci, pv, pvf, s), "permute panels");
   check(hipStreamSynchronize(s), "panels sync");
@@ -508,14 +522,27 @@ static void upload_panels(pdlp_handle* h, DevCsr& M, const HostPanels& H, int64_
 }
 
 // Mean duration (ms) of a plain product pass over K (which = 0) or K' (1).
+// Mean duration (ms) of the step pass over K (which = 0, the dual step) or K'
+// (1, the primal step) in the current layout, on a private state: current
+// buffer 0, a tiny step, a pending weight of 0.  The passes then read the
+// zero start buffers and write only the next-iterate buffers, dx, the
+// partials and +0 into the running sums, all of which the first step of a
+// solve overwrites before reading them.
 static double time_probe(pdlp_handle* h, int which, int reps) {
   hipStream_t s = h->stream;
+  Params T = h->P;
+  T.st = h->probe_st;
+  T.tr = Trace{};
+  auto pass = [&]() {
+    if (which) launch_primal(T, s);
+    else launch_dual(T, s);
+  };
   hipEvent_t a, b;
   check(hipEventCreate(&a), "hipEventCreate");
   check(hipEventCreate(&b), "hipEventCreate");
-  launch_probe(h->P, which, s);
+  pass();
   check(hipEventRecord(a, s), "event");
-  for (int i = 0; i < reps; ++i) launch_probe(h->P, which, s);
+  for (int i = 0; i < reps; ++i) pass();
   check(hipEventRecord(b, s), "event");
   check(hipEventSynchronize(b), "event sync");
   float ms = 0.f;
@@ -527,61 +554,90 @@ static double time_probe(pdlp_handle* h, int which, int reps) {
 
 // Layout of each matrix: the option's, or (spmv_layout = -1) the fastest of
 // row blocks, row blocks with XCD-contiguous ranges, and column panels (when
-// built), each with one workgroup per block or a persistent grid, timed on
-// plain products.  The fastest candidate replaces plain row blocks only when
-// it is faster by more than 5 %, so close calls stay on the default.
+// built), each with one workgroup per block or a persistent grid, and for the
+// step passes each with kTile or kTileWide nonzeros per block, timed on the
+// step passes themselves.  A candidate replaces the best so far only when
+// faster by more than 2 %, and plain row blocks of kTile only when faster by
+// more than 5 %, so close calls keep the earlier choice (timings move a few
+// percent from run to run; the choice changes the order of sums).  The
+// evaluation passes take the chosen layout with kTile blocks.
 static void choose_layouts(pdlp_handle* h) {
   Params& P = h->P;
-  double* pin = h->dalloc<double>((size_t)std::max(h->m, h->n));
-  double* pout = h->dalloc<double>((size_t)std::max(h->m, h->n));
-  check(setup_fill(std::max(h->m, h->n), pin, 1.0, h->stream), "probe fill");
-  P.probe_in = pin;
-  P.probe_out = pout;
-  for (int which = 0; which < 2; ++which) {
-    DevCsr& M = which ? P.KT : P.K;
+  {
+    DevState z;
+    std::memset(&z, 0, sizeof z);
+    z.eta = 1e-6;
+    z.omega = 1.0;
+    z.has_pending = 1;
+    h->probe_st = h->dalloc<DevState>(1);
+    check(hipMemcpyAsync(h->probe_st, &z, sizeof z, hipMemcpyHostToDevice, h->stream), "probe state");
+  }
+  // the primal pass first: the dual pass gathers its dx
+  for (int which = 1; which >= 0; --which) {
+    DevCsr& M = which ? P.KT : P.K;     // the evaluation passes' view
+    DevCsr& V = which ? P.KTs : P.Ks;   // the step passes' view
     const int mode = (which == 1 && h->opt.spmv_layout_kt != -2) ? h->opt.spmv_layout_kt : h->opt.spmv_layout;
     const bool has_pan = M.pan.seg_ptr != nullptr;
     // persistent grid: at most CUs x 8 workgroups (a multiple of 8, keeping
     // each workgroup on one XCD), each taking about four blocks or more
-    auto pgrid = [&](int layout) {
-      const int nb = layout == 1 ? M.pan.nsblocks : M.nblocks;
+    auto pgrid = [&](int nb) {
       const int want = ((nb + 3) / 4 + 7) / 8 * 8;
       return std::max(8, std::min(h->persist_grid, want));
     };
-    auto set = [&](int layout, int remap, int grid) {
+    auto set = [&](int layout, int remap, int grid, int tile) {
       M.layout = layout;
       M.remap = remap;
-      M.grid = grid ? pgrid(layout) : 0;
+      M.grid = grid ? pgrid(layout == 1 ? M.pan.nsblocks : M.nblocks) : 0;
       M.nred = layout == 1 ? M.rows_grid : M.nblocks;
+      V = M;
+      if (tile == kTileWide) {
+        V.tile = kTileWide;
+        V.blocks = h->wide_blocks[which];
+        V.nblocks = h->wide_nblocks[which];
+        if (layout == 1) {
+          V.pan.sblocks = h->wide_sblocks[which];
+          V.pan.nsblocks = h->wide_nsblocks[which];
+        }
+        V.grid = grid ? pgrid(layout == 1 ? V.pan.nsblocks : V.nblocks) : 0;
+        V.nred = layout == 1 ? V.rows_grid : V.nblocks;
+      }
     };
-    if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid
-      const int g = (mode & 4) ? 1 : 0;
-      if ((mode & 3) == 0) set(0, 0, g);
-      else if ((mode & 3) == 2) set(0, 1, g);
-      else set(has_pan ? 1 : 0, 0, g);
+    if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid, bit 3 the wide step tiles
+      const int g = (mode & 4) ? 1 : 0, t = (mode & 8) ? kTileWide : kTile;
+      if ((mode & 3) == 0) set(0, 0, g, t);
+      else if ((mode & 3) == 2) set(0, 1, g, t);
+      else set(has_pan ? 1 : 0, 0, g, t);
       continue;
     }
-    set(0, 0, 0);
+    set(0, 0, 0, kTile);
     if (h->nnz < (1 << 20)) continue;   // small problems: row blocks
-    // candidates: (layout, remap) x (one workgroup per block, persistent grid)
-    const double base = time_probe(h, which, 5);
+    const double base = time_probe(h, which, 6);
     double best = INFINITY;
-    int best_l = 0, best_r = 0, best_g = 0;
+    int best_l = 0, best_r = 0, best_g = 0, best_t = kTile;
     const int cands[3][2] = {{0, 0}, {0, 1}, {1, 0}};
-    for (const auto& c : cands) {
-      if (c[0] == 1 && !has_pan) continue;
-      for (int g : {0, 1}) {
-        if (c[0] == 0 && c[1] == 0 && g == 0) continue;   // the baseline, timed above
-        set(c[0], c[1], g);
-        const double t = time_probe(h, which, 5);
-        if (t < best) { best = t; best_l = c[0]; best_r = c[1]; best_g = g; }
+    for (int tile : {kTile, kTileWide}) {
+      for (const auto& c : cands) {
+        if (c[0] == 1 && !has_pan) continue;
+        for (int g : {0, 1}) {
+          if (tile == kTile && c[0] == 0 && c[1] == 0 && g == 0) continue;   // the baseline, timed above
+          set(c[0], c[1], g, tile);
+          const double t = time_probe(h, which, 6);
+          if (t < 0.98 * best) {
+            best = t;
+            best_l = c[0];
+            best_r = c[1];
+            best_g = g;
+            best_t = tile;
+          }
+        }
       }
     }
     if (!(best < 0.95 * base)) {
       best = base;
       best_l = best_r = best_g = 0;
+      best_t = kTile;
     }
-    set(best_l, best_r, best_g);
+    set(best_l, best_r, best_g, best_t);
     h->probe_ms[which] = best;
   }
 }
@@ -973,6 +1029,15 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     RowBlock* dbt = h->dalloc<RowBlock>(bt.size());
     check(hipMemcpyAsync(dbk, bk.data(), bk.size() * sizeof(RowBlock), kind, s), "upload blocks");
     check(hipMemcpyAsync(dbt, bt.data(), bt.size() * sizeof(RowBlock), kind, s), "upload blocks");
+    // the wider tiling a step pass may take (chosen with the layout)
+    for (int which = 0; which < 2; ++which) {
+      std::vector<RowBlock> w = partition_rows(which ? hrpT.data() : H.rp.data(), 0, which ? n : m, kTileWide);
+      if (w.empty()) w.push_back(RowBlock{0, 0});
+      RowBlock* dw = h->dalloc<RowBlock>(w.size());
+      check(hipMemcpyAsync(dw, w.data(), w.size() * sizeof(RowBlock), kind, s), "upload blocks");
+      h->wide_blocks[which] = dw;
+      h->wide_nblocks[which] = (int32_t)w.size();
+    }
     Params& P = h->P;
     P.K = DevCsr{h->rp, h->ci, h->val, h->valf, dbk, (int32_t)bk.size(), m, 0, 0, 0, elem_grid(m), 0, PanelCsr{}};
     P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, dbt, (int32_t)bt.size(), n, 0, 0, 0, elem_grid(n), 0,
@@ -986,18 +1051,21 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
       std::vector<int32_t> hciT;
       if (want_k) {
         HostPanels HP = build_panels(H.rp.data(), H.ci.data(), m, n, hrpT.data());
-        upload_panels(h, P.K, HP, nnz, h->ci, h->val, h->valf);
+        upload_panels(h, 0, P.K, HP, nnz, h->ci, h->val, h->valf);
       }
       if (want_kt) {
         hciT.resize((size_t)std::max<int64_t>(nnz, 1));
         if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
         HostPanels HP = build_panels(hrpT.data(), hciT.data(), n, m, H.rp.data());
-        upload_panels(h, P.KT, HP, nnz, h->ciT, h->valT, h->valTf);
+        upload_panels(h, 1, P.KT, HP, nnz, h->ciT, h->valT, h->valTf);
       }
     }
+    P.Ks = P.K;
+    P.KTs = P.KT;
     alloc_iterates(h);
-    const size_t redk = std::max<size_t>(bk.size(), (size_t)P.K.rows_grid);
-    const size_t redt = std::max<size_t>(bt.size(), (size_t)P.KT.rows_grid);
+    // partials: one per block of either tiling, or per workgroup of the row pass
+    const size_t redk = std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid});
+    const size_t redt = std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid});
     P.partA = h->dalloc<double>(redt);
     P.partB = h->dalloc<double>(2 * redk);
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
@@ -1141,8 +1209,10 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.eta_hat = f->eta_hat;
   I.setup_s = h->setup_s;
   I.solve_s = now_s() - t0;
-  I.layout_k = (h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0)) + (h->P.K.grid > 0 ? 4 : 0);
-  I.layout_kt = (h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0)) + (h->P.KT.grid > 0 ? 4 : 0);
+  I.layout_k = (h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0)) + (h->P.K.grid > 0 ? 4 : 0) +
+                (h->P.Ks.tile == kTileWide ? 8 : 0);
+  I.layout_kt = (h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0)) + (h->P.KT.grid > 0 ? 4 : 0) +
+                (h->P.KTs.tile == kTileWide ? 8 : 0);
   I.ray_source = f->ray_src;
   I.ray_obj = f->ray_obj;
   I.ray_res = f->ray_res;
@@ -1669,6 +1739,8 @@ extern "C" int pdlp_create_batch(const pdlp_problem* ps, int32_t count, const pd
     Params& P = h->P;
     P.K = DevCsr{h->rp, h->ci, h->val, h->valf, nullptr, 0, h->m, 0, 0, 0, 0, 0, PanelCsr{}};
     P.KT = DevCsr{h->rpT, h->ciT, h->valT, h->valTf, nullptr, 0, h->n, 0, 0, 0, 0, 0, PanelCsr{}};
+    P.Ks = P.K;
+    P.KTs = P.KT;
     alloc_iterates(h);
     P.st = nullptr;
     h->bst = h->dalloc<DevState>((size_t)count);
@@ -1842,6 +1914,9 @@ static Params handoff_params(const pdlp_handle* h, int32_t b, const pdlp_handle:
   sp.KT.nrows = sp.n;
   sp.KT.layout = sp.KT.remap = sp.KT.grid = 0;
   sp.KT.rows_grid = elem_grid(sp.n);
+  sp.K.tile = sp.KT.tile = 0;   // the kTile blocks above, for every pass
+  sp.Ks = sp.K;
+  sp.KTs = sp.KT;
   sp.partA = L.pa;
   sp.partB = L.pb;
   sp.partE0 = L.pe0;

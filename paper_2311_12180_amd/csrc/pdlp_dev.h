@@ -12,6 +12,7 @@ namespace pdlp {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wavefronts of 64)
 constexpr int kTile = 3072;        // nonzeros staged in LDS per row block (12 per thread)
+constexpr int kTileWide = 6144;    // the wider tiling a step pass may take (24 per thread)
 constexpr int kMaxRows = 1024;     // rows per row block
 constexpr int kElemBlocks = 2048;  // fixed grid of the row-wise kernels (deterministic partials)
 constexpr int kPanels = 8;         // column panels of the split layout = XCDs of the chip
@@ -63,6 +64,7 @@ struct DevCsr {
   int32_t grid;           // grid of the row-block (phase-1) kernels: 0 = one workgroup per block,
                           // else a persistent grid (a multiple of 8) looping over the blocks
   PanelCsr pan;
+  int32_t tile;           // nonzeros per block of `blocks` and `pan.sblocks`: 0 = kTile, or kTileWide
 };
 
 // Solver state in device memory.  The first 16 bytes are the status word the
@@ -116,6 +118,9 @@ struct Trace {
 struct Params {
   DevCsr K;     // m rows
   DevCsr KT;    // n rows
+  // the views the step passes take of K and K': the
+  // same arrays, with a row-block tiling of their own (kTile or kTileWide)
+  DevCsr Ks, KTs;
   int32_t m, n;
   int32_t use_f32;
   int32_t pad0;
@@ -137,8 +142,6 @@ struct Params {
   const double* D1; const double* D2;
   // outputs of the last solve (user orientation)
   double* xo; double* yo; double* rco;
-  // probe vectors of the layout tuner
-  const double* probe_in; double* probe_out;
   // one partial (NV doubles) per workgroup, added in order by the decision kernels
   double* partA;          // ||dx||^2
   double* partB;          // ||dy||^2, dy'K~dx

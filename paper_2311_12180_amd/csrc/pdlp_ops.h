@@ -573,20 +573,6 @@ struct OutputOp {
   }
 };
 
-// Plain products for the layout tuner: out = K~ in (ProbeK) or K~' in (ProbeKT).
-template <int WHICH>
-struct ProbeOp {
-  static constexpr int NV = 1, NACC = 0;
-  __device__ static bool idle(const Params&, const DevState*) { return false; }
-  __device__ static const DevCsr& mat(const Params& p) { return WHICH ? p.KT : p.K; }
-  __device__ static double* part(const Params&) { return nullptr; }
-  const double* __restrict__ in;
-  double* __restrict__ out;
-  __device__ ProbeOp(const Params& p, const DevState*) : in(p.probe_in), out(p.probe_out) {}
-  __device__ void gather(int j, double* g) const { g[0] = in[j]; }
-  __device__ void epi(int i, const double* s, double*) const { out[i] = s[0]; }
-};
-
 
 // ---------------------------------------------------------------------------- decisions
 

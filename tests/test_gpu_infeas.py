@@ -139,7 +139,7 @@ def test_certificates_match_oracle(P, orc, kind, arg, every):
         assert d <= max(1e-8, 100 * spread), (d, spread)
 
 
-@pytest.mark.parametrize("layout,prec", [(1, 0), (2, 0), (0, 1)])
+@pytest.mark.parametrize("layout,prec", [(1, 0), (2, 0), (0, 1), (9, 1)])
 def test_every_layout_and_fp32_matrix(P, orc, layout, prec):
     """Column panels (two-phase kernels), XCD-remapped row blocks and the
     FP32 matrix compute the same certificates."""

@@ -142,12 +142,12 @@ def test_trajectory_matches_oracle(P, orc, name, period, kmax):
 
 
 @pytest.mark.parametrize("name", ["random_1000x2000", "skewed_3000x6000", "long_rows", "transport_30x40"])
-@pytest.mark.parametrize("layout", [1, 2, 4, 5, 6])
+@pytest.mark.parametrize("layout", [1, 2, 4, 5, 6, 8, 9, 13])
 def test_layouts_match_oracle(P, orc, name, layout):
-    """Column panels (1), XCD-contiguous row blocks (2) and their persistent-grid
-    forms (4, 5, 6) follow the oracle's
-    trajectory like the default layout: same decisions, iterates within the
-    rounding-order bar, over 100 accepted steps."""
+    """Column panels (1), XCD-contiguous row blocks (2), their persistent-grid
+    forms (4, 5, 6) and the step passes on 6144-nonzero blocks (8, 9, 13)
+    follow the oracle's trajectory like the default layout: same decisions,
+    iterates within the rounding-order bar, over 100 accepted steps."""
     p = PROBLEMS[name]()
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64)
     h = P.pdlp_create(p, time_limit_s=60.0, trace=4096, spmv_layout=layout, **opts)
