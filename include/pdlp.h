@@ -93,7 +93,7 @@ typedef struct {
   int32_t poll_every;         /* 4: graph launches between two reads of the 8-byte status word */
   int32_t graph;              /* 1: the inner loop is a captured hipGraph; 0: the same kernels
                                  launched one by one (for callers that cannot use graphs) */
-  int32_t spmv_layout;        /* -1: chosen per matrix at create by timing plain products (default);
+  int32_t spmv_layout;        /* -1: chosen per matrix at create by timing the step passes (default);
                                  0: row blocks; 1: column panels (one per XCD) with a second pass
                                  that adds each row's panel sums; 2: row blocks with contiguous
                                  block ranges per XCD; plus 4: a persistent grid (one workgroup

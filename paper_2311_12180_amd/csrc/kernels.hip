@@ -389,8 +389,8 @@ static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
   }
 }
 
-// A step pass over a step view: the view replaces the
-// matrix in the kernels' parameters, and its tiling picks the kernels.
+// A step pass over a step view: the view replaces the matrix in the kernels'
+// parameters, and its tiling picks the kernels.
 template <class Op, int WHICH>
 static void launch_view(const Params& p, hipStream_t s) {
   Params q = p;

@@ -521,7 +521,6 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
   S.part = h->dalloc<double>(2 * (size_t)std::max(S.nseg, 1));
 }
 
-// Mean duration (ms) of a plain product pass over K (which = 0) or K' (1).
 // Mean duration (ms) of the step pass over K (which = 0, the dual step) or K'
 // (1, the primal step) in the current layout, on a private state: current
 // buffer 0, a tiny step, a pending weight of 0.  The passes then read the
