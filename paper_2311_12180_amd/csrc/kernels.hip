@@ -80,15 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_seg(Params p) {
   const Op op(p, p.st);
   const PanelCsr& S = Op::mat(p).pan;
   double* __restrict__ part = S.part;
-  const int32_t* __restrict__ dst = S.seg_dst;
   for (int i = blockIdx.x; i < S.nsblocks; i += gridDim.x) {
     spmv_block<Op::NV, VT, kBlock, TILE>(
         S.seg_ptr, S.pci, pick<VT>(S.pv, S.pvf), S.sblocks[i], lds, red,
         [&](int c, double* g) { op.gather(c, g); },
         [&](int s, const double* sums) {
-          const int d = dst[s];
 #pragma unroll
-          for (int k = 0; k < Op::NV; ++k) part[Op::NV * d + k] = sums[k];
+          for (int k = 0; k < Op::NV; ++k) part[Op::NV * s + k] = sums[k];
         });
     __syncthreads();   // the next block reuses lds
   }
@@ -111,8 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_rows(Params p) {
 #pragma unroll
     for (int k = 0; k < Op::NV; ++k) s[k] = 0.0;
     for (int q = S.row_seg[r]; q < S.row_seg[r + 1]; ++q) {
+      const int g = S.slot_seg[q];
 #pragma unroll
-      for (int k = 0; k < Op::NV; ++k) s[k] += S.part[Op::NV * q + k];
+      for (int k = 0; k < Op::NV; ++k) s[k] += S.part[Op::NV * g + k];
     }
     op.epi(r, s, acc);
   }

@@ -113,7 +113,7 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int nrows) {
 
 // Column-panel layout (see PanelCsr), built on the host from the structure.
 struct HostPanels {
-  std::vector<int32_t> seg_ptr, seg_dst, row_seg, perm;
+  std::vector<int32_t> seg_ptr, slot_seg, row_seg, perm;
   std::vector<RowBlock> sblocks, sblocks_wide;   // phase-1 blocks of kTile and of kTileWide nonzeros
 };
 
@@ -154,7 +154,7 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
   }
   std::vector<int64_t> seg_base(seg);
   H.seg_ptr.assign((size_t)nseg + 1, 0);
-  H.seg_dst.assign((size_t)nseg, 0);
+  H.slot_seg.assign((size_t)nseg, 0);
   H.perm.assign((size_t)nnz, 0);
   std::vector<int32_t> last(kPanels, -1);
   for (int r = 0; r < nrows; ++r) {
@@ -163,7 +163,8 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
       if (last[p] != r) {
         const int64_t sp = seg[p]++;
         H.seg_ptr[(size_t)sp] = (int32_t)ent[p];
-        H.seg_dst[(size_t)sp] = H.row_seg[(size_t)r] + __builtin_popcount(mask[(size_t)r] & ((1u << p) - 1u));
+        H.slot_seg[(size_t)(H.row_seg[(size_t)r] + __builtin_popcount(mask[(size_t)r] & ((1u << p) - 1u)))] =
+            (int32_t)sp;
         last[p] = r;
       }
       H.perm[(size_t)ent[p]++] = e;
@@ -489,10 +490,10 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
   hipStream_t s = h->stream;
   const hipMemcpyKind kind = hipMemcpyHostToDevice;
   PanelCsr& S = M.pan;
-  S.nseg = (int32_t)H.seg_dst.size();
+  S.nseg = (int32_t)H.slot_seg.size();
   S.nsblocks = (int32_t)H.sblocks.size();
   int32_t* seg_ptr = h->dalloc<int32_t>(H.seg_ptr.size());
-  int32_t* seg_dst = h->dalloc<int32_t>(H.seg_dst.size());
+  int32_t* slot_seg = h->dalloc<int32_t>(H.slot_seg.size());
   int32_t* row_seg = h->dalloc<int32_t>(H.row_seg.size());
   RowBlock* sb = h->dalloc<RowBlock>(H.sblocks.size());
   int32_t* perm = h->dalloc<int32_t>((size_t)nnz);
@@ -500,7 +501,8 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
   double* pv = h->dalloc<double>((size_t)nnz);
   float* pvf = vf ? h->dalloc<float>((size_t)nnz) : nullptr;
   check(hipMemcpyAsync(seg_ptr, H.seg_ptr.data(), H.seg_ptr.size() * 4, kind, s), "upload panels");
-  if (!H.seg_dst.empty()) check(hipMemcpyAsync(seg_dst, H.seg_dst.data(), H.seg_dst.size() * 4, kind, s), "upload panels");
+  if (!H.slot_seg.empty())
+    check(hipMemcpyAsync(slot_seg, H.slot_seg.data(), H.slot_seg.size() * 4, kind, s), "upload panels");
   check(hipMemcpyAsync(row_seg, H.row_seg.data(), H.row_seg.size() * 4, kind, s), "upload panels");
   check(hipMemcpyAsync(sb, H.sblocks.data(), H.sblocks.size() * sizeof(RowBlock), kind, s), "upload panels");
   RowBlock* sbw = h->dalloc<RowBlock>(H.sblocks_wide.size());
@@ -512,7 +514,7 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
   check(setup_permute(nnz, perm, ci, v, vf, pci, pv, pvf, s), "permute panels");
   check(hipStreamSynchronize(s), "panels sync");
   S.seg_ptr = seg_ptr;
-  S.seg_dst = seg_dst;
+  S.slot_seg = slot_seg;
   S.row_seg = row_seg;
   S.pci = pci;
   S.pv = pv;

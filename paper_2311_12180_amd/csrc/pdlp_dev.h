@@ -40,13 +40,14 @@ struct PanelCsr {
   int32_t nseg;
   int32_t nsblocks;
   const int32_t* seg_ptr;   // [nseg+1] start of each segment in pci / pv (panel-major)
-  const int32_t* seg_dst;   // [nseg]   row-major index of the segment (its partial slot)
-  const int32_t* row_seg;   // [nrows+1] row r's partial slots are [row_seg[r], row_seg[r+1])
+  const int32_t* slot_seg;  // [nseg]   segment of each row-major slot
+  const int32_t* row_seg;   // [nrows+1] row r's slots are [row_seg[r], row_seg[r+1]), in panel order
   const int32_t* pci;       // [nnz] column indices in segment order
   const double* pv;         // [nnz] FP64 values in segment order
   const float* pvf;         // [nnz] FP32 values in segment order (nullptr unless FP32 steps)
   const RowBlock* sblocks;  // [nsblocks] phase-1 blocks (rows of the segment "matrix")
-  double* part;             // [2 * nseg] segment sums, row-major
+  double* part;             // [2 * nseg] segment sums in segment (panel-major) order, so that each
+                            // workgroup's stores are contiguous and stay on its own XCD
 };
 
 struct DevCsr {
