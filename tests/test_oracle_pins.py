@@ -188,6 +188,74 @@ def test_adaptive_step_worked_example(orc, cval):
     assert r.info["iterations"] == 3 and r.info["attempts"] == 4
 
 
+def _golden_env(g):
+    env = {"__builtins__": {}, "inf": math.inf, "abs": abs, "min": min, "sqrt": math.sqrt, "exp": math.exp,
+           "log": math.log}
+    for line in g["defs"]:
+        k, v = line.split("=", 1)
+        env[k.strip()] = eval(v, env)
+    return env
+
+
+def check_evaluation_golden(orc, case):
+    """Compare an oracle (module with solve()) with case A or B of
+    tests/golden/evaluation_restart_1d.txt; raises AssertionError on a
+    mismatch."""
+    import os
+    g = read_golden(os.path.join(os.path.dirname(__file__), "golden", "evaluation_restart_1d.txt"))
+    env = _golden_env(g)
+    for line in g["checks"]:
+        assert eval(line, env), line
+    opts = {k.strip(): int(v) for k, v in (s.split("=", 1) for s in g[f"{case}.options"])}
+    p = lpgen.from_dense([[1.0]], [2.0], [1.0], [0.0], [math.inf], [lpgen.ROW_GE])
+    r = orc.solve(p, eps_rel=0.0, detect_infeas=0, trace_cap=16, **opts)
+    ev = lambda s: eval(s, env)
+    att = g[f"{case}.attempts"]
+    assert len(r.trace["att_k"]) == len(att)
+    for i, line in enumerate(att):
+        k, eta, etabar, acc = [s.strip() for s in line.split(",")]
+        assert r.trace["att_k"][i] == int(k)
+        assert r.trace["att_eta"][i] == pytest.approx(ev(eta), rel=1e-13)
+        eb = ev(etabar)
+        if math.isinf(eb):
+            assert math.isinf(r.trace["att_etabar"][i])
+        else:
+            assert r.trace["att_etabar"][i] == pytest.approx(eb, rel=1e-12)
+        assert r.trace["att_acc"][i] == int(acc)
+    evs = g[f"{case}.evaluations"]
+    assert len(r.trace["ev_k"]) == len(evs)
+    for i, line in enumerate(evs):
+        k, kc, ka, cand, reason, om = [s.strip() for s in line.split(",")]
+        assert r.trace["ev_k"][i] == int(k)
+        assert r.trace["ev_kkt_cur"][i] == pytest.approx(ev(kc), rel=1e-13)
+        assert r.trace["ev_kkt_avg"][i] == pytest.approx(ev(ka), rel=1e-13)
+        assert r.trace["ev_cand"][i] == int(cand)
+        assert r.trace["ev_reason"][i] == int(reason)
+        assert r.trace["ev_omega"][i] == pytest.approx(ev(om), rel=1e-14)
+    fin = {k.strip(): ev(v) for k, v in (s.split("=", 1) for s in g[f"{case}.final"])}
+    assert r.x_hat[0] == pytest.approx(fin["x_hat"], rel=1e-12)
+    assert r.y_hat[0] == pytest.approx(fin["y_hat"], rel=1e-12)
+    for key in ("eta_hat", "sum_eta", "omega", "kkt0"):
+        assert r.info[key] == pytest.approx(fin[key], rel=1e-12), key
+    for key in ("restarts", "iterations", "attempts"):
+        assert r.info[key] == fin[key], key
+    assert r.status == "ITER_LIMIT"
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_evaluation_and_restart_worked_example(orc, case):
+    """Hand-derived evaluation of Algorithm 1 on min 2x, x >= 1, x >= 0
+    (tests/golden/evaluation_restart_1d.txt): the step-size-weighted average,
+    KKT_omega with the omega^2 weights of eq. (kkt) for both iterates, the
+    Section 3.4 candidate and criterion, the Section 2.2 primal weight update
+    (case A) and its eps_zero guard (case B), KKT_0 recomputed with the new
+    weight, and the next step taken from the restart point with that weight.
+    tests/test_oracle_mutants.py shows that a uniform average, omega in place
+    of omega^2, an inverted candidate and KKT_0 kept at the old weight each
+    fail this check."""
+    check_evaluation_golden(orc, case)
+
+
 def test_step_bound_exceeds_inverse_spectral_norm(orc):
     """eta_bar = ||dz||_w^2 / (2|dy'K dx|) >= 1/||K||_2 for any dz (AM-GM and
     Cauchy-Schwarz), and every accepted step satisfies eta <= eta_bar."""
