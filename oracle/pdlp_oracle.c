@@ -59,9 +59,10 @@
  *     linear in d = zh - z with gradient g = (K'y - c, q - Kx); its maximiser
  *     is d(lam) = proj_{Z - z}(W^-1 g / lam), W = diag(omega, 1/omega), for the
  *     lam at which ||d(lam)||_omega = r (or the box corner when the ball does
- *     not bind).  lam is found in log space between hi = ||W^-1 g||_omega / r
- *     (where ||d|| <= r) and lo = 1e-12 hi by 22 passes of 4-point
- *     multisection.  The candidate is the iterate with the smaller
+ *     not bind).  It is solved exactly: the breakpoints at which coordinates
+ *     of d reach their bounds are sorted and ||d||_omega = r is solved on the
+ *     interval between two of them, where ||d||^2 is a quadratic in 1/lam
+ *     (no iteration).  The candidate is the iterate with the smaller
  *     rho_{||z - z^{n,0}||}(z) (ties to the average); criteria (i)-(iii) as for
  *     KKT with rho in place of KKT, the reference value being the restart
  *     point's rho (the candidate's at the restart, with the radius to the
@@ -540,85 +541,88 @@ int orc_ray_test(const orc_problem* p, const double* x_dir, const double* y_dir,
 
 /* ---------------------------------------------------------------- normalized duality gap */
 
-#define GAP_POINTS 4    /* lambda values per multisection pass */
-#define GAP_PASSES 22
+/* One coordinate of the trust-region problem of rho_r: with s = 1/lam the
+ * maximiser's coordinate is d(s) = clip(a s, lo, hi), a = (W^-1 g)_j, weight w
+ * (omega for x, 1/omega for y), gradient g; it reaches its bound (the one a
+ * points to) at the breakpoint s = bound / a. */
+typedef struct {
+  double t;      /* breakpoint (+inf when that bound is infinite) */
+  double a, w, g, bound;
+} gap_coord;
 
-/* omega ||dx||^2 + ||dy||^2 / omega and g'd at d(lam) (see the description above) */
-static void gap_sums(const lp_t* P, const double* x, const double* y, const double* gx, const double* gy,
-                     double omega, double lam, double* N, double* G) {
-  int32_t m = P->m, n = P->n;
-  double* tn = (double*)xalloc((size_t)n, sizeof(double));
-  double* tg = (double*)xalloc((size_t)n, sizeof(double));
-  double* tm = (double*)xalloc((size_t)m, sizeof(double));
-  double* tq = (double*)xalloc((size_t)m, sizeof(double));
-  /* d = W^-1 g / lam: x-part g_x / (omega lam), y-part g_y omega / lam */
-  double sx = 1.0 / (omega * lam), sy = omega / lam, iom = 1.0 / omega;
-  for (int32_t j = 0; j < n; ++j) {
-    double d = gx[j] * sx;
-    double lo = P->l[j] - x[j], hi = P->u[j] - x[j];
-    if (d < lo) d = lo;
-    if (d > hi) d = hi;
-    tn[j] = omega * (d * d);
-    tg[j] = gx[j] * d;
-  }
-  for (int32_t i = 0; i < m; ++i) {
-    double d = gy[i] * sy;
-    if (P->ineq[i] && d < -y[i]) d = -y[i];
-    tm[i] = (d * d) * iom;
-    tq[i] = gy[i] * d;
-  }
-  *N = blocked_sum(n, tn) + blocked_sum(m, tm);
-  *G = blocked_sum(n, tg) + blocked_sum(m, tq);
-  free(tn); free(tg); free(tm); free(tq);
+static int cmp_breakpoint(const void* p, const void* q) {
+  double a = ((const gap_coord*)p)->t, b = ((const gap_coord*)q)->t;
+  return (a > b) - (a < b);
 }
 
-/* rho_r at the scaled point (x, y) with K~x = kx, K~'y = kty */
+/* rho_r at the scaled point (x, y) with K~x = kx, K~'y = kty, solved exactly.
+ * The objective L(x, yh) - L(xh, y) is linear in d = zh - z with gradient
+ * g = (K'y - c, q - Kx).  Over the box Z - z intersected with the ball
+ * ||d||_omega <= r its maximiser is d(s) = proj_{Z - z}(s W^-1 g) at the
+ * largest s >= 0 with ||d(s)||_omega <= r (s = inf when the ball never binds).
+ * ||d(s)||_omega^2 = A s^2 + C on each interval between consecutive
+ * breakpoints, A summing w a^2 over the coordinates not yet at their bound and
+ * C summing w bound^2 over those at it; it does not decrease with s.  The
+ * breakpoints are sorted, the interval on which ||d||^2 reaches r^2 is found,
+ * its A and C are summed afresh and s = sqrt((r^2 - C) / A) solved there. */
 static double normalized_gap(const lp_t* P, const double* x, const double* y, const double* kx,
                              const double* kty, double omega, double r) {
   if (!(r > 0.0)) return 0.0;
   int32_t m = P->m, n = P->n;
-  double* gx = (double*)xalloc((size_t)n, sizeof(double));
-  double* gy = (double*)xalloc((size_t)m, sizeof(double));
-  double* t1 = (double*)xalloc((size_t)n, sizeof(double));
-  double* t2 = (double*)xalloc((size_t)m, sizeof(double));
+  gap_coord* cs = (gap_coord*)xalloc((size_t)n + (size_t)m, sizeof(gap_coord));
+  int64_t nc = 0;
   for (int32_t j = 0; j < n; ++j) {
-    gx[j] = kty[j] - P->c[j];
-    t1[j] = (gx[j] * gx[j]) / omega;
+    double g = kty[j] - P->c[j], a = g / omega;
+    if (a == 0.0) continue;
+    double b = a > 0.0 ? P->u[j] - x[j] : P->l[j] - x[j];
+    gap_coord e = {isfinite(b) ? b / a : INFINITY, a, omega, g, b};
+    cs[nc++] = e;
   }
   for (int32_t i = 0; i < m; ++i) {
-    gy[i] = P->q[i] - kx[i];
-    t2[i] = omega * (gy[i] * gy[i]);
+    double g = P->q[i] - kx[i], a = g * omega;
+    if (a == 0.0) continue;
+    double b = a > 0.0 ? INFINITY : (P->ineq[i] ? -y[i] : -INFINITY);
+    gap_coord e = {isfinite(b) ? b / a : INFINITY, a, 1.0 / omega, g, b};
+    cs[nc++] = e;
   }
-  double gn2 = blocked_sum(n, t1) + blocked_sum(m, t2);
-  double rho = 0.0;
-  if (gn2 > 0.0) {
-    double r2 = r * r, N, G;
-    double hi = sqrt(gn2) / r, lo = hi * 1e-12;
-    gap_sums(P, x, y, gx, gy, omega, lo, &N, &G);
-    if (N > r2) {
-      for (int it = 0; it < GAP_PASSES; ++it) {
-        double q = exp(log(hi / lo) / (GAP_POINTS + 1));
-        double lam[GAP_POINTS], Nk[GAP_POINTS];
-        double v = lo;
-        for (int k = 0; k < GAP_POINTS; ++k) {
-          v = v * q;
-          lam[k] = v;
-          gap_sums(P, x, y, gx, gy, omega, v, &Nk[k], &G);
-        }
-        /* N is nonincreasing in lam: keep N(lo) > r2 >= N(hi) */
-        int k = 0;
-        while (k < GAP_POINTS && Nk[k] > r2) ++k;
-        double nlo = k > 0 ? lam[k - 1] : lo;
-        double nhi = k < GAP_POINTS ? lam[k] : hi;
-        lo = nlo;
-        hi = nhi;
-      }
-      gap_sums(P, x, y, gx, gy, omega, hi, &N, &G);
+  qsort(cs, (size_t)nc, sizeof(gap_coord), cmp_breakpoint);
+  double r2 = r * r;
+  /* the first breakpoint index `cut` such that ||d(t_cut)||^2 >= r^2: the
+   * coordinates before it are at their bounds on the crossing interval */
+  double A = 0.0, C = 0.0;
+  for (int64_t q = 0; q < nc; ++q) A += cs[q].w * cs[q].a * cs[q].a;
+  int64_t cut = 0;
+  while (cut < nc && isfinite(cs[cut].t)) {
+    double t = cs[cut].t;
+    if (A * t * t + C >= r2) break;
+    A -= cs[cut].w * cs[cut].a * cs[cut].a;
+    C += cs[cut].w * cs[cut].bound * cs[cut].bound;
+    ++cut;
+  }
+  /* sums of the crossing interval taken afresh (the running ones above only
+   * locate it); every coordinate from `cut` on is free there */
+  double* ta = (double*)xalloc((size_t)nc + 1, sizeof(double));
+  double* tc = (double*)xalloc((size_t)nc + 1, sizeof(double));
+  for (int64_t q = 0; q < nc; ++q) {
+    ta[q] = q >= cut ? cs[q].w * (cs[q].a * cs[q].a) : 0.0;
+    tc[q] = q < cut ? cs[q].w * (cs[q].bound * cs[q].bound) : 0.0;
+  }
+  A = blocked_sum(nc, ta);
+  C = blocked_sum(nc, tc);
+  double s = INFINITY;   /* the ball does not bind: every coordinate at its bound */
+  if (cut < nc) s = A > 0.0 ? sqrt((r2 - C > 0.0 ? r2 - C : 0.0) / A) : 0.0;
+  for (int64_t q = 0; q < nc; ++q) {
+    double d;
+    if (q < cut || !isfinite(s)) d = cs[q].bound;
+    else {
+      d = cs[q].a * s;
+      if (cs[q].a > 0.0 ? d > cs[q].bound : d < cs[q].bound) d = cs[q].bound;
     }
-    rho = G / r;
+    ta[q] = cs[q].g * d;
   }
-  free(gx); free(gy); free(t1); free(t2);
-  return rho;
+  double G = blocked_sum(nc, ta);
+  free(cs); free(ta); free(tc);
+  return G / r;
 }
 
 static double weighted_dist(int32_t n, int32_t m, const double* x, const double* x0, const double* y,

@@ -4,8 +4,9 @@ metric that Section 3.4 says the KKT error replaces) in the oracle.
 rho_r(z) = max { L(x, yh) - L(xh, y) : zh in Z, ||zh - z||_omega <= r } / r
 is pinned against: its closed form when no bound binds (the dual norm of the
 gradient), its closed form when only the box binds, a brute-force grid search
-over a two-variable box-and-ball, zero at a saddle point, and the monotonicity
-of r rho_r in r.  The restart scheme that uses it converges to the known
+over a two-variable box-and-ball, a brute-force enumeration of every active set
+of the box-and-ball problem on tiny LPs (exact, to rounding), zero at a saddle
+point, and the monotonicity of r rho_r in r.  The restart scheme that uses it converges to the known
 optimum.
 """
 import numpy as np
@@ -56,6 +57,59 @@ def test_two_variables_against_a_grid(w, r):
     val = np.where(w * (DX ** 2 + DY ** 2) <= r * r, -c[0] * DX - c[1] * DY, -np.inf).max() / r
     # the grid under-estimates by at most its spacing times the gradient
     assert val - 1e-12 <= rho <= val + 2e-3
+
+
+def _active_set_max(g, w, lo, hi, r):
+    """max g'd over {lo <= d <= hi, sum w d^2 <= r^2} by brute force over the
+    KKT forms of the maximiser: every coordinate is at its lower bound, at its
+    upper bound, or free with d_j = s g_j / w_j for one common s > 0 fixed by
+    the ball; the best feasible candidate is the maximum (tiny n only)."""
+    import itertools
+    best = -np.inf
+    for pat in itertools.product((0, 1, 2), repeat=len(g)):
+        d = np.zeros(len(g))
+        free = [j for j, k in enumerate(pat) if k == 2]
+        for j, k in enumerate(pat):
+            if k < 2:
+                d[j] = lo[j] if k == 0 else hi[j]
+        if not np.all(np.isfinite(d)):
+            continue
+        if free:
+            a = np.array([g[j] / w[j] for j in free])
+            rest = r * r - np.sum(w * d * d)
+            A = np.sum(np.array([w[j] for j in free]) * a * a)
+            if rest < 0 or A == 0:
+                continue
+            s = np.sqrt(rest / A)
+            d[free] = s * a
+        if np.all(d >= lo - 1e-12) and np.all(d <= hi + 1e-12) and np.sum(w * d * d) <= r * r * (1 + 1e-12):
+            best = max(best, float(g @ d))
+    return best
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_exact_against_active_set_enumeration(seed):
+    """rho_r equals the brute-force maximum over every active set of the
+    box-and-ball problem to rounding, on tiny LPs whose rows and columns mix
+    every bound type (so the ball binds, the box binds, or both)."""
+    rng = np.random.default_rng(100 + seed)
+    m, n = 2, 3
+    A = rng.standard_normal((m, n)); b = rng.standard_normal(m); c = rng.standard_normal(n)
+    l = np.where(rng.random(n) < 0.8, -rng.uniform(0, 1, n), -INF)
+    u = np.where(rng.random(n) < 0.8, rng.uniform(0, 1, n), INF)
+    rt = rng.integers(0, 2, m)                    # EQ or GE rows
+    p = lpgen.from_dense(A, c, b, l, u, rt)
+    x = np.clip(rng.uniform(-0.5, 0.5, n), l, u)
+    y = np.where(rt == 1, np.abs(rng.standard_normal(m)), rng.standard_normal(m))
+    w = float(rng.uniform(0.3, 3.0))
+    gx, gy = A.T @ y - c, b - A @ x
+    g = np.concatenate([gx, gy])
+    wt = np.concatenate([np.full(n, w), np.full(m, 1.0 / w)])
+    lo = np.concatenate([l - x, np.where(rt == 1, -y, -INF)])
+    hi = np.concatenate([u - x, np.full(m, INF)])
+    for r in (0.05, 0.4, 2.0, 50.0):
+        ref = _active_set_max(g, wt, lo, hi, r) / r
+        assert _gap(p, x, y, w, r) == pytest.approx(ref, rel=1e-12, abs=1e-15)
 
 
 def test_zero_at_a_saddle_point_and_monotone_in_r():
