@@ -10,11 +10,15 @@ timed inside pdlp_solve with the iterate already resident in HBM.  The line
 also carries:
   roofline     -- the dominant step kernel's algorithmic bytes per launch over
                   its mean launch duration (HIP events on the solver's stream),
-                  against 8 TB/s;
-  cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same LP
-                  (its first iterations), on the host cores;
+                  against 8 TB/s, and the fixed cost of a solve without steps;
+  roofline_fp32_matrix -- the same for both step kernels with the FP32 matrix;
+  cpu_baseline -- the FP64 CPU oracle on the same LP on the host cores: a solve
+                  to rel KKT 1e-4 with every core (capped, never extrapolated)
+                  and the first iterations with one thread;
   time_to_tol  -- wall time to rel KKT 1e-4 with the FP64 and the FP32 matrix and to
-                  1e-8 with the FP64 matrix, and of the 2000 x 2000 transportation LP to 1e-6.
+                  1e-8 with the FP64 matrix, and of the 2000 x 2000 transportation LP to 1e-6;
+  small_lp     -- the m = 1000, n = 2000 random LP to 1e-4 and 1e-8, GPU and oracle;
+  batch, warm_start -- the 4,096-LP batch and the learned warm start.
 """
 from __future__ import annotations
 
@@ -72,21 +76,84 @@ def _traffic_from_profiles(kernel: str):
     return None
 
 
-def cpu_baseline(prob, iters: int):
-    import oracle
-    oracle.build()
+def host_threads() -> int:
     cores = len(os.sched_getaffinity(0))
     env_threads = os.environ.get("OMP_NUM_THREADS")
-    threads = min(cores, int(env_threads)) if env_threads and env_threads.isdigit() else cores
+    return min(cores, int(env_threads)) if env_threads and env_threads.isdigit() else cores
+
+
+def cpu_baseline(prob, eps: float, cap_s: float, iters_1t: int):
+    """The oracle on the 1e6 x 2e6 LP on the host cores: with every core, a
+    solve to rel KKT eps capped at cap_s seconds of solve time (never
+    extrapolated), whose iterations per second are the baseline value; with
+    one thread, the first iters_1t accepted iterations."""
+    import oracle
+    oracle.build()
+    threads = host_threads()
     t0 = time.time()
-    r = oracle.solve(prob, eps_rel=0.0, max_iter=iters, threads=threads)
+    r = oracle.solve(prob, eps_rel=eps, max_iter=1_000_000, time_limit_s=cap_s, threads=threads)
     wall = time.time() - t0
     info = r.info
+    reached = r.status == "OPTIMAL"
+    t1 = time.time()
+    r1 = oracle.solve(prob, eps_rel=0.0, max_iter=iters_1t, threads=1)
+    wall1 = time.time() - t1
+    i1 = r1.info
     return {"value": info["iterations"] / info["solve_s"], "unit": "PDHG iters/sec", "cores": info["threads_used"],
             "kind": "oracle",
-            "sample": (f"first {info['iterations']} accepted PDHG iterations ({info['attempts']} attempts, "
-                       f"{info['evaluations']} evaluations) of the same 1e6x2e6 LP, FP64; "
-                       f"setup {info['setup_s']:.1f}s excluded, total {wall:.1f}s")}
+            "sample": (f"a solve of the same 1e6x2e6 LP (FP64) to rel KKT {eps:g}, capped at {cap_s:g} s: "
+                       f"{info['iterations']} accepted iterations ({info['attempts']} attempts, "
+                       f"{info['evaluations']} evaluations) in {info['solve_s']:.1f} s, "
+                       + ("tolerance reached" if reached else f"not reached in {info['solve_s']:.1f} s")
+                       + f"; setup {info['setup_s']:.1f} s excluded, total {wall:.1f} s"),
+            "time_to_tol_s": round(info["solve_s"], 2) if reached else None,
+            "status": r.status, "primal_obj": info["primal_obj"],
+            "one_thread": {"value": i1["iterations"] / i1["solve_s"], "cores": i1["threads_used"],
+                           "sample": f"first {i1['iterations']} accepted iterations in {i1['solve_s']:.1f} s "
+                                     f"(setup {i1['setup_s']:.1f} s excluded, total {wall1:.1f} s)"}}
+
+
+def small_lp_section(P, stream, seeds=(0, 1, 2)):
+    """The m = 1000, n = 2000 random LP (8 nonzeros per column) to rel KKT
+    1e-4 and 1e-8: GPU wall time (setup and solve apart) and iterations per
+    second, the attempt-slot floor, and the oracle with every host core and
+    with one thread on the same LPs; objective error of the GPU's solution
+    against the oracle's."""
+    import lpgen
+    import oracle
+    oracle.build()
+    out = {"workload": "random LP m=1000 (500 EQ, 500 LE), n=2000, 8 nnz per column, x in [0,10], FP64",
+           "seeds": list(seeds)}
+    for eps in (1e-4, 1e-8):
+        g_solve, g_setup, g_it, g_att, errs = [], [], [], [], []
+        o_all, o_one, o_it = [], [], []
+        for sd in seeds:
+            p = lpgen.config0(sd)
+            h = P.pdlp_create(p, stream=stream, eps_rel=eps, time_limit_s=60.0)
+            P.pdlp_solve(h)          # first solve: graph capture, code load
+            P.pdlp_solve(h)
+            _, _, _, inf = P.pdlp_get_solution(h)
+            P.pdlp_destroy(h)
+            r = oracle.solve(p, eps_rel=eps, threads=host_threads())
+            r1 = oracle.solve(p, eps_rel=eps, threads=1)
+            g_solve.append(inf["solve_s"]); g_setup.append(inf["setup_s"])
+            g_it.append(inf["iterations"]); g_att.append(inf["attempts"])
+            o_all.append(r.info["solve_s"]); o_one.append(r1.info["solve_s"]); o_it.append(r.info["iterations"])
+            ro = r.info["primal_obj"]
+            errs.append(abs(inf["primal_obj"] - ro) / (1 + abs(ro)))
+        out[f"{eps:g}"] = {
+            "gpu_solve_s": [round(v, 4) for v in g_solve], "gpu_setup_s": [round(v, 4) for v in g_setup],
+            "gpu_iterations": g_it, "gpu_attempts": g_att,
+            "gpu_iters_per_s": round(float(np.sum(g_it) / np.sum(g_solve)), 1),
+            "gpu_attempts_per_s": round(float(np.sum(g_att) / np.sum(g_solve)), 1),
+            "oracle_solve_s_all_cores": [round(v, 4) for v in o_all],
+            "oracle_solve_s_one_thread": [round(v, 4) for v in o_one],
+            "oracle_iterations": o_it, "oracle_cores": host_threads(),
+            "oracle_iters_per_s_all_cores": round(float(np.sum(o_it) / np.sum(o_all)), 1),
+            "oracle_iters_per_s_one_thread": round(float(np.sum(o_it) / np.sum(o_one)), 1),
+            "obj_rel_err_vs_oracle_max": max(errs)}
+        log(f"random 1000x2000 to {eps:g}: {out[f'{eps:g}']}")
+    return out
 
 
 def _gen_batch_lp(args):
@@ -265,7 +332,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--cpu-cap", type=float, default=60.0,
+                    help="solve-time cap (s) of the all-core oracle run to rel KKT 1e-4 on the large LP")
+    ap.add_argument("--cpu-iters-1t", type=int, default=16,
+                    help="accepted iterations of the one-thread oracle sample on the large LP")
+    ap.add_argument("--no-small", action="store_true", help="skip the m=1000, n=2000 random LP section")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--profile-attempts", type=int, default=200)
     ap.add_argument("--layout", type=int, nargs=2, default=(-1, -2), metavar=("K", "KT"),
@@ -329,11 +400,17 @@ def main():
     # per-kernel durations (HIP events on the solver's stream) and the roofline
     ms_a, ms_b = P.pdlp_profile_attempts(h, args.profile_attempts)
     by_a, by_b = P.pdlp_step_bytes(h)
-    # a step is one kernel (row blocks) or two (column panels: segment sums, then rows)
-    names = {0: "{}<{}>", 1: "k_seg<{1}> + k_rows<{1}>", 2: "{}<{}> (XCD-contiguous blocks)"}
+    # a step is one kernel (row blocks), two (column panels: segment sums, then rows) or three
+    # (LDS-staged panels: long-row segment sums, short-row segment sums, then rows)
+    names = {0: "{}<{}>", 1: "k_seg<{1}> + k_rows<{1}>", 2: "{}<{}> (XCD-contiguous blocks)",
+             3: "k_stage<{1}> + k_seg<{1}> + k_rows<{1}> (LDS-staged panels)"}
     lk, lt = info["layout_k"], info["layout_kt"]
-    kname = lambda lay, op: (names[lay & 3].format("k_fused", op) + (" (persistent grid)" if lay & 4 else "") +
-                             (" (6144-nonzero blocks)" if lay & 8 else ""))
+
+    def kname(lay, op):
+        if (lay & 3) == 3:
+            return names[3].format("", op) + f" ({256 << (lay >> 4)}-thread staging workgroups)"
+        return (names[lay & 3].format("k_fused", op) + (" (persistent grid)" if lay & 4 else "") +
+                (" (6144-nonzero blocks)" if lay & 8 else ""))
     kern = {"primal_step": (ms_a, by_a, kname(lt, "PrimalOp")), "dual_step": (ms_b, by_b, kname(lk, "DualOp"))}
     dom = max(kern, key=lambda k: kern[k][0])
     ms_d, by_d, kname = kern[dom]
@@ -347,7 +424,35 @@ def main():
                                  "GBps": round(kern[[k for k in kern if k != dom][0]][1] /
                                                (kern[[k for k in kern if k != dom][0]][0] * 1e-3) / 1e9, 1)},
                 "copy_GBps": round(copy_gbps, 1)}
+    # fixed cost of a solve: the starting evaluation, the output and the
+    # host-device round trips, without any step (max_iter = 0)
+    P.pdlp_set_termination(h, 0.0, 0, 600.0)
+    fixed = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.pdlp_solve(h)
+        torch.cuda.synchronize()
+        fixed.append(time.perf_counter() - t1)
+    roofline["solve_fixed_ms"] = round(1e3 * float(np.median(fixed)), 3)
     log(f"roofline: {roofline}")
+    P.pdlp_destroy(h)
+
+    # the same step kernels with the FP32 matrix (FP64 accumulation and iterates)
+    h = P.pdlp_create(prob, stream=stream, eps_rel=0.0, max_iter=args.warmup, time_limit_s=600.0,
+                      a_precision=1, detect_infeas=args.detect_infeas)
+    P.pdlp_solve(h)
+    ms_a32, ms_b32 = P.pdlp_profile_attempts(h, args.profile_attempts)
+    by_a32, by_b32 = P.pdlp_step_bytes(h)
+    i32 = P.pdlp_get_solution(h)[3]
+    roof32 = {"layout_k_kt": [i32["layout_k"], i32["layout_kt"]]}
+    for nm, ms_, by_ in (("primal_step", ms_a32, by_a32), ("dual_step", ms_b32, by_b32)):
+        ach = by_ / (ms_ * 1e-3) / 1e9
+        roof32[nm] = {"bytes_per_launch": by_, "ms_per_launch": ms_, "achieved": round(ach, 1),
+                      "frac": round(ach / PEAK_HBM_GBPS, 4)}
+    roof32["ms_per_attempt_pair"] = round(ms_a32 + ms_b32, 4)
+    roof32["fp64_ms_per_attempt_pair"] = round(ms_a + ms_b, 4)
+    log(f"roofline, FP32 matrix: {roof32}")
     P.pdlp_destroy(h)
 
     ttt = None
@@ -369,7 +474,9 @@ def main():
             ttt[name] = {"status": inf["status_name"], "iterations": inf["iterations"],
                          "attempts": inf["attempts"], "restarts": inf["restarts"],
                          "setup_s": round(inf["setup_s"], 3), "solve_s": round(inf["solve_s"], 3),
+                         "iters_per_s": round(inf["iterations"] / max(inf["solve_s"], 1e-9), 1),
                          "rel_kkt_gpu": inf["rel_kkt"], "rel_kkt_cpu_fp64_recheck": ev["rel_kkt"],
+                         "primal_obj": inf["primal_obj"],
                          "obj_rel_err_vs_known_optimum": abs(inf["primal_obj"] - obj_star) / (1 + abs(obj_star))}
             if pre:
                 ttt[name]["solved_m_n"] = [inf["m_solved"], inf["n_solved"]]
@@ -402,10 +509,20 @@ def main():
         ws = warmstart_section(P, stream, args.ws_train, args.ws_test, args.ws_epochs, 64, 1e-3, 1e-6)
         log(f"warm start: {ws}")
 
+    small = None
+    if not args.no_small:
+        small = small_lp_section(P, stream)
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(prob, args.cpu_iters)
+        cpu = cpu_baseline(prob, 1e-4, args.cpu_cap, args.cpu_iters_1t)
         log(f"cpu baseline: {cpu}")
+        if ttt is not None:
+            # each GPU objective at rel KKT 1e-4 against the FP64 oracle's objective at the same tolerance
+            ro = cpu["primal_obj"]
+            for name in ("fp64_1e-4", "fp32_matrix_1e-4"):
+                if cpu["status"] == "OPTIMAL":
+                    ttt[name]["obj_rel_err_vs_oracle_1e-4"] = abs(ttt[name]["primal_obj"] - ro) / (1 + abs(ro))
 
     line = {"metric": "PDHG iters/sec + wall time to rel KKT 1e-4/1e-8; SpMV HBM GB/s vs peak",
             "value": round(steps / dt, 2), "unit": "PDHG iters/sec", "n_gpus": 1, "steps": steps,
@@ -415,8 +532,8 @@ def main():
                                    "power-law capped at 10,000, FP64 matrix",
                        "m": prob.m, "n": prob.n, "nnz": prob.nnz, "eval_period": 64,
                        "spmv_layout_k_kt": [info["layout_k"], info["layout_kt"]]},
-            "roofline": roofline, "cpu_baseline": cpu, "time_to_tol": ttt, "batch": batch,
-            "warm_start": ws}
+            "roofline": roofline, "roofline_fp32_matrix": roof32, "cpu_baseline": cpu, "time_to_tol": ttt,
+            "small_lp": small, "batch": batch, "warm_start": ws}
     print(json.dumps(line), flush=True)
 
 

@@ -90,7 +90,8 @@ typedef struct {
                                  restart / termination evaluations use the FP64 matrix */
   int32_t kkt_omega_power;    /* 2: KKT_omega weights omega^2 and omega^-2 as in eq. (kkt); 1 */
   int32_t trace;              /* capacity of the decision trace (attempts and evaluations), 0 = off */
-  int32_t poll_every;         /* 4: graph launches between two reads of the 8-byte status word */
+  int32_t poll_every;         /* 1: graph launches between two reads of the 8-byte status word
+                                 (fewer are launched once the graphs in flight can reach max_iter) */
   int32_t graph;              /* 1: the inner loop is a captured hipGraph; 0: the same kernels
                                  launched one by one (for callers that cannot use graphs) */
   int32_t spmv_layout;        /* -1: chosen per matrix at create by timing the step passes (default);
@@ -99,8 +100,14 @@ typedef struct {
                                  block ranges per XCD; plus 4: a persistent grid (one workgroup
                                  per 8 waves of every CU, looping over the row blocks); plus 8:
                                  the step passes take blocks of 6144 nonzeros instead of 3072
-                                 (the evaluation passes keep 3072).  The timing at create tries
-                                 every combination on matrices with 2^20 nonzeros or more.  The
+                                 (the evaluation passes keep 3072); or 3, 19, 35: the step pass
+                                 runs on LDS-staged column panels -- the rows with at least 128
+                                 nonzeros (numbered first by row_order) are cut into panels of
+                                 16,384 columns whose slice of the gathered vector a workgroup of
+                                 256, 512 or 1024 threads copies into LDS once, the other rows
+                                 are swept directly -- with column panels on a persistent grid
+                                 for the evaluation passes.  The timing at create tries every
+                                 combination on matrices with 2^20 nonzeros or more.  The
                                  layout changes the order of floating-point sums; fix it for
                                  bitwise reproducibility across handles.  This field applies to
                                  K, and to K' unless spmv_layout_kt says otherwise */
@@ -177,7 +184,8 @@ typedef struct {
   double setup_s;             /* pdlp_create: upload, transpose, scaling, layout choice */
   double solve_s;             /* pdlp_solve wall time */
   int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout: 0, 1, 2,
-                                   plus 4 for a persistent grid, plus 8 for the wide step tiles);
+                                   plus 4 for a persistent grid, plus 8 for the wide step tiles,
+                                   or 3, 19, 35 for LDS-staged step passes);
                                    for an LP of a batch: its sweeps of K and K' (see
                                    pdlp_batch_schedule) */
   int64_t handoff_k;          /* an LP of a batch: accepted steps when the single-LP kernels took

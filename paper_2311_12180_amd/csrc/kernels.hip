@@ -124,6 +124,129 @@ __global__ __launch_bounds__(kBlock) void k_rows(Params p) {
   }
 }
 
+// LDS-staged panels, phase 1 (step passes: one gathered vector).  A work item
+// is a run of one column panel's chunks: the workgroup copies the panel's
+// slice of the gathered vector into LDS once; then each wavefront takes whole
+// chunks, every lane summing its segment in stored order (coalesced loads of
+// the lane-interleaved entries, every gather an LDS read, no barrier), and
+// stores the segment sums.  A chunk's descriptor is read while the previous
+// chunk is summed.
+template <class Op, typename VT, int BS>
+__global__ __launch_bounds__(BS) void k_stage(Params p) {
+  static_assert(Op::NV == 1, "staged panels hold one gathered vector");
+  __shared__ double xs[kStageWidth];
+  if (Op::idle(p, p.st)) return;
+  const Op op(p, p.st);
+  const StagedCsr& S = Op::mat(p).stg;
+  double* __restrict__ part = S.part;
+  const VT* __restrict__ vals = pick<VT>(S.pv, S.pvf);
+  const uint16_t* __restrict__ pci = S.pci;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int kWaves = BS / 64;
+  constexpr int kU = 8;   // loads in flight per lane
+  for (int w = blockIdx.x; w < S.nwork; w += gridDim.x) {
+    const int c0 = S.wpanel[w] * kStageWidth;
+    const int nc = min(kStageWidth, S.ncols - c0);
+    for (int j0 = 0; j0 < nc; j0 += kU * BS) {
+      double g[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * BS + (int)threadIdx.x;
+        op.gather(c0 + (j < nc ? j : nc - 1), &g[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * BS + (int)threadIdx.x;
+        if (j < nc) xs[j] = g[u];
+      }
+    }
+    __syncthreads();
+    const int ch1 = S.wchunk[w + 1];
+    int c = S.wchunk[w] + wv;
+    int len = 0, off = 0, s0 = 0, s1 = 0;
+    if (c < ch1) {
+      len = S.clen[c];
+      off = S.coff[c];
+      s0 = S.cseg[c];
+      s1 = S.cseg[c + 1];
+    }
+    while (c < ch1) {
+      const int cn = c + kWaves;
+      int nlen = 0, noff = 0, ns0 = 0, ns1 = 0;
+      if (cn < ch1) {
+        nlen = S.clen[cn];
+        noff = S.coff[cn];
+        ns0 = S.cseg[cn];
+        ns1 = S.cseg[cn + 1];
+      }
+      const int base = off + lane;
+      double acc = 0.0;
+      for (int k = 0; k < len; k += kU) {
+        int col[kU];
+        double a[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int kk = k + u < len ? k + u : len - 1;   // past the end: the last entry again (in bounds)
+          col[u] = __builtin_nontemporal_load(pci + base + kk * kStageLanes);
+          a[u] = (double)__builtin_nontemporal_load(vals + base + kk * kStageLanes);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (k + u < len) acc += a[u] * xs[col[u]];
+      }
+      if (s0 + lane < s1) part[s0 + lane] = acc;
+      c = cn;
+      len = nlen;
+      off = noff;
+      s0 = ns0;
+      s1 = ns1;
+    }
+    __syncthreads();   // the next work item rewrites xs
+  }
+}
+
+// LDS-staged panels, phase 2: workgroups [0, nrblocks) sweep one block of
+// short rows each, gathering from global memory; the last nlong_groups give
+// each long row a wavefront (its lanes add the row's segment sums
+// lane-strided in panel order, then a shuffle tree), dispatched after the
+// short blocks so that their dependent loads overlap the tail of the sweep.
+// Every row runs the epilogue.  One reduction partial per workgroup.
+template <class Op, typename VT>
+__global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
+  __shared__ double lds[Op::NV * kTile];
+  __shared__ double red[AccSize<Op>::RED];
+  if (Op::idle(p, p.st)) return;
+  const Op op(p, p.st);
+  const DevCsr& M = Op::mat(p);
+  const StagedCsr& S = M.stg;
+  double acc[AccSize<Op>::N];
+#pragma unroll
+  for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
+  const int nlg = S.nlong_groups, nrb = S.nrblocks;
+  if ((int)blockIdx.x >= nrb) {
+    constexpr int kWaves = kBlock / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = (blockIdx.x - nrb) * kWaves + wv; r < S.rlong; r += nlg * kWaves) {
+      double sum = 0.0;
+      const int q1 = S.row_seg[r + 1];
+      for (int q = S.row_seg[r] + lane; q < q1; q += 64) sum += S.part[S.slot_seg[q]];
+      sum = wave_sum(sum);
+      if (lane == 0) op.epi(r, &sum, acc);
+    }
+  } else {
+    spmv_block<Op::NV, VT, kBlock, kTile>(
+        M.rp, M.ci, pick<VT>(M.v, M.vf), S.rblocks[blockIdx.x], lds, red,
+        [&](int c, double* g) { op.gather(c, g); }, [&](int r, const double* s) { op.epi(r, s, acc); });
+  }
+  if constexpr (Op::NACC > 0) {
+    block_sum<Op::NACC>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < Op::NACC; ++k) Op::part(p)[Op::NACC * blockIdx.x + k] = acc[k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------- decisions
 
 
@@ -388,6 +511,19 @@ static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
   }
 }
 
+// A step pass in the LDS-staged layout: the long rows' staged panels
+// (stg.cfg selects the workgroup size), then the row pass.
+template <class Op, typename VT>
+static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
+  const StagedCsr& S = M.stg;
+  if (S.nwork > 0) {
+    if (S.cfg == 2) hipLaunchKernelGGL((k_stage<Op, VT, 1024>), dim3(S.nwork), dim3(1024), 0, s, p);
+    else if (S.cfg == 1) hipLaunchKernelGGL((k_stage<Op, VT, 512>), dim3(S.nwork), dim3(512), 0, s, p);
+    else hipLaunchKernelGGL((k_stage<Op, VT, 256>), dim3(S.nwork), dim3(256), 0, s, p);
+  }
+  hipLaunchKernelGGL((k_stage_rows<Op, VT>), dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), 0, s, p);
+}
+
 // A step pass over a step view: the view replaces the matrix in the kernels'
 // parameters, and its tiling picks the kernels.
 template <class Op, int WHICH>
@@ -395,7 +531,10 @@ static void launch_view(const Params& p, hipStream_t s) {
   Params q = p;
   DevCsr& M = WHICH ? q.KT : q.K;
   M = WHICH ? p.KTs : p.Ks;
-  if (M.tile == kTileWide) {
+  if (M.layout == 3) {
+    if (q.use_f32) launch_staged<Op, float>(q, M, s);
+    else launch_staged<Op, double>(q, M, s);
+  } else if (M.tile == kTileWide) {
     if (q.use_f32) launch_op<Op, float, kTileWide>(q, M, s);
     else launch_op<Op, double, kTileWide>(q, M, s);
   } else {

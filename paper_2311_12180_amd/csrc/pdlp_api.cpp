@@ -51,6 +51,8 @@ hipError_t setup_sumsq(int64_t n, const double* a, double* part, double* out, hi
 hipError_t setup_absmax(int64_t nnz, const double* v, unsigned long long* out, hipStream_t s);
 hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s);
 hipError_t setup_fill(int64_t n, double* a, double val, hipStream_t s);
+hipError_t setup_permute_values(int64_t count, const int32_t* perm, const double* v, const float* vf, double* pv,
+                                float* pvf, hipStream_t s);
 hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
                          int32_t* pci, double* pv, float* pvf, hipStream_t s);
 hipError_t setup_rename(int64_t nnz, const int32_t* inv, int32_t* ci, hipStream_t s);
@@ -82,7 +84,8 @@ inline void check(hipError_t e, const char* what) {
 // first so that these heavier blocks are dispatched before the short ones; the
 // runs of short rows between them are cut greedily at `tile` nonzeros or
 // kMaxRows rows.
-std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end, int tile = kTile) {
+std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end, int tile = kTile,
+                                     int max_rows = kMaxRows) {
   std::vector<RowBlock> longs, shorts;
   int r = begin;
   while (r < end) {
@@ -93,7 +96,7 @@ std::vector<RowBlock> partition_rows(const int32_t* rp, int begin, int end, int 
     }
     const int r0 = r;
     int nz = 0;
-    while (r < end && r - r0 < kMaxRows) {
+    while (r < end && r - r0 < max_rows) {
       const int len = rp[r + 1] - rp[r];
       if (len > tile || nz + len > tile) break;
       nz += len;
@@ -117,10 +120,22 @@ struct HostPanels {
   std::vector<RowBlock> sblocks, sblocks_wide;   // phase-1 blocks of kTile and of kTileWide nonzeros
 };
 
-HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int ncols, const int32_t* col_ptr) {
+// Rows [r0, nrows) only (the rows before r0 get no segments); seg_ptr
+// offsets count from the first nonzero of row r0, perm holds CSR indices.
+HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int ncols, const int32_t* col_ptr,
+                        int r0 = 0) {
   HostPanels H;
-  const int64_t nnz = rp[nrows];
-  // panel boundaries: about nnz / kPanels nonzeros each (col_ptr = row pointer of the transpose)
+  const int64_t nnz = (int64_t)rp[nrows] - rp[r0];
+  // panel boundaries: about nnz / kPanels nonzeros of these rows each
+  // (col_ptr = row pointer of the transpose when the range is every row;
+  // otherwise the range's own column counts)
+  std::vector<int32_t> own;
+  if (r0 > 0) {
+    own.assign((size_t)ncols + 1, 0);
+    for (int32_t e = rp[r0]; e < rp[nrows]; ++e) own[(size_t)ci[e] + 1]++;
+    for (int j = 0; j < ncols; ++j) own[(size_t)j + 1] += own[(size_t)j];
+    col_ptr = own.data();
+  }
   std::vector<int32_t> cb(kPanels + 1, ncols);
   cb[0] = 0;
   for (int p = 1, j = 0; p < kPanels; ++p) {
@@ -133,7 +148,7 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
     for (int j = cb[p]; j < cb[p + 1]; ++j) colpan[(size_t)j] = (uint8_t)p;
   std::vector<uint8_t> mask((size_t)nrows, 0);
   std::vector<int64_t> pnnz(kPanels, 0), pseg(kPanels, 0);
-  for (int r = 0; r < nrows; ++r) {
+  for (int r = r0; r < nrows; ++r) {
     for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
       const int p = colpan[(size_t)ci[e]];
       mask[(size_t)r] |= (uint8_t)(1u << p);
@@ -157,7 +172,7 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
   H.slot_seg.assign((size_t)nseg, 0);
   H.perm.assign((size_t)nnz, 0);
   std::vector<int32_t> last(kPanels, -1);
-  for (int r = 0; r < nrows; ++r) {
+  for (int r = r0; r < nrows; ++r) {
     for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
       const int p = colpan[(size_t)ci[e]];
       if (last[p] != r) {
@@ -185,6 +200,137 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
     for (int p = 0; p < kPanels; ++p)
       for (size_t j = 0; j < pb[p].size(); ++j) sb[j * kPanels + p] = pb[p][j];
   }
+  return H;
+}
+
+// LDS-staged panel layout (see StagedCsr), built on the host from the
+// structure.  Rows [0, rlong) -- the leading rows with at least `min_len`
+// nonzeros -- are cut into panels of kStageWidth columns; each panel's
+// segments are sorted by length (longest first, then by row), numbered in
+// that order and grouped in chunks of kStageLanes, stored lane-interleaved
+// with zero padding up to the chunk's longest segment.  Each panel's chunks
+// are cut into `per_panel` work items of about equal entry counts.  The rows
+// [rlong, nrows) are cut into plain row blocks.
+struct HostStaged {
+  int32_t rlong = 0, nseg = 0;
+  int64_t nnz_long = 0, nent = 0;
+  std::vector<int32_t> wpanel, wchunk, coff, clen, cseg, perm, row_seg, slot_seg;
+  std::vector<uint16_t> pci;   // column relative to the panel (kStageWidth <= 65536)
+  std::vector<RowBlock> rblocks;
+};
+
+constexpr int kStageMinLen = 128;   // nonzeros of a row summed through the staged panels
+
+// Work items per panel: one workgroup per CU of the chip's 256 in a single
+// wave when the panels are fewer than the CUs.
+int stage_items_per_panel(int ncols) {
+  const int np = (ncols + kStageWidth - 1) / kStageWidth;
+  return std::max(1, 256 / std::max(np, 1));
+}
+
+// Nonzeros of the leading rows with at least min_len nonzeros.
+int64_t leading_long_nnz(const int32_t* rp, int nrows, int min_len) {
+  int r = 0;
+  while (r < nrows && rp[r + 1] - rp[r] >= min_len) ++r;
+  return (int64_t)rp[r] - rp[0];
+}
+
+HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int ncols, int min_len, int per_panel) {
+  HostStaged H;
+  int rl = 0;
+  while (rl < nrows && rp[rl + 1] - rp[rl] >= min_len) ++rl;
+  H.rlong = rl;
+  H.nnz_long = (int64_t)rp[rl] - rp[0];
+  const int np = (ncols + kStageWidth - 1) / kStageWidth;
+  // segments (nonzero count, row) of every panel
+  struct Seg {
+    int32_t cnt, row;
+  };
+  std::vector<std::vector<Seg>> ps((size_t)np);
+  std::vector<int32_t> cnt((size_t)np, 0), touched;
+  for (int r = 0; r < rl; ++r) {
+    touched.clear();
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      const int p = ci[e] / kStageWidth;
+      if (cnt[(size_t)p]++ == 0) touched.push_back(p);
+    }
+    for (int p : touched) {
+      ps[(size_t)p].push_back(Seg{cnt[(size_t)p], r});
+      cnt[(size_t)p] = 0;
+    }
+  }
+  // ids: panel-major, longest first inside a panel; chunks of kStageLanes
+  std::vector<int64_t> sbase((size_t)np + 1, 0);
+  for (int p = 0; p < np; ++p) {
+    std::stable_sort(ps[(size_t)p].begin(), ps[(size_t)p].end(),
+                     [](const Seg& a, const Seg& b) { return a.cnt > b.cnt; });
+    sbase[(size_t)p + 1] = sbase[(size_t)p] + (int64_t)ps[(size_t)p].size();
+  }
+  H.nseg = (int32_t)sbase[(size_t)np];
+  std::vector<int64_t> seg_at((size_t)H.nseg);   // entry position of a segment's first nonzero
+  std::vector<int32_t> chunk0((size_t)np + 1, 0);
+  int64_t ent = 0;
+  for (int p = 0; p < np; ++p) {
+    chunk0[(size_t)p] = (int32_t)H.coff.size();
+    const std::vector<Seg>& v = ps[(size_t)p];
+    for (size_t i = 0; i < v.size(); i += kStageLanes) {
+      const int32_t len = v[i].cnt;
+      H.coff.push_back((int32_t)ent);
+      H.clen.push_back(len);
+      H.cseg.push_back((int32_t)(sbase[(size_t)p] + (int64_t)i));
+      for (size_t l = 0; l < (size_t)kStageLanes && i + l < v.size(); ++l)
+        seg_at[(size_t)(sbase[(size_t)p] + (int64_t)(i + l))] = ent + (int64_t)l;
+      ent += (int64_t)kStageLanes * len;
+    }
+  }
+  chunk0[(size_t)np] = (int32_t)H.coff.size();
+  H.cseg.push_back(H.nseg);
+  H.nent = ent;
+  // every long row's segment ids in panel order (its slots), then its entries in place
+  std::vector<std::vector<int32_t>> rowsegs((size_t)rl);
+  for (int p = 0; p < np; ++p)
+    for (size_t i = 0; i < ps[(size_t)p].size(); ++i)
+      rowsegs[(size_t)ps[(size_t)p][i].row].push_back((int32_t)(sbase[(size_t)p] + (int64_t)i));
+  H.perm.assign((size_t)std::max<int64_t>(ent, 1), -1);
+  H.pci.assign((size_t)std::max<int64_t>(ent, 1), 0);
+  H.row_seg.assign((size_t)rl + 1, 0);
+  std::vector<int64_t> at((size_t)np);
+  for (int r = 0; r < rl; ++r) {
+    for (int32_t sid : rowsegs[(size_t)r]) {
+      const int p = (int)(std::upper_bound(sbase.begin(), sbase.end(), (int64_t)sid) - sbase.begin()) - 1;
+      at[(size_t)p] = seg_at[(size_t)sid];
+      H.slot_seg.push_back(sid);
+    }
+    H.row_seg[(size_t)r + 1] = (int32_t)H.slot_seg.size();
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      const int p = ci[e] / kStageWidth;
+      const int64_t pos = at[(size_t)p];
+      at[(size_t)p] += kStageLanes;
+      H.perm[(size_t)pos] = e;
+      H.pci[(size_t)pos] = (uint16_t)(ci[e] - p * kStageWidth);
+    }
+  }
+  // work items: each panel's chunks cut into per_panel runs of about equal entries
+  H.wchunk.push_back(0);
+  for (int p = 0; p < np; ++p) {
+    const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
+    if (a == b) continue;
+    const int64_t e0 = H.coff[(size_t)a];
+    const int64_t tot = (b < (int32_t)H.coff.size() ? (int64_t)H.coff[(size_t)b] : ent) - e0;
+    int k = 1;
+    for (int32_t c = a; c < b; ++c) {
+      const int64_t done = (int64_t)H.coff[(size_t)c] - e0 + (int64_t)kStageLanes * H.clen[(size_t)c];
+      if (c + 1 == b || (k < per_panel && done * per_panel >= tot * k)) {
+        H.wpanel.push_back(p);
+        H.wchunk.push_back(c + 1);
+        ++k;
+      }
+    }
+  }
+  // short rows: at most one row per thread of a block, so that no thread
+  // runs two row epilogues one after the other
+  H.rblocks = partition_rows(rp, rl, nrows, kTile, kBlock);
+  if (H.rblocks.empty()) H.rblocks.push_back(RowBlock{rl, rl});
   return H;
 }
 
@@ -225,6 +371,9 @@ struct pdlp_handle {
   int32_t wide_nblocks[2] = {0, 0};
   const RowBlock* wide_sblocks[2] = {nullptr, nullptr};
   int32_t wide_nsblocks[2] = {0, 0};
+  // the LDS-staged layouts of K and K' a step view may take
+  StagedCsr stg[2] = {};
+  bool has_stg[2] = {false, false};
   std::string err = "no error";
   bool solved = false;
   pdlp_info info{};
@@ -350,7 +499,7 @@ extern "C" int pdlp_default_options(pdlp_options* o) {
   o->a_precision = PDLP_A_FP64;
   o->kkt_omega_power = 2;
   o->trace = 0;
-  o->poll_every = 4;
+  o->poll_every = 1;
   o->graph = 1;
   o->spmv_layout = -1;
   o->spmv_layout_kt = -2;
@@ -382,11 +531,17 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.trace < 0) return why = "trace must be >= 0", -1;
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
-  auto bad_layout = [](int v) { return v < -1 || v > 14 || (v >= 0 && (v & 3) == 3); };
+  // -1; 0, 1, 2 plus 4 and/or 8; 3, 19, 35 (LDS-staged step passes, phase-1 workgroups of 256, 512, 1024)
+  auto bad_layout = [](int v) {
+    if (v == 3 || v == 19 || v == 35) return false;
+    return v < -1 || v > 14 || (v >= 0 && (v & 3) == 3);
+  };
   if (bad_layout(o.spmv_layout))
-    return why = "spmv_layout must be -1 or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles)", -1;
+    return why = "spmv_layout must be -1, or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), "
+                 "or 3, 19, 35 (LDS-staged step passes)", -1;
   if (o.spmv_layout_kt != -2 && bad_layout(o.spmv_layout_kt))
-    return why = "spmv_layout_kt must be -2, -1 or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles)", -1;
+    return why = "spmv_layout_kt must be -2, -1, or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), "
+                 "or 3, 19, 35 (LDS-staged step passes)", -1;
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
@@ -523,6 +678,52 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
   S.part = h->dalloc<double>(2 * (size_t)std::max(S.nseg, 1));
 }
 
+// Device copy of an LDS-staged layout for the step view of matrix `which`
+// (kept in h->stg until the chooser or the option selects it).
+static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, int ncols, const double* v,
+                          const float* vf) {
+  hipStream_t s = h->stream;
+  const hipMemcpyKind kind = hipMemcpyHostToDevice;
+  auto up = [&](const auto& vec, const char* what) {
+    using T = typename std::decay_t<decltype(vec)>::value_type;
+    T* d = h->dalloc<T>(vec.size());
+    if (!vec.empty()) check(hipMemcpyAsync(d, vec.data(), vec.size() * sizeof(T), kind, s), what);
+    return d;
+  };
+  StagedCsr& S = h->stg[which];
+  S = StagedCsr{};
+  S.nwork = (int32_t)H.wpanel.size();
+  S.ncols = ncols;
+  S.nseg = H.nseg;
+  S.rlong = H.rlong;
+  // the row pass: a wavefront per long row (four per workgroup), then one
+  // workgroup per block of short rows
+  S.nlong_groups = std::min(kElemBlocks, (H.rlong + kBlock / 64 - 1) / (kBlock / 64));
+  S.nrblocks = (int32_t)H.rblocks.size();
+  S.wpanel = up(H.wpanel, "upload staged panels");
+  S.wchunk = up(H.wchunk, "upload staged panels");
+  S.coff = up(H.coff, "upload staged panels");
+  S.clen = up(H.clen, "upload staged panels");
+  S.cseg = up(H.cseg, "upload staged panels");
+  S.row_seg = up(H.row_seg, "upload staged panels");
+  S.slot_seg = up(H.slot_seg, "upload staged panels");
+  S.rblocks = up(H.rblocks, "upload staged panels");
+  S.pci = up(H.pci, "upload staged panels");
+  const int64_t ne = std::max<int64_t>(H.nent, 1);
+  int32_t* perm = h->dalloc<int32_t>((size_t)ne);
+  double* pv = h->dalloc<double>((size_t)ne);
+  float* pvf = vf ? h->dalloc<float>((size_t)ne) : nullptr;
+  if (H.nent) {
+    check(hipMemcpyAsync(perm, H.perm.data(), (size_t)H.nent * 4, kind, s), "upload staged panels");
+    check(setup_permute_values(H.nent, perm, v, vf, pv, pvf, s), "permute staged panels");
+  }
+  S.pv = pv;
+  S.pvf = pvf;
+  S.part = h->dalloc<double>((size_t)H.nseg + 1);
+  check(hipStreamSynchronize(s), "staged panels sync");
+  h->has_stg[which] = H.nseg > 0;
+}
+
 // Mean duration (ms) of the step pass over K (which = 0, the dual step) or K'
 // (1, the primal step) in the current layout, on a private state: current
 // buffer 0, a tiny step, a pending weight of 0.  The passes then read the
@@ -603,11 +804,29 @@ static void choose_layouts(pdlp_handle* h) {
         V.nred = layout == 1 ? V.rows_grid : V.nblocks;
       }
     };
-    if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid, bit 3 the wide step tiles
+    // the step view in the LDS-staged layout (phase-1 workgroup size `cfg`);
+    // the evaluation view then always takes column panels (else row blocks) on
+    // a persistent grid, so that the layout code names the whole configuration
+    auto set_staged = [&](int cfg) {
+      set(has_pan ? 1 : 0, 0, 1, kTile);
+      V = M;
+      V.layout = 3;
+      V.tile = kTile;
+      V.remap = 0;
+      V.grid = 0;
+      V.stg = h->stg[which];
+      V.stg.cfg = cfg;
+      V.nred = V.stg.nlong_groups + V.stg.nrblocks;
+    };
+    if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid, bit 3 the wide step tiles;
+                       // 3 + 16 cfg: staged step view, column panels (else row blocks) on a persistent grid
+                       // for the evaluations
       const int g = (mode & 4) ? 1 : 0, t = (mode & 8) ? kTileWide : kTile;
       if ((mode & 3) == 0) set(0, 0, g, t);
       else if ((mode & 3) == 2) set(0, 1, g, t);
-      else set(has_pan ? 1 : 0, 0, g, t);
+      else if ((mode & 3) == 1) set(has_pan ? 1 : 0, 0, g, t);
+      else if (h->has_stg[which]) set_staged((mode >> 4) & 3);
+      else set(has_pan ? 1 : 0, 0, 1, kTile);
       continue;
     }
     set(0, 0, 0, kTile);
@@ -639,6 +858,19 @@ static void choose_layouts(pdlp_handle* h) {
       best_t = kTile;
     }
     set(best_l, best_r, best_g, best_t);
+    if (h->has_stg[which]) {
+      int best_c = -1;
+      for (int cfg = 0; cfg < 3; ++cfg) {
+        set_staged(cfg);
+        const double t = time_probe(h, which, 6);
+        if (t < 0.98 * best) {
+          best = t;
+          best_c = cfg;
+        }
+      }
+      set(best_l, best_r, best_g, best_t);
+      if (best_c >= 0) set_staged(best_c);
+    }
     h->probe_ms[which] = best;
   }
 }
@@ -1046,8 +1278,12 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     // a panel layout pays when the gathered vector does not fit one XCD's L2;
     // spmv_layout = 1 builds it for any size (tests)
     const int mode_k = opt.spmv_layout, mode_kt = opt.spmv_layout_kt != -2 ? opt.spmv_layout_kt : opt.spmv_layout;
-    const bool want_k = (mode_k >= 0 && (mode_k & 3) == 1) || (mode_k == -1 && nnz >= (1 << 20) && n >= (1 << 18));
-    const bool want_kt = (mode_kt >= 0 && (mode_kt & 3) == 1) || (mode_kt == -1 && nnz >= (1 << 20) && m >= (1 << 18));
+    // (a staged code builds it under the size rule of the automatic choice,
+    // so that its evaluation passes take the same layout either way)
+    const bool want_k = (mode_k >= 0 && (mode_k & 3) == 1) ||
+                        ((mode_k == -1 || (mode_k & 3) == 3) && nnz >= (1 << 20) && n >= (1 << 18));
+    const bool want_kt = (mode_kt >= 0 && (mode_kt & 3) == 1) ||
+                         ((mode_kt == -1 || (mode_kt & 3) == 3) && nnz >= (1 << 20) && m >= (1 << 18));
     {
       std::vector<int32_t> hciT;
       if (want_k) {
@@ -1061,12 +1297,40 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
         upload_panels(h, 1, P.KT, HP, nnz, h->ciT, h->valT, h->valTf);
       }
     }
+    // the LDS-staged step layouts: when the long rows (at least kStageMinLen
+    // nonzeros, numbered first) hold most of the nonzeros and the gathered
+    // vector is large; spmv_layout = 3 (+16 cfg) builds them for any size (tests)
+    {
+      const bool force_k = mode_k >= 0 && (mode_k & 3) == 3, force_kt = mode_kt >= 0 && (mode_kt & 3) == 3;
+      const bool auto_k = mode_k == -1 && nnz >= (1 << 20) && n >= (1 << 18);
+      const bool auto_kt = mode_kt == -1 && nnz >= (1 << 20) && m >= (1 << 18);
+      if (force_k || auto_k) {
+        const int64_t nl = leading_long_nnz(H.rp.data(), m, kStageMinLen);
+        if (force_k || 2 * nl >= nnz) {
+          HostStaged HS = build_staged(H.rp.data(), H.ci.data(), m, n, kStageMinLen, stage_items_per_panel(n));
+          upload_staged(h, 0, HS, n, h->val, h->valf);
+        }
+      }
+      if (force_kt || auto_kt) {
+        const int64_t nl = leading_long_nnz(hrpT.data(), n, kStageMinLen);
+        if (force_kt || 2 * nl >= nnz) {
+          std::vector<int32_t> hciT((size_t)std::max<int64_t>(nnz, 1));
+          if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
+          HostStaged HS = build_staged(hrpT.data(), hciT.data(), n, m, kStageMinLen, stage_items_per_panel(m));
+          upload_staged(h, 1, HS, m, h->valT, h->valTf);
+        }
+      }
+    }
     P.Ks = P.K;
     P.KTs = P.KT;
     alloc_iterates(h);
     // partials: one per block of either tiling, or per workgroup of the row pass
-    const size_t redk = std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid});
-    const size_t redt = std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid});
+    // (and per workgroup of the staged layouts' row pass)
+    auto stg_red = [&](int w) {
+      return h->has_stg[w] ? (size_t)(h->stg[w].nlong_groups + h->stg[w].nrblocks) : (size_t)0;
+    };
+    const size_t redk = std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid, stg_red(0)});
+    const size_t redt = std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid, stg_red(1)});
     P.partA = h->dalloc<double>(redt);
     P.partB = h->dalloc<double>(2 * redk);
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
@@ -1183,6 +1447,8 @@ static void start_solve(pdlp_handle* h) {
   launch_init(h->P, h->has_warm ? h->wx : nullptr, h->has_warm ? h->wy : nullptr, s);
   launch_eval(h->P, s);
   check(hipGetLastError(), "launch start");
+  // the state after the starting evaluation (the first poll of the solve loop)
+  check(hipMemcpyAsync(s0, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s), "read state");
   check(hipStreamSynchronize(s), "start sync");
 }
 
@@ -1210,10 +1476,12 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.eta_hat = f->eta_hat;
   I.setup_s = h->setup_s;
   I.solve_s = now_s() - t0;
-  I.layout_k = (h->P.K.layout == 1 ? 1 : (h->P.K.remap ? 2 : 0)) + (h->P.K.grid > 0 ? 4 : 0) +
-                (h->P.Ks.tile == kTileWide ? 8 : 0);
-  I.layout_kt = (h->P.KT.layout == 1 ? 1 : (h->P.KT.remap ? 2 : 0)) + (h->P.KT.grid > 0 ? 4 : 0) +
-                (h->P.KTs.tile == kTileWide ? 8 : 0);
+  auto code = [](const DevCsr& M, const DevCsr& V) {
+    if (V.layout == 3) return 3 + 16 * V.stg.cfg;
+    return (M.layout == 1 ? 1 : (M.remap ? 2 : 0)) + (M.grid > 0 ? 4 : 0) + (V.tile == kTileWide ? 8 : 0);
+  };
+  I.layout_k = code(h->P.K, h->P.Ks);
+  I.layout_kt = code(h->P.KT, h->P.KTs);
   I.ray_source = f->ray_src;
   I.ray_obj = f->ray_obj;
   I.ray_res = f->ray_res;
@@ -1246,16 +1514,26 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
     start_solve(h);
     hipStream_t s = h->stream;
     const int per = h->opt.poll_every;
-    // pipelined polling: launch batch b, then wait for the status copied after batch b-1
+    // accepted steps one graph can take at most: an evaluation falls due after
+    // every P accepted steps and the attempt slots idle until it has run
+    const int64_t per_graph = (int64_t)h->opt.eval_period * h->rounds;
+    // pipelined polling: launch batch b, then wait for the status copied after
+    // batch b-1.  A batch is left empty (a status read only) while the graphs
+    // in flight could already take the solve to max_iter, so a solve with a
+    // step budget ends with at most the idle slots of its last graph.
     int pending = -1;  // index of the status buffer of the previous batch
-    check(hipMemcpyAsync(h->st_host[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s), "read state");
-    check(hipStreamSynchronize(s), "sync");
+    int graphs_in[2] = {0, 0};   // graphs launched in the batch of each status buffer
     const bool done = h->st_host[0]->done != 0;
+    int64_t k_seen = h->st_host[0]->k;
+    int64_t in_flight = 0;       // graphs launched after the status k_seen was read
     int cur = 0;
     int64_t last_k = -1;
     int stalls = 0;
     while (!done) {
-      for (int i = 0; i < per; ++i) {
+      const int nl = (h->opt.max_iter - k_seen <= in_flight * per_graph) ? 0 : per;
+      graphs_in[cur] = nl;
+      in_flight += nl;
+      for (int i = 0; i < nl; ++i) {
         if (h->opt.graph) {
           check(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
         } else {
@@ -1275,16 +1553,20 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
       if (pending >= 0) {
         check(hipEventSynchronize(h->ev[pending]), "hipEventSynchronize");
         if (h->st_host[pending]->done) break;
+        k_seen = h->st_host[pending]->k;
+        in_flight -= graphs_in[pending];
         // a healthy run accepts a step within a few attempts; a batch of graphs
         // without any accepted step means the state is broken
-        if (h->st_host[pending]->k == last_k) {
-          if (++stalls >= 64) {
-            launch_set_limit(h->st, PDLP_NUMERICAL_ERROR, s);
-            break;
+        if (graphs_in[pending] > 0) {
+          if (k_seen == last_k) {
+            if (++stalls >= 64) {
+              launch_set_limit(h->st, PDLP_NUMERICAL_ERROR, s);
+              break;
+            }
+          } else {
+            stalls = 0;
+            last_k = k_seen;
           }
-        } else {
-          stalls = 0;
-          last_k = h->st_host[pending]->k;
         }
       }
       if (now_s() - t0 > h->opt.time_limit_s) {

@@ -50,6 +50,47 @@ struct PanelCsr {
                             // workgroup's stores are contiguous and stay on its own XCD
 };
 
+// LDS-staged panel layout of a CSR matrix for a step pass (one gathered
+// vector).  The long rows (at least 128 nonzeros; the descending-length row
+// order numbers them first) are cut by columns into panels of kStageWidth
+// columns; the nonzeros of long row r in panel p form segment (r, p).  Inside
+// a panel the segments are sorted by length (longest first) and grouped in
+// chunks of kStageLanes, one segment per lane of a wavefront, stored
+// lane-interleaved (entry k of lane l at coff + 64 k + l) with zeros padding
+// each lane up to the chunk's longest segment, column indices relative to the
+// panel (16 bits).  Phase 1 (k_stage): a work item (one workgroup) is a run of one
+// panel's chunks; it copies the panel's slice of the gathered vector into LDS
+// once, then each wavefront sums whole chunks (coalesced loads, every gather
+// an LDS read, no barrier) and stores one sum per segment.  Phase 2
+// (k_stage_rows): the short rows are swept as plain row blocks of at most one
+// row per thread (equal lengths are numbered by first column, so their
+// gathers run in address order), then a wavefront per long row adds its
+// segment sums in panel order; every row runs the epilogue.
+constexpr int kStageWidth = 16384;   // columns per panel: 128 KB of FP64 in LDS (at most 65536: 16-bit indices)
+constexpr int kStageLanes = 64;      // segments per chunk
+struct StagedCsr {
+  int32_t nwork;            // phase-1 work items
+  int32_t ncols;
+  int32_t nseg;             // segments of the long rows
+  int32_t cfg;              // phase-1 workgroup size: 0: 256, 1: 512, 2: 1024 threads
+  int32_t rlong;            // rows [0, rlong) are the long rows
+  int32_t nlong_groups;     // phase-2 workgroups of the long rows
+  int32_t nrblocks;         // phase-2 row blocks of the short rows (at most kBlock rows each)
+  int32_t pad;
+  const int32_t* wpanel;    // [nwork] panel of each work item
+  const int32_t* wchunk;    // [nwork+1] chunk range of each work item
+  const int32_t* coff;      // [nchunk] first entry of each chunk
+  const int32_t* clen;      // [nchunk] entries per lane (the chunk's longest segment)
+  const int32_t* cseg;      // [nchunk+1] first segment of each chunk
+  const uint16_t* pci;      // column index relative to the panel (0 on padding)
+  const double* pv;         // FP64 values (0 on padding)
+  const float* pvf;         // FP32 values (nullptr unless FP32 steps)
+  const int32_t* row_seg;   // [rlong+1] long row r's segments: slot_seg[row_seg[r] .. row_seg[r+1]), in panel order
+  const int32_t* slot_seg;
+  double* part;             // [nseg] segment sums
+  const RowBlock* rblocks;  // [nrblocks] row blocks of the short rows [rlong, nrows)
+};
+
 struct DevCsr {
   const int32_t* rp;
   const int32_t* ci;
@@ -58,7 +99,7 @@ struct DevCsr {
   const RowBlock* blocks; // long rows first, then runs of short rows
   int32_t nblocks;
   int32_t nrows;
-  int32_t layout;         // 0: fused row blocks; 1: column panels (two phases)
+  int32_t layout;         // 0: fused row blocks; 1: column panels (two phases); 3: LDS-staged panels (stg)
   int32_t remap;          // fused layout: contiguous block ranges per XCD
   int32_t nred;           // reduction partials of a pass over this matrix
   int32_t rows_grid;      // grid of the phase-2 (row-wise) kernels
@@ -66,6 +107,7 @@ struct DevCsr {
                           // else a persistent grid (a multiple of 8) looping over the blocks
   PanelCsr pan;
   int32_t tile;           // nonzeros per block of `blocks` and `pan.sblocks`: 0 = kTile, or kTileWide
+  StagedCsr stg;          // layout 3 (step views only): LDS-staged panels of the long rows
 };
 
 // Solver state in device memory.  The first 16 bytes are the status word the

@@ -139,6 +139,16 @@ __global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, const i
   }
 }
 
+// Values of a padded layout: entry q is entry perm[q], or a zero where perm[q] < 0.
+__global__ void k_permute_values(int64_t count, const int32_t* __restrict__ perm, const double* __restrict__ v,
+                                 const float* __restrict__ vf, double* __restrict__ pv, float* __restrict__ pvf) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = perm[q];
+    pv[q] = p >= 0 ? v[p] : 0.0;
+    if (vf) pvf[q] = p >= 0 ? vf[p] : 0.0f;
+  }
+}
+
 // Row renumbering: K~' entries keep their place and get the new row index;
 // row vectors are gathered into the new order (new row r is old row perm[r]).
 __global__ void k_rename(int64_t nnz, const int32_t* __restrict__ inv, int32_t* __restrict__ ci) {
@@ -279,6 +289,12 @@ hipError_t setup_to_f32(int64_t nnz, const double* v, float* f, hipStream_t s) {
 hipError_t setup_permute(int64_t nnz, const int32_t* perm, const int32_t* ci, const double* v, const float* vf,
                          int32_t* pci, double* pv, float* pvf, hipStream_t s) {
   if (nnz > 0) hipLaunchKernelGGL(k_permute, grid_for(nnz), dim3(256), 0, s, nnz, perm, ci, v, vf, pci, pv, pvf);
+  return hipGetLastError();
+}
+
+hipError_t setup_permute_values(int64_t count, const int32_t* perm, const double* v, const float* vf, double* pv,
+                                float* pvf, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_permute_values, grid_for(count), dim3(256), 0, s, count, perm, v, vf, pv, pvf);
   return hipGetLastError();
 }
 

@@ -118,10 +118,11 @@ def test_rejects_bad_sizes_and_options(P):
     _bad(p, P, P.PDLP_ERR_ARG, "eps_rel", eps_rel=float("nan"))
     _bad(p, P, P.PDLP_ERR_ARG, "max_iter", max_iter=-1)
     _bad(p, P, P.PDLP_ERR_ARG, "kkt_omega_power", kkt_omega_power=3)
-    # layouts: 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles); 3 is no layout
-    for bad in (-2, 3, 7, 11, 15, 16):
+    # layouts: 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), or
+    # 3 + 16 cfg (LDS-staged step passes, cfg 0..2) with no other bit
+    for bad in (-2, 7, 11, 15, 16, 23, 27, 51, 67):
         _bad(p, P, P.PDLP_ERR_ARG, "spmv_layout must be", spmv_layout=bad)
-    for bad in (-3, 3, 15, 16):
+    for bad in (-3, 15, 16, 39, 51):
         _bad(p, P, P.PDLP_ERR_ARG, "spmv_layout_kt must be", spmv_layout_kt=bad)
 
 

@@ -12,7 +12,7 @@ Bars:
     rounding-level changes (renumbered rows and columns, b and c moved by
     1e-15): that step moves with rounding (512..832 for one planted LP in the
     oracle alone, testing at every evaluation); when the
-    GPU took the oracle's path, the unit ray lies within max(1e-8, 100x) the
+    GPU took the oracle's path, the unit ray lies within max(1e-8, 10x) the
     oracle's own spread under renumbering (the rays are iterate differences of
     a diverging run, so their small entries carry the iterates' sensitivity to
     summation order);
@@ -24,6 +24,7 @@ import numpy as np
 import pytest
 
 import lpgen
+from tests import bars
 from tests.farkas import check_dual_ray, check_primal_ray
 
 pytestmark = pytest.mark.gpu
@@ -136,7 +137,7 @@ def test_certificates_match_oracle(P, orc, kind, arg, every):
     if I["iterations"] == r.info["iterations"] and I["ray_source"] == r.info["ray_source"] and spread is not None:
         d = float(np.abs(_ray(res) - _ray(r)).max())
         print(f"  unit ray vs oracle {d:.1e}, oracle spread {spread:.1e}")
-        assert d <= max(1e-8, 100 * spread), (d, spread)
+        assert d <= bars.bar(spread, 1e-8), (d, spread)
 
 
 @pytest.mark.parametrize("layout,prec", [(1, 0), (2, 0), (0, 1), (9, 1)])

@@ -6,7 +6,7 @@ Bars:
   * iterates after k accepted steps (k <= 100): identical decisions (every
     accept/reject, candidate and restart reason) and ||gpu - oracle||_inf /
     max(1, ||oracle||_inf) <= 1e-10 for x~ and y~ on the m=1000, n=2000
-    random LP; on the other families the bar is max(1e-10, 100 x the
+    random LP; on the other families the bar is max(1e-10, 10 x the
     oracle's own spread under a row/column renumbering), because there the
     step bound's denominator cancels and the trajectory itself amplifies
     rounding-order differences;
@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import lpgen
+from tests import bars
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +66,8 @@ PROBLEMS = {
     "transport_30x40": lambda: lpgen.transportation(1, 30, 40),
     "mixed_bounds": lambda: lpgen.mixed_lp(1),
     "long_rows": lambda: _long_row_lp(0),
+    # 3 column panels of the LDS-staged layout (16,384 columns each)
+    "skewed_20000x40000": lambda: lpgen.skewed_lp(3, m=20000, n=40000, nnz_target=400000, cap=8000),
 }
 
 
@@ -83,7 +86,7 @@ def test_scaling_is_bitwise_oracle(P, orc, name):
     np.testing.assert_array_equal(vs, ovs)
 
 
-def _rounding_spread(orc, p, opts, copies=3):
+def _rounding_spread(orc, p, opts, copies=4):
     """How far the oracle moves from itself when only the summation order
     changes (rows and columns renumbered, `copies` times): the method's own
     sensitivity to rounding over the same iterations.  The step bound's
@@ -110,7 +113,7 @@ def _rounding_spread(orc, p, opts, copies=3):
 @pytest.mark.parametrize("period", [1, 64])
 @pytest.mark.parametrize("kmax", [1, 10, 100])
 def test_trajectory_matches_oracle(P, orc, name, period, kmax):
-    """Identical decisions, and iterates within max(1e-10, 100 x the oracle's
+    """Identical decisions, and iterates within max(1e-10, 10 x the oracle's
     own rounding-order spread) after kmax accepted steps.  On the random LP of
     m=1000, n=2000 the spread is ~1e-14, so the bar there is 1e-10."""
     p = PROBLEMS[name]()
@@ -123,11 +126,12 @@ def test_trajectory_matches_oracle(P, orc, name, period, kmax):
     if not stable:
         pytest.skip(f"{name} P={period} k={kmax}: the oracle itself takes different decisions when only "
                     "its summation order changes (a near-tie); no unique trajectory to compare")
-    tol_x, tol_s = max(1e-10, 100 * sx), max(1e-10, 100 * se)
+    tol_x, tol_s = bars.bar(sx), bars.bar(se)
     ex, ey = _rel_inf(xh, r.x_hat), _rel_inf(yh, r.y_hat)
     ee = abs(st["eta_hat"] - r.info["eta_hat"]) / r.info["eta_hat"]
     print(f"{name} P={period} k={kmax}: x {ex:.2e} y {ey:.2e} eta_hat {ee:.2e} | "
-          f"oracle spread x {sx:.2e} scalars {se:.2e} | tol {tol_x:.2e} {tol_s:.2e}")
+          f"oracle spread x {sx:.2e} scalars {se:.2e} | tol {tol_x:.2e} {tol_s:.2e} | "
+          f"error / spread {bars.ratio(max(ex, ey), sx)}")
     assert st["iterations"] == r.info["iterations"] == kmax
     np.testing.assert_array_equal(tr["att_acc"], r.trace["att_acc"])
     np.testing.assert_array_equal(tr["ev_reason"], r.trace["ev_reason"])
@@ -141,13 +145,21 @@ def test_trajectory_matches_oracle(P, orc, name, period, kmax):
         assert max(ex, ey) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["random_1000x2000", "skewed_3000x6000", "long_rows", "transport_30x40"])
-@pytest.mark.parametrize("layout", [1, 2, 4, 5, 6, 8, 9, 13])
+LAYOUT_CASES = [(name, layout) for name in ("random_1000x2000", "skewed_3000x6000", "long_rows", "transport_30x40")
+                for layout in (1, 2, 4, 5, 6, 8, 9, 13)]
+# LDS-staged step passes of K (phase-1 workgroups of 256, 512 and 1024
+# threads) on the LPs with long rows, one of them over three column panels
+LAYOUT_CASES += [(name, layout) for name in ("skewed_3000x6000", "long_rows", "skewed_20000x40000")
+                 for layout in (3, 19, 35)]
+
+
+@pytest.mark.parametrize("name,layout", LAYOUT_CASES)
 def test_layouts_match_oracle(P, orc, name, layout):
     """Column panels (1), XCD-contiguous row blocks (2), their persistent-grid
-    forms (4, 5, 6) and the step passes on 6144-nonzero blocks (8, 9, 13)
-    follow the oracle's trajectory like the default layout: same decisions,
-    iterates within the rounding-order bar, over 100 accepted steps."""
+    forms (4, 5, 6), the step passes on 6144-nonzero blocks (8, 9, 13) and
+    the LDS-staged step passes (3, 19, 35) follow the oracle's trajectory
+    like the default layout: same decisions, iterates within the
+    rounding-order bar, over 100 accepted steps."""
     p = PROBLEMS[name]()
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64)
     h = P.pdlp_create(p, time_limit_s=60.0, trace=4096, spmv_layout=layout, **opts)
@@ -155,12 +167,16 @@ def test_layouts_match_oracle(P, orc, name, layout):
     xh, yh, st = P.pdlp_get_iterate(h)
     tr = P.pdlp_get_trace(h, 4096)
     info = P.pdlp_get_solution(h)[3]
-    assert (info["layout_k"], info["layout_kt"]) == (layout, layout)
+    if (layout & 3) == 3:   # LDS-staged step view of K; K' has no long rows here and keeps panels
+        assert info["layout_k"] == layout
+    else:
+        assert (info["layout_k"], info["layout_kt"]) == (layout, layout)
     r, sx, se, stable = _rounding_spread(orc, p, opts)
     assert stable
-    tol_x = max(1e-10, 100 * sx)
+    tol_x = bars.bar(sx)
     ex, ey = _rel_inf(xh, r.x_hat), _rel_inf(yh, r.y_hat)
-    print(f"{name} layout {layout}: x {ex:.2e} y {ey:.2e} tol {tol_x:.2e}")
+    print(f"{name} layout {layout}: x {ex:.2e} y {ey:.2e} tol {tol_x:.2e} "
+          f"error / spread {bars.ratio(max(ex, ey), sx)}")
     np.testing.assert_array_equal(tr["att_acc"], r.trace["att_acc"])
     np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
     assert st["attempts"] == r.info["attempts"] and st["restarts"] == r.info["restarts"]
@@ -203,7 +219,11 @@ def test_other_families_end_to_end(P, orc, name):
 
 def test_fp32_matrix_mode(P, orc):
     """FP32-rounded scaled matrix in the steps: trajectory parity with the
-    oracle's FP32 mode, and rel KKT 1e-4 on the true (FP64) LP."""
+    oracle's FP32 mode, and rel KKT 1e-4 on the true (FP64) LP.  The
+    objective at 1e-4 lies within 1e-6 of the oracle's FP32-mode objective
+    when the two took the same path (else 2 eps), and within 2 eps of the
+    FP64 oracle's: two points that both meet rel KKT eps can differ by about
+    that much in objective, whatever the matrix precision."""
     p = lpgen.config0(2)
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64, a_precision=1)
     h = P.pdlp_create(p, time_limit_s=60.0, **opts)
@@ -217,7 +237,14 @@ def test_fp32_matrix_mode(P, orc):
     e = orc.evaluate(p, res.x, res.y)
     assert e["rel_kkt"] <= 1e-4 * (1 + 1e-6)
     r64 = orc.solve(p, eps_rel=1e-4)
-    print("fp32 objective error vs fp64 oracle:", (res.info["primal_obj"] - r64.info["primal_obj"]))
+    r32 = orc.solve(p, eps_rel=1e-4, a_precision=1)
+    obj = res.info["primal_obj"]
+    e64 = abs(obj - r64.info["primal_obj"]) / (1 + abs(r64.info["primal_obj"]))
+    e32 = abs(obj - r32.info["primal_obj"]) / (1 + abs(r32.info["primal_obj"]))
+    same = res.info["iterations"] == r32.info["iterations"] and res.info["attempts"] == r32.info["attempts"]
+    print(f"fp32 objective error vs the FP64 oracle {e64:.1e}, vs the oracle's FP32 mode {e32:.1e} (same path {same})")
+    assert e32 <= (1e-6 if same else 2e-4)
+    assert e64 <= 2e-4
 
 
 def test_box_lp_without_rows(P):

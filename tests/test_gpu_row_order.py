@@ -4,7 +4,7 @@ handles) against the given order (row_order = 0) and the oracle.
 The renumbering happens after the scaling and every row vector crossing the
 interface is mapped back, so: the preconditioner and the scaled matrix are
 bitwise those of the given order (and the oracle's); the first accepted steps
-match the oracle within max(1e-10, 100 x) its own spread under renumbering
+match the oracle within max(1e-10, 10 x) its own spread under renumbering
 (only summation orders differ); a warm start from the known optimum in the
 caller's order ends at the first evaluation; solves re-check with the FP64
 evaluator; the iterate after a few steps agrees with the given-order run to
@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import lpgen
+from tests import bars
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def test_first_steps_match_oracle(P, orc, make):
     opts = dict(eps_rel=0.0, max_iter=100)
     r = orc.solve(p, **opts)
     spread = 0.0
-    for s in range(2):
+    for s in range(3):
         rng = np.random.default_rng(40 + s)
         rp, cp = rng.permutation(p.m), rng.permutation(p.n)
         q = orc.solve(lpgen.permute(p, rp, cp), **opts)
@@ -66,9 +67,10 @@ def test_first_steps_match_oracle(P, orc, make):
             pytest.skip("the oracle's own decisions change under renumbering (a near-tie)")
         spread = max(spread, _rel_inf(q.x, r.x[cp]), _rel_inf(q.y, r.y[rp]))
     res = P.solve(p, row_order=1, time_limit_s=60.0, **opts)
-    tol = max(1e-10, 100 * spread)
+    tol = bars.bar(spread)
     ex, ey = _rel_inf(res.x, r.x), _rel_inf(res.y, r.y)
-    print(f"{p.name}: x {ex:.1e} y {ey:.1e} (oracle spread {spread:.1e})")
+    print(f"{p.name}: x {ex:.1e} y {ey:.1e} (oracle spread {spread:.1e}, "
+          f"error / spread {bars.ratio(max(ex, ey), spread)})")
     assert res.info["attempts"] == r.info["attempts"]
     assert ex <= tol and ey <= tol
 
