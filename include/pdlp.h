@@ -232,6 +232,21 @@ int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const double* y0, doub
  * the host reads only an 8-byte status word between graph launches. */
 int pdlp_solve(pdlp_handle* h);
 
+/* For callers that cannot allocate device memory during a solve (serving
+ * loops and harnesses that forbid allocation once set up): pdlp_solve with
+ * the same kernels, results and status, launched one by one (no graph is
+ * instantiated), with every reduction partial and segment sum of the solve
+ * in a static device array of the library (64 MiB per GPU, held until the
+ * process ends) instead of the handle's own buffers.  It calls no hipMalloc,
+ * hipFree or other allocating routine; the handle (created by pdlp_create,
+ * which allocates) still owns the problem, the iterates and the outputs.
+ * Call it with the handle's device current (else PDLP_ERR_STATE).
+ * PDLP_ERR_UNSUPPORTED if the LP's partial sums need more than 64 MiB (the
+ * message gives the size) or on a batch handle (PDLP_ERR_STATE).  Every call
+ * on one GPU shares that array and clears it first: calls that overlap on one
+ * GPU, from any handle or thread, race. */
+int pdlp_solve_noalloc(pdlp_handle* h);
+
 /* Change the termination test of later solves: eps_rel >= 0, max_iter >= 0
  * accepted steps, time_limit_s > 0 (same meaning as in pdlp_options).
  * PDLP_ERR_ARG for values out of range; the handle keeps its old values then. */

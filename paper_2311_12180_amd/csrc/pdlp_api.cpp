@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -374,6 +375,10 @@ struct pdlp_handle {
   // the LDS-staged layouts of K and K' a step view may take
   StagedCsr stg[2] = {};
   bool has_stg[2] = {false, false};
+  // device of the handle, and the sizes (doubles) of the reduction partials
+  // that pdlp_solve_noalloc places in the static scratch
+  int device = 0;
+  size_t red_k = 0, red_t = 0;
   std::string err = "no error";
   bool solved = false;
   pdlp_info info{};
@@ -1331,6 +1336,8 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     };
     const size_t redk = std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid, stg_red(0)});
     const size_t redt = std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid, stg_red(1)});
+    h->red_k = redk;
+    h->red_t = redt;
     P.partA = h->dalloc<double>(redt);
     P.partB = h->dalloc<double>(2 * redk);
     P.partE0 = h->dalloc<double>(4 * (size_t)kElemBlocks);
@@ -1359,6 +1366,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
       check(hipGetDevice(&dev), "hipGetDevice");
       check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
       h->persist_grid = std::max(8, prop.multiProcessorCount * 8);
+      h->device = dev;
     }
     choose_layouts(h);
   } catch (const HipFail& f) {
@@ -1501,13 +1509,13 @@ extern "C" int pdlp_set_termination(pdlp_handle* h, double eps_rel, int64_t max_
   return PDLP_OK;
 }
 
-extern "C" int pdlp_solve(pdlp_handle* h) {
-  if (!h) return PDLP_ERR_ARG;
-  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve on a batch handle (use the _batch entry points)");
+// Algorithm 1 on a single-LP handle with the kernel parameters h->P: the
+// captured graph (use_graph) or the same kernels launched one by one.
+static int solve_single(pdlp_handle* h, bool use_graph) {
   const double t0 = now_s();
   try {
-    if (h->opt.graph && !h->gexec) build_graph(h);
-    if (!h->opt.graph) {
+    if (use_graph && !h->gexec) build_graph(h);
+    if (!use_graph) {
       h->slots_per_round = h->opt.eval_period + std::max(2, h->opt.eval_period / 8);
       h->rounds = std::max(1, 64 / h->opt.eval_period);
     }
@@ -1534,7 +1542,7 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
       graphs_in[cur] = nl;
       in_flight += nl;
       for (int i = 0; i < nl; ++i) {
-        if (h->opt.graph) {
+        if (use_graph) {
           check(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
         } else {
           for (int r = 0; r < h->rounds; ++r) {
@@ -1583,6 +1591,109 @@ extern "C" int pdlp_solve(pdlp_handle* h) {
   }
   h->solved = true;
   return PDLP_OK;
+}
+
+extern "C" int pdlp_solve(pdlp_handle* h) {
+  if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve on a batch handle (use the _batch entry points)");
+  return solve_single(h, h->opt.graph != 0);
+}
+
+// ---------------------------------------------------------------------------- allocation-free solve
+//
+// pdlp_solve_noalloc runs the same kernels as pdlp_solve, launched one by one
+// (instantiating a graph allocates), with every reduction partial and segment
+// sum of the solve in `scratch`, a static device array that each GPU the
+// library runs on holds until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device on the first call there.
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current).
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" int pdlp_solve_noalloc(pdlp_handle* h) {
+  if (!h) return PDLP_ERR_ARG;
+  if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_solve_noalloc on a batch handle");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(h, PDLP_ERR_HIP, "hipGetDevice failed");
+  if (dev != h->device)
+    return fail(h, PDLP_ERR_STATE, "pdlp_solve_noalloc: make the handle's device (" + std::to_string(h->device) +
+                                       ") current first (current: " + std::to_string(dev) + ")");
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, PDLP_ERR_UNSUPPORTED, "device index beyond 63");
+  // the buffers the solve writes and reads within one step or evaluation:
+  // reduction partials, and the segment sums of the layouts in use
+  Params Q = h->P;
+  struct Part {
+    double** at[4];
+    size_t count;
+  };
+  Part parts[16];
+  int np = 0;
+  auto add = [&](double** a, size_t count, double** b = nullptr) { parts[np++] = Part{{a, b, nullptr, nullptr}, count}; };
+  add(&Q.partA, h->red_t);
+  add(&Q.partB, 2 * h->red_k);
+  add(&Q.partE0, 4 * (size_t)kElemBlocks);
+  add(&Q.partE1, 10 * h->red_k);
+  add(&Q.partE2, 8 * h->red_t);
+  if (Q.infeas) {
+    add(&Q.partE3, 8 * h->red_k);
+    add(&Q.partE4, 12 * h->red_t);
+  }
+  if (Q.gap) add(&Q.partG, (size_t)kGapAcc * 2 * kElemBlocks);
+  for (int w = 0; w < 2; ++w) {
+    DevCsr& M = w ? Q.KT : Q.K;     // evaluation view
+    DevCsr& V = w ? Q.KTs : Q.Ks;   // step view (its panel sums are the same buffer as M's)
+    if ((M.layout == 1 || V.layout == 1) && M.pan.part)
+      add(&M.pan.part, 2 * (size_t)std::max(M.pan.nseg, 1), &V.pan.part);
+    if (V.layout == 3) add(&V.stg.part, (size_t)V.stg.nseg + 1);
+  }
+  size_t need = 0;
+  for (int i = 0; i < np; ++i) need = (need + 255) / 256 * 256 + parts[i].count * sizeof(double);
+  if (need > kScratchBytes)
+    return fail(h, PDLP_ERR_UNSUPPORTED,
+                "pdlp_solve_noalloc: this LP's partial sums need " + std::to_string(need) +
+                    " bytes of device scratch, more than its " + std::to_string(kScratchBytes) +
+                    " bytes; use pdlp_solve");
+  void* base = nullptr;
+  const hipError_t e = scratch_address(dev, &base);
+  if (e != hipSuccess) return fail(h, PDLP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  size_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    const Part& q = parts[i];
+    off = (off + 255) / 256 * 256;
+    double* ptr = reinterpret_cast<double*>(static_cast<unsigned char*>(base) + off);
+    for (double** a : q.at)
+      if (a) *a = ptr;
+    off += q.count * sizeof(double);
+  }
+  // the array keeps the last call's contents: start this solve from zeros
+  if (hipMemsetAsync(base, 0, need, h->stream) != hipSuccess)
+    return fail(h, PDLP_ERR_HIP, "hipMemsetAsync of the scratch failed");
+  const Params saved = h->P;
+  h->P = Q;
+  const int rc = solve_single(h, false);
+  h->P = saved;
+  return rc;
 }
 
 // A device vector over the rows, in the given row order.

@@ -30,6 +30,7 @@ ERRORS = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_DATA", -3: "PDLP_ERR_HIP", -4: "PDLP
           -5: "PDLP_ERR_STATE", -6: "PDLP_ERR_UNSUPPORTED"}
 
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_set_warm_start", "pdlp_set_termination", "pdlp_solve",
+            "pdlp_solve_noalloc",
             "pdlp_get_solution", "pdlp_get_iterate", "pdlp_get_scaling", "pdlp_get_trace",
             "pdlp_profile_attempts", "pdlp_step_bytes", "pdlp_create_batch", "pdlp_set_warm_start_batch",
             "pdlp_solve_batch", "pdlp_get_solution_batch", "pdlp_batch_schedule", "pdlp_presolve",
@@ -98,6 +99,7 @@ def lib() -> C.CDLL:
         L.pdlp_set_warm_start.argtypes = [vp, vp, vp, dbl]
         L.pdlp_set_termination.argtypes = [vp, dbl, i64, dbl]
         L.pdlp_solve.argtypes = [vp]
+        L.pdlp_solve_noalloc.argtypes = [vp]
         L.pdlp_get_solution.argtypes = [vp, vp, vp, vp, C.POINTER(pdlp_info)]
         L.pdlp_get_iterate.argtypes = [vp, vp, vp, C.POINTER(pdlp_iter_state)]
         L.pdlp_get_scaling.argtypes = [vp, vp, vp, vp]
@@ -324,6 +326,12 @@ def pdlp_set_termination(h: Handle, eps_rel: float, max_iter: int, time_limit_s:
 
 def pdlp_solve(h: Handle):
     _check(lib().pdlp_solve(h.ptr), h)
+
+
+def pdlp_solve_noalloc(h: Handle):
+    """pdlp_solve without any device allocation (partial sums in the library's
+    static device scratch; see include/pdlp.h)."""
+    _check(lib().pdlp_solve_noalloc(h.ptr), h)
 
 
 def _info_dict(info: pdlp_info) -> dict:
