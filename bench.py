@@ -337,8 +337,8 @@ def main():
     ap.add_argument("--cpu-iters-1t", type=int, default=16,
                     help="accepted iterations of the one-thread oracle sample on the large LP")
     ap.add_argument("--no-small", action="store_true", help="skip the m=1000, n=2000 random LP section")
-    ap.add_argument("--small-only", action="store_true",
-                    help="run only the m=1000, n=2000 random LP section and print its JSON (for profiling)")
+    ap.add_argument("--only", choices=("small", "batch", "warmstart"),
+                    help="run only that section and print its JSON (for profiling)")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--profile-attempts", type=int, default=200)
     ap.add_argument("--layout", type=int, nargs=2, default=(-1, -2), metavar=("K", "KT"),
@@ -364,8 +364,15 @@ def main():
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     dev = torch.device("cuda:0")
-    if args.small_only:
-        print(json.dumps(small_lp_section(P, torch.cuda.current_stream().cuda_stream)), flush=True)
+    if args.only:
+        st = torch.cuda.current_stream().cuda_stream
+        if args.only == "small":
+            out = small_lp_section(P, st)
+        elif args.only == "batch":
+            out = batch_section(P, st, args.batch_count, 1e-6, args.batch_sample)
+        else:
+            out = warmstart_section(P, st, args.ws_train, args.ws_test, args.ws_epochs, 64, 1e-3, 1e-6)
+        print(json.dumps(out), flush=True)
         return
     t = time.time()
     prob = lpgen.config1(0)

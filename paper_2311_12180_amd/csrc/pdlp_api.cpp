@@ -13,7 +13,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1977,8 +1979,9 @@ static void launch_batch_solve(pdlp_handle* h, double eps_rel, int64_t max_iter,
   check(hipGetLastError(), "batch launch");
 }
 
-// Wall time (ms) of a batch solve capped at `iters` accepted steps per LP.
-static double time_batch(pdlp_handle* h, int64_t iters, int reps) {
+// Wall time (ms) of a capped solve of the LPs `sub` only (a queue of their own).
+static double time_batch_subset(pdlp_handle* h, int64_t iters, int reps, const std::vector<int32_t>& sub) {
+  check(hipMemcpyAsync(h->order2, sub.data(), sub.size() * 4, hipMemcpyHostToDevice, h->stream), "upload sample");
   hipEvent_t a = nullptr, b = nullptr;
   double best = 1e30;
   try {
@@ -1986,7 +1989,7 @@ static double time_batch(pdlp_handle* h, int64_t iters, int reps) {
     check(hipEventCreate(&b), "hipEventCreate");
     for (int r = 0; r < reps; ++r) {
       check(hipEventRecord(a, h->stream), "event");
-      launch_batch_solve(h, 0.0, iters, 60.0);
+      launch_batch_solve(h, 0.0, iters, 60.0, 0, h->order2, (int32_t)sub.size());
       check(hipEventRecord(b, h->stream), "event");
       check(hipEventSynchronize(b), "sync");
       float ms = 0.f;
@@ -2003,10 +2006,19 @@ static double time_batch(pdlp_handle* h, int64_t iters, int reps) {
   return best;
 }
 
+namespace {
+// Lanes-per-row choices already tuned in this process, per (device, LDS
+// configuration, side, class): a later batch of the same classes skips the search.
+std::mutex g_lane_mu;
+std::map<std::tuple<int, size_t, int, int>, uint8_t> g_lane_cache;
+}  // namespace
+
 // Schedule of the persistent launch: lanes per row for the rows of K~ and of
-// K~' of every LP, chosen per (row-length, size) class by timing capped solves
-// of the whole batch (coordinate descent over the classes, lanes in 1..64),
-// then the number of workgroups.  Fixed values in the options skip the search.
+// K~' of every LP, chosen per (row-length, size) class by timing capped
+// solves of a sample of that class's LPs (at most one per workgroup of the
+// launch, spread over the class) under each choice, and remembered for the
+// process; then the number of workgroups, by timing capped solves of the whole
+// batch.  Fixed values in the options skip the search.
 static void tune_batch(pdlp_handle* h) {
   const int32_t cnt = h->count;
   const pdlp_options& opt = h->opt;
@@ -2035,8 +2047,10 @@ static void tune_batch(pdlp_handle* h) {
   const bool tune_lanes = opt.batch_lanes == 0;
   if (!tune_lanes && opt.batch_grid) return;
   const int64_t iters = 64;
-  (void)time_batch(h, iters, 1);  // first launch: code object load
-  double best = time_batch(h, iters, 2);
+  {
+    std::vector<int32_t> one(1, 0);
+    (void)time_batch_subset(h, 8, 1, one);   // first launch: code object load
+  }
   if (tune_lanes) {
     for (int side = 0; side < 2; ++side) {
       std::vector<int> classes;
@@ -2044,33 +2058,57 @@ static void tune_batch(pdlp_handle* h) {
       std::sort(classes.begin(), classes.end());
       classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
       for (int c : classes) {
-        uint8_t cur = 0;
+        std::vector<int32_t> members;
         for (int32_t b = 0; b < cnt; ++b)
-          if (cls[2 * b + side] == c) cur = h->lanes_h[2 * b + side];
-        const uint8_t start = cur;
-        for (int L : {0, 1, 2, 4, 8, 16, 32, 64}) {
-          if (L == start) continue;
-          for (int32_t b = 0; b < cnt; ++b)
-            if (cls[2 * b + side] == c) h->lanes_h[2 * b + side] = (uint8_t)L;
-          upload();
-          const double t = time_batch(h, iters, 2);
-          if (t < 0.98 * best) {
-            best = t;
-            cur = (uint8_t)L;
-          }
+          if (cls[2 * b + side] == c) members.push_back(b);
+        const auto key = std::make_tuple(dev, h->lds_bytes, side, c);
+        int cached = -1;
+        {
+          std::lock_guard<std::mutex> lock(g_lane_mu);
+          auto it = g_lane_cache.find(key);
+          if (it != g_lane_cache.end()) cached = it->second;
         }
-        for (int32_t b = 0; b < cnt; ++b)
-          if (cls[2 * b + side] == c) h->lanes_h[2 * b + side] = cur;
+        uint8_t cur = h->lanes_h[2 * (size_t)members[0] + side];
+        if (cached >= 0) {
+          cur = (uint8_t)cached;
+        } else {
+          // a sample spread over the class, at most one LP per workgroup
+          std::vector<int32_t> sub;
+          const size_t take = std::min(members.size(), (size_t)std::max(1, h->grid));
+          for (size_t i = 0; i < take; ++i) sub.push_back(members[i * members.size() / take]);
+          auto set_class = [&](uint8_t L) {
+            for (int32_t b : members) h->lanes_h[2 * (size_t)b + side] = L;
+            upload();
+          };
+          double best = time_batch_subset(h, iters, 2, sub);
+          const uint8_t start = cur;
+          for (int L : {0, 1, 2, 4, 8, 16, 32, 64}) {
+            if (L == start) continue;
+            set_class((uint8_t)L);
+            const double t = time_batch_subset(h, iters, 2, sub);
+            if (t < 0.98 * best) {
+              best = t;
+              cur = (uint8_t)L;
+            }
+          }
+          std::lock_guard<std::mutex> lock(g_lane_mu);
+          g_lane_cache[key] = cur;
+        }
+        for (int32_t b : members) h->lanes_h[2 * (size_t)b + side] = cur;
         upload();
       }
     }
   }
   if (!opt.batch_grid) {
+    std::vector<int32_t> all((size_t)cnt);
+    for (int32_t b = 0; b < cnt; ++b) all[(size_t)b] = b;
+    const int64_t giters = 32;
+    double best = time_batch_subset(h, giters, 1, all);
     int bestg = h->grid;
     for (int g = full / 2; g >= cus; g /= 2) {
       if (g >= cnt) continue;
       h->grid = g;
-      const double t = time_batch(h, iters, 2);
+      const double t = time_batch_subset(h, giters, 1, all);
       if (t < 0.98 * best) {
         best = t;
         bestg = g;
