@@ -5,8 +5,10 @@
 // The row reductions of the preconditioner run one thread per row in storage
 // order, and the vector norms sum 4096-element blocks serially and then the
 // block sums serially, so the scaled problem is bitwise reproducible.
-#include <hipcub/hipcub.hpp>
 #include <math.h>
+
+#include <algorithm>
+#include <utility>
 
 #include "pdlp_dev.h"
 
@@ -168,6 +170,159 @@ __global__ void k_fill(int64_t n, double* __restrict__ a, double v) {
     a[i] = v;
 }
 
+// ---------------------------------------------------------------------------- transpose: sort and scan
+//
+// CSR(K) -> CSR(K') is a stable sort of the nonzero positions by column (rows
+// stay ascending inside each column): a least-significant-digit radix sort
+// over 8-bit digits of the column index, each pass a tile histogram, an
+// exclusive scan of the digit-major histogram table and a stable scatter;
+// the row pointers of K' are the exclusive scan of the column counts.
+// Every quantity is an integer count, so the results do not depend on the
+// order of the atomic increments.
+
+constexpr int kSortTile = 4096;               // keys per tile (one workgroup)
+constexpr int kSortThreads = 256;
+constexpr int kSortPer = kSortTile / kSortThreads;
+constexpr int kRadix = 256;                   // 8-bit digits
+
+// Digit counts of every tile, digit-major: hist[d * ntiles + tile].
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int64_t n, const int32_t* __restrict__ keys, int shift,
+                                                             int32_t* __restrict__ hist, int ntiles) {
+  __shared__ int32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortPer; ++k) {
+    const int64_t i = base + k * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: the tile is taken in chunks of kSortThreads keys
+// in order; a key's place is its digit's offset for this tile, plus the keys
+// of that digit in earlier chunks, in earlier wavefronts of this chunk and in
+// lower lanes of its own wavefront (lanes with the same digit found by eight
+// ballots, one per digit bit).
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(int64_t n, const int32_t* __restrict__ keys,
+                                                                const int32_t* __restrict__ vals, int shift,
+                                                                const int32_t* __restrict__ offs, int ntiles,
+                                                                int32_t* __restrict__ keys_out,
+                                                                int32_t* __restrict__ vals_out) {
+  constexpr int kW = kSortThreads / 64;
+  __shared__ int32_t run[kRadix];
+  __shared__ int32_t wc[kW][kRadix];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  run[threadIdx.x] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < kSortPer; ++k) {
+#pragma unroll
+    for (int v = 0; v < kW; ++v) wc[v][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = base + k * kSortThreads + threadIdx.x;
+    const bool valid = i < n;
+    const int32_t key = valid ? keys[i] : 0;
+    const int32_t val = valid ? vals[i] : 0;
+    const int d = (key >> shift) & (kRadix - 1);
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(valid && bit);
+      same &= bit ? m : ~m;
+    }
+    const int rank = __popcll(same & below);
+    if (valid && rank == 0) wc[w][d] = __popcll(same);
+    __syncthreads();
+    if (valid) {
+      int32_t pos = offs[(int64_t)d * ntiles + blockIdx.x] + run[d] + rank;
+      for (int v = 0; v < w; ++v) pos += wc[v][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int v = 0; v < kW; ++v) add += wc[v][threadIdx.x];
+    run[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of n int32 counts, in three kernels: tile sums, a scan of
+// the tile sums by one workgroup, each tile's scan from its offset.
+__global__ __launch_bounds__(kSortThreads) void k_scan_tiles(int64_t n, const int32_t* __restrict__ in,
+                                                             int32_t* __restrict__ sums) {
+  __shared__ int32_t red[kSortThreads];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortPer;
+  int32_t t = 0;
+  for (int k = 0; k < kSortPer; ++k)
+    if (base + k < n) t += in[base + k];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int j = 0; j < kSortThreads; ++j) s += red[j];
+    sums[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int nt, int32_t* __restrict__ sums) {
+  __shared__ int32_t part[1024];
+  const int per = (nt + 1023) / 1024;
+  const int b0 = threadIdx.x * per, b1 = min(nt, b0 + per);
+  int32_t t = 0;
+  for (int b = b0; b < b1; ++b) t += sums[b];
+  part[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int j = 0; j < 1024; ++j) {
+      const int32_t x = part[j];
+      part[j] = s;
+      s += x;
+    }
+  }
+  __syncthreads();
+  int32_t s = part[threadIdx.x];
+  for (int b = b0; b < b1; ++b) {
+    const int32_t x = sums[b];
+    sums[b] = s;
+    s += x;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_apply(int64_t n, const int32_t* __restrict__ in,
+                                                             const int32_t* __restrict__ sums,
+                                                             int32_t* __restrict__ out) {
+  __shared__ int32_t pre[kSortThreads];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortPer;
+  int32_t t = 0;
+  for (int k = 0; k < kSortPer; ++k)
+    if (base + k < n) t += in[base + k];
+  pre[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s = sums[blockIdx.x];
+    for (int j = 0; j < kSortThreads; ++j) {
+      const int32_t x = pre[j];
+      pre[j] = s;
+      s += x;
+    }
+  }
+  __syncthreads();
+  int32_t s = pre[threadIdx.x];
+  for (int k = 0; k < kSortPer; ++k) {
+    if (base + k < n) {
+      const int32_t x = in[base + k];
+      out[base + k] = s;
+      s += x;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------- host side
 
 static inline dim3 grid_for(int64_t n, int per = 256) {
@@ -183,59 +338,69 @@ hipError_t setup_normalize(int m, const int32_t* rp, double* v, const double* b,
   return hipGetLastError();
 }
 
-// CSR(K) -> CSR(K'): stable radix sort of the nonzero positions by column.
+// Exclusive scan of n counts into out[0..n) (tile sums in `sums`, which holds
+// ceil(n / kSortTile) entries).
+static void scan_counts(int64_t n, const int32_t* in, int32_t* out, int32_t* sums, hipStream_t s) {
+  if (n <= 0) return;
+  const int nt = (int)((n + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kSortThreads), 0, s, n, in, sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nt, sums);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kSortThreads), 0, s, n, in, sums, out);
+}
+
+// CSR(K) -> CSR(K'): stable sort of the nonzero positions by column (the
+// radix sort above), the column counts scanned into the row pointers of K'.
 hipError_t setup_transpose(int m, int n, int64_t nnz, const int32_t* ci, const double* v, const int32_t* rowid,
                            int32_t* rpT, int32_t* ciT, double* vT, int32_t* rowidT, int32_t* perm_out,
                            hipStream_t s) {
+  (void)m;
   hipError_t e;
-  int32_t *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *cnt = nullptr;
-  void* tmp = nullptr;
-  size_t tmp_bytes = 0, scan_bytes = 0;
+  int32_t *ka = nullptr, *kb = nullptr, *va = nullptr, *vb = nullptr, *cnt = nullptr, *hist = nullptr,
+          *sums = nullptr;
   const int64_t nz = nnz > 0 ? nnz : 1;
-  if ((e = hipMalloc(&keys_in, nz * sizeof(int32_t))) != hipSuccess) return e;
-  if ((e = hipMalloc(&keys_out, nz * sizeof(int32_t))) != hipSuccess) goto out;
-  if ((e = hipMalloc(&vals_in, nz * sizeof(int32_t))) != hipSuccess) goto out;
+  const int ntiles = (int)((nz + kSortTile - 1) / kSortTile);
+  const int64_t nhist = (int64_t)kRadix * ntiles;
+  const int64_t nsum = std::max<int64_t>((nhist + kSortTile - 1) / kSortTile, ((int64_t)n + 1 + kSortTile - 1) / kSortTile);
+  if ((e = hipMalloc(&ka, nz * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = hipMalloc(&kb, nz * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&va, nz * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&vb, nz * sizeof(int32_t))) != hipSuccess) goto out;
   if ((e = hipMalloc(&cnt, (size_t)(n + 1) * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&hist, (size_t)nhist * sizeof(int32_t))) != hipSuccess) goto out;
+  if ((e = hipMalloc(&sums, (size_t)std::max<int64_t>(nsum, 1) * sizeof(int32_t))) != hipSuccess) goto out;
   if (nnz > 0) {
-    int end_bit = 1;
-    while (end_bit < 31 && (1ll << end_bit) < (long long)n) ++end_bit;
-    if ((e = hipMemcpyAsync(keys_in, ci, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
-    hipLaunchKernelGGL(k_iota, grid_for(nnz), dim3(256), 0, s, nnz, vals_in);
-    if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys_in, keys_out, vals_in, perm_out, (int)nnz,
-                                                0, end_bit, s)) != hipSuccess)
-      goto out;
-  }
-  if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, cnt, rpT, n + 1, s)) != hipSuccess) goto out;
-  if (scan_bytes > tmp_bytes) tmp_bytes = scan_bytes;
-  if ((e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1)) != hipSuccess) goto out;
-  if (nnz > 0) {
-    size_t tb = tmp_bytes;
-    int end_bit = 1;
-    while (end_bit < 31 && (1ll << end_bit) < (long long)n) ++end_bit;
-    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys_in, keys_out, vals_in, perm_out, (int)nnz, 0, end_bit,
-                                                s)) != hipSuccess)
-      goto out;
+    int bits = 1;
+    while (bits < 31 && (1ll << bits) < (long long)n) ++bits;
+    if ((e = hipMemcpyAsync(ka, ci, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
+    hipLaunchKernelGGL(k_iota, grid_for(nnz), dim3(256), 0, s, nnz, va);
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kSortThreads), 0, s, nnz, ka, shift, hist, ntiles);
+      scan_counts(nhist, hist, hist, sums, s);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kSortThreads), 0, s, nnz, ka, va, shift, hist, ntiles,
+                         kb, vb);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
+    if ((e = hipMemcpyAsync(perm_out, va, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
   }
   if ((e = hipMemsetAsync(cnt, 0, (size_t)(n + 1) * sizeof(int32_t), s)) != hipSuccess) goto out;
   if (nnz > 0) hipLaunchKernelGGL(k_col_count, grid_for(nnz), dim3(256), 0, s, nnz, ci, cnt);
-  {
-    size_t tb = tmp_bytes;
-    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, rpT, n + 1, s)) != hipSuccess) goto out;
-  }
+  scan_counts((int64_t)n + 1, cnt, rpT, sums, s);
   if (nnz > 0) {
     hipLaunchKernelGGL(k_transpose_fill, grid_for(nnz), dim3(256), 0, s, nnz, perm_out, rowid, v, ciT, vT);
     // row ids of K' entries are the column indices of K in sorted order
-    if ((e = hipMemcpyAsync(rowidT, keys_out, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
-      goto out;
+    if ((e = hipMemcpyAsync(rowidT, ka, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
   }
   e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
 out:
-  (void)hipFree(keys_in);
-  (void)hipFree(keys_out);
-  (void)hipFree(vals_in);
+  (void)hipFree(ka);
+  (void)hipFree(kb);
+  (void)hipFree(va);
+  (void)hipFree(vb);
   (void)hipFree(cnt);
-  (void)hipFree(tmp);
+  (void)hipFree(hist);
+  (void)hipFree(sums);
   return e;
 }
 
