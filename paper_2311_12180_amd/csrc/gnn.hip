@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace gnnk {
 
 constexpr int kH = 64;
@@ -252,21 +254,30 @@ __global__ __launch_bounds__(kBlock) void k_head(int N, const float* __restrict_
   }
 }
 
-// Per LP (one workgroup each) of the range: pool = [mean h_v | mean h_c] and
-// oh = pool . w_o + b_o.  voff / coff are the LPs' node offsets relative to the
-// range.
-__global__ __launch_bounds__(kBlock) void k_pool(int count, const int32_t* __restrict__ voff,
-                                                 const int32_t* __restrict__ coff, int v0, int c0,
-                                                 const float* __restrict__ Hv, const float* __restrict__ Hc,
-                                                 const float* __restrict__ wo, const float* __restrict__ bo,
-                                                 float* __restrict__ pool, float* __restrict__ oh) {
+// Pooling for the omega head, pool = [mean h_v | mean h_c] per LP of the
+// range and oh = pool . w_o + b_o, in two kernels so that a range of a few
+// LPs still spreads over the chip: each LP's nodes are cut into kPoolSlices
+// contiguous slices, one workgroup sums a slice (its wavefronts striding over
+// the nodes, then added in wavefront order), and a wavefront per LP adds the
+// slices in order.  voff / coff are the LPs' node offsets relative to the range.
+constexpr int kPoolSlices = 16;
+
+__global__ __launch_bounds__(kBlock) void k_pool_part(int count, const int32_t* __restrict__ voff,
+                                                      const int32_t* __restrict__ coff, int v0, int c0,
+                                                      const float* __restrict__ Hv, const float* __restrict__ Hc,
+                                                      float* __restrict__ part) {
   __shared__ float red[2][kBlock / 64][kH];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+  for (int t = blockIdx.x; t < count * kPoolSlices; t += gridDim.x) {
+    const int k = t / kPoolSlices, sl = t % kPoolSlices;
     const int jb = voff[k] - v0, je = voff[k + 1] - v0, ib = coff[k] - c0, ie = coff[k + 1] - c0;
+    const int j0 = jb + (int)((int64_t)(je - jb) * sl / kPoolSlices);
+    const int j1 = jb + (int)((int64_t)(je - jb) * (sl + 1) / kPoolSlices);
+    const int i0 = ib + (int)((int64_t)(ie - ib) * sl / kPoolSlices);
+    const int i1 = ib + (int)((int64_t)(ie - ib) * (sl + 1) / kPoolSlices);
     float sv = 0.f, sc = 0.f;
-    for (int j = jb + wave; j < je; j += kBlock / 64) sv += Hv[(size_t)j * kH + lane];
-    for (int i = ib + wave; i < ie; i += kBlock / 64) sc += Hc[(size_t)i * kH + lane];
+    for (int j = j0 + wave; j < j1; j += kBlock / 64) sv += Hv[(size_t)j * kH + lane];
+    for (int i = i0 + wave; i < i1; i += kBlock / 64) sc += Hc[(size_t)i * kH + lane];
     red[0][wave][lane] = sv;
     red[1][wave][lane] = sc;
     __syncthreads();
@@ -276,14 +287,32 @@ __global__ __launch_bounds__(kBlock) void k_pool(int count, const int32_t* __res
         a += red[0][q][lane];
         c += red[1][q][lane];
       }
-      a = je > jb ? a / (float)(je - jb) : 0.f;
-      c = ie > ib ? c / (float)(ie - ib) : 0.f;
-      pool[(size_t)k * 128 + lane] = a;
-      pool[(size_t)k * 128 + kH + lane] = c;
-      const float s = wave_sum(a * wo[lane] + c * wo[kH + lane]);
-      if (lane == 0) oh[k] = s + bo[0];
+      part[(size_t)t * 2 * kH + lane] = a;
+      part[(size_t)t * 2 * kH + kH + lane] = c;
     }
     __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_fin(int count, const int32_t* __restrict__ voff,
+                                                     const int32_t* __restrict__ coff,
+                                                     const float* __restrict__ part, const float* __restrict__ wo,
+                                                     const float* __restrict__ bo, float* __restrict__ pool,
+                                                     float* __restrict__ oh) {
+  const int lane = threadIdx.x & 63;
+  for (int k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); k < count; k += gridDim.x * (kBlock / 64)) {
+    const int nv = voff[k + 1] - voff[k], nc = coff[k + 1] - coff[k];
+    float a = 0.f, c = 0.f;
+    for (int sl = 0; sl < kPoolSlices; ++sl) {
+      a += part[((size_t)k * kPoolSlices + sl) * 2 * kH + lane];
+      c += part[((size_t)k * kPoolSlices + sl) * 2 * kH + kH + lane];
+    }
+    a = nv > 0 ? a / (float)nv : 0.f;
+    c = nc > 0 ? c / (float)nc : 0.f;
+    pool[(size_t)k * 128 + lane] = a;
+    pool[(size_t)k * 128 + kH + lane] = c;
+    const float s = wave_sum(a * wo[lane] + c * wo[kH + lane]);
+    if (lane == 0) oh[k] = s + bo[0];
   }
 }
 
@@ -579,12 +608,36 @@ __global__ __launch_bounds__(kBlock) void k_embed_bwd(int N, int fdim, const flo
   }
 }
 
-// g[e] (+)= sum over the nparts partials of entry e, in partial order.
-__global__ void k_sum_parts(int nparts, int width, const float* __restrict__ part, float* __restrict__ g) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < width; e += gridDim.x * blockDim.x) {
+// g[e] = sum over the nparts partials of entry e: a workgroup per 64
+// entries, wavefront w summing partials w, w + 4, ... (eight loads in flight),
+// the four wavefront sums then added in order.
+__global__ __launch_bounds__(kBlock) void k_sum_parts(int nparts, int width, const float* __restrict__ part,
+                                                      float* __restrict__ g) {
+  __shared__ float red[kBlock / 64][64];
+  constexpr int kW = kBlock / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e0 = blockIdx.x * 64; e0 < width; e0 += gridDim.x * 64) {
+    const int e = e0 + lane;
     float s = 0.f;
-    for (int q = 0; q < nparts; ++q) s += part[(size_t)q * width + e];
-    g[e] = s;
+    if (e < width) {
+      int q = w;
+      for (; q + 7 * kW < nparts; q += 8 * kW) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(q + u * kW) * width + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; q < nparts; q += kW) s += part[(size_t)q * width + e];
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e < width) {
+      float t = red[0][lane];
+      for (int k = 1; k < kW; ++k) t += red[k][lane];
+      g[e] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -665,9 +718,14 @@ void launch_head(int N, const float* H, const float* w, const float* b, float* o
   hipLaunchKernelGGL(k_head, dim3(grid_for((int64_t)N * kH)), dim3(kBlock), 0, s, N, H, w, b, out);
 }
 void launch_pool(int count, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* Hv,
-                 const float* Hc, const float* wo, const float* bo, float* pool, float* oh, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool, dim3(count < 8192 ? count : 8192), dim3(kBlock), 0, s, count, voff, coff, v0, c0, Hv, Hc,
-                     wo, bo, pool, oh);
+                 const float* Hc, const float* wo, const float* bo, float* pool, float* poolpart, float* oh,
+                 hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t tasks = (int64_t)count * kPoolSlices;
+  hipLaunchKernelGGL(k_pool_part, dim3((unsigned)std::min<int64_t>(tasks, 16384)), dim3(kBlock), 0, s, count, voff,
+                     coff, v0, c0, Hv, Hc, poolpart);
+  hipLaunchKernelGGL(k_pool_fin, dim3((unsigned)std::min<int64_t>((count + kBlock / 64 - 1) / (kBlock / 64), 4096)), dim3(kBlock), 0, s, count,
+                     voff, coff, poolpart, wo, bo, pool, oh);
 }
 void launch_loss(int count, int first, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* xh,
                  const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float wx,
@@ -714,7 +772,8 @@ void launch_embed_bwd(int N, int fdim, const float* F, const float* dH, const fl
   hipLaunchKernelGGL(k_embed_bwd, dim3(embed_bwd_grid(N)), dim3(kBlock), 0, s, N, fdim, F, dH, H, part);
 }
 void launch_sum_parts(int nparts, int width, const float* part, float* g, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(width)), dim3(kBlock), 0, s, nparts, width, part, g);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::max(1, (width + 63) / 64)), dim3(kBlock), 0, s, nparts, width,
+                     part, g);
 }
 void launch_adam(int n, float* th, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t s) {

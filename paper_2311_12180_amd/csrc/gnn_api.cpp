@@ -39,7 +39,8 @@ void launch_gemm_fwd(int N, const float* A0, const float* A1, const unsigned sho
                      hipStream_t s);
 void launch_head(int N, const float* H, const float* w, const float* b, float* out, hipStream_t s);
 void launch_pool(int count, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* Hv,
-                 const float* Hc, const float* wo, const float* bo, float* pool, float* oh, hipStream_t s);
+                 const float* Hc, const float* wo, const float* bo, float* pool, float* poolpart, float* oh,
+                 hipStream_t s);
 void launch_loss(int count, int first, const int32_t* voff, const int32_t* coff, int v0, int c0, const float* xh,
                  const float* yh, const float* oh, const float* xt, const float* yt, const float* ot, float wx,
                  float wy, float wo, float* dxh, float* dyh, float* doh, double* loss, hipStream_t s);
@@ -113,6 +114,7 @@ struct pdlp_gnn {
   float *dhv = nullptr, *dhv2 = nullptr, *dmv = nullptr, *dhc = nullptr, *dhc2 = nullptr, *dmc = nullptr;
   float *xh = nullptr, *yh = nullptr, *dxh = nullptr, *dyh = nullptr;
   float *oh = nullptr, *doh = nullptr, *pool = nullptr;
+  float* poolpart = nullptr;   // per LP and node slice: partial sums of the pooling
   double *loss = nullptr, *x0 = nullptr, *y0 = nullptr, *om0 = nullptr;
   float* part = nullptr;
   std::string err = "no error";
@@ -175,6 +177,7 @@ struct pdlp_gnn {
     oh = dalloc<float>(cap_k, act);
     doh = dalloc<float>(cap_k, act);
     pool = dalloc<float>((size_t)cap_k * 2 * kH, act);
+    poolpart = dalloc<float>((size_t)cap_k * 16 * 2 * kH, act);
     loss = dalloc<double>(cap_k, act);
     x0 = dalloc<double>(cap_v, act);
     y0 = dalloc<double>(cap_c, act);
@@ -382,7 +385,7 @@ void forward(pdlp_gnn* g, const Range& R) {
   launch_head(R.nv, g->hv[kRounds], th + kWx, th + kWx + kH, g->xh, s);
   launch_head(R.nc, g->hc[kRounds], th + kWy, th + kWy + kH, g->yh, s);
   launch_pool(R.K, g->col_off + R.first, g->row_off + R.first, R.v0, R.c0, g->hv[kRounds], g->hc[kRounds],
-              th + kWo, th + kWo + 2 * kH, g->pool, g->oh, s);
+              th + kWo, th + kWo + 2 * kH, g->pool, g->poolpart, g->oh, s);
 }
 
 // Weight-gradient partials of one transform, summed into grad[off ..].
