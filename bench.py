@@ -412,13 +412,17 @@ def main():
     # per-kernel durations (HIP events on the solver's stream) and the roofline
     ms_a, ms_b = P.pdlp_profile_attempts(h, args.profile_attempts)
     by_a, by_b = P.pdlp_step_bytes(h)
-    # a step is one kernel (row blocks), two (column panels: segment sums, then rows) or three
-    # (LDS-staged panels: long-row segment sums, short-row segment sums, then rows)
+    # a step is one kernel (row blocks, SELL-64 chunks) or two (column panels: segment sums, then
+    # rows; LDS-staged panels: the long rows' panel segment sums, then the row pass)
     names = {0: "{}<{}>", 1: "k_seg<{1}> + k_rows<{1}>", 2: "{}<{}> (XCD-contiguous blocks)",
-             3: "k_stage<{1}> + k_seg<{1}> + k_rows<{1}> (LDS-staged panels)"}
+             3: "k_stage<{1}> + k_stage_rows<{1}> (LDS-staged panels)"}
     lk, lt = info["layout_k"], info["layout_kt"]
 
     def kname(lay, op):
+        if lay & 64:
+            cfg = (lay >> 4) & 3
+            return (f"k_sell<{op}> (SELL-64 chunks, " +
+                    ("256-thread workgroups)" if cfg == 2 else f"{1024 >> cfg}-thread workgroups, LDS slice of y)"))
         if (lay & 3) == 3:
             return names[3].format("", op) + f" ({256 << (lay >> 4)}-thread staging workgroups)"
         return (names[lay & 3].format("k_fused", op) + (" (persistent grid)" if lay & 4 else "") +

@@ -106,7 +106,15 @@ typedef struct {
                                  16,384 columns whose slice of the gathered vector a workgroup of
                                  256, 512 or 1024 threads copies into LDS once, the other rows
                                  are swept directly -- with column panels on a persistent grid
-                                 for the evaluation passes.  The timing at create tries every
+                                 for the evaluation passes; or 64, 80, 96: the step pass runs
+                                 on SELL-64 chunks -- 64 consecutive rows stored
+                                 lane-interleaved, one row per lane, zero-padded to the chunk's
+                                 longest row (built automatically when the padding stays within
+                                 1/8; with row_order the rows of K' come by descending length) --
+                                 in workgroups of 1024 or 512 threads that first copy the
+                                 leading 8192 entries of the gathered vector into LDS (64, 80),
+                                 or of 256 threads without that copy (96); the evaluation passes
+                                 as for 3.  The timing at create tries every
                                  combination on matrices with 2^20 nonzeros or more.  The
                                  layout changes the order of floating-point sums; fix it for
                                  bitwise reproducibility across handles.  This field applies to
@@ -165,10 +173,15 @@ typedef struct {
                                  descending number of nonzeros, equal counts by first column
                                  (after the scaling, so D1, D2 and K~ are unchanged): on LPs with
                                  skewed row lengths the gathers of y and of x then hit the caches
-                                 far more often.  Only the order of floating-point sums changes;
-                                 every vector crossing this interface (y, D1, K~, warm starts)
-                                 stays in the caller's row order.  0 = the given order.  Batch
-                                 handles keep the given order */
+                                 far more often.  On LPs with 2^20 nonzeros or more it first
+                                 renumbers the columns: sorted by descending number of nonzeros,
+                                 cut into groups of 64, the groups dealt out over the column
+                                 range (16,384-column strides), so that the rows of K' fill
+                                 SELL-64 chunks with little padding while every wide column range
+                                 keeps columns of every count.  2 = rows and columns at any size.  Only the order of floating-point sums
+                                 changes; every vector crossing this interface (x, y, reduced
+                                 costs, D1, D2, K~, warm starts) stays in the caller's order.
+                                 0 = the given order.  Batch handles keep the given order */
 } pdlp_options;
 
 typedef struct {
@@ -185,7 +198,8 @@ typedef struct {
   double solve_s;             /* pdlp_solve wall time */
   int32_t layout_k, layout_kt;  /* layouts in use for K and K' (values of spmv_layout: 0, 1, 2,
                                    plus 4 for a persistent grid, plus 8 for the wide step tiles,
-                                   or 3, 19, 35 for LDS-staged step passes);
+                                   or 3, 19, 35 for LDS-staged step passes, or 64, 80, 96 for
+                                   SELL-64 step passes);
                                    for an LP of a batch: its sweeps of K and K' (see
                                    pdlp_batch_schedule) */
   int64_t handoff_k;          /* an LP of a batch: accepted steps when the single-LP kernels took

@@ -14,6 +14,8 @@
 //            serving panel i % 8 only (one XCD per panel, so the gathered
 //            slice of the vector stays in that XCD's L2), phase 2 adds each
 //            row's segment sums in panel order and runs the epilogue.
+// The step passes may also take an LDS-staged panel layout (long rows) or a
+// SELL-64 layout (one row per lane), both described at their kernels.
 // No workgroup reads another workgroup's results inside a launch: reductions
 // leave one partial per workgroup and a single-workgroup kernel after the
 // launch adds them in a fixed order.
@@ -240,6 +242,82 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
   }
   if constexpr (Op::NACC > 0) {
     block_sum<Op::NACC>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < Op::NACC; ++k) Op::part(p)[Op::NACC * blockIdx.x + k] = acc[k];
+    }
+  }
+}
+
+// SELL-64 step pass (layout 4) on a persistent grid: wavefront w of the grid
+// takes chunks w, w + (waves of the grid), ...; each lane sums its row's
+// entries in stored order (coalesced loads of the lane-interleaved entries,
+// kU of them in flight) and runs the epilogue.  With HOT, the workgroup first
+// copies the leading S.hot entries of the gathered vector into LDS, and
+// gathers below S.hot read that copy.  One reduction partial per workgroup.
+template <class Op, typename VT, int BS, bool HOT>
+__global__ __launch_bounds__(BS) void k_sell(Params p) {
+  static_assert(Op::NV == 1, "the SELL step view gathers one vector");
+  constexpr int kWaves = BS / 64;
+  constexpr int kU = 8;
+  __shared__ double xs[HOT ? kSellHot : 1];
+  __shared__ double red[AccSize<Op>::N * kWaves];
+  if (Op::idle(p, p.st)) return;
+  const Op op(p, p.st);
+  const DevCsr& M = Op::mat(p);
+  const SellCsr& S = M.sel;
+  const int hot = HOT ? S.hot : 0;
+  if (HOT) {
+    for (int j0 = 0; j0 < hot; j0 += kU * BS) {
+      double g[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * BS + (int)threadIdx.x;
+        op.gather(j < hot ? j : hot - 1, &g[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * BS + (int)threadIdx.x;
+        if (j < hot) xs[j] = g[u];
+      }
+    }
+    __syncthreads();
+  }
+  const VT* __restrict__ vals = pick<VT>(S.sv, S.svf);
+  const int32_t* __restrict__ sci = S.sci;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double acc[AccSize<Op>::N];
+#pragma unroll
+  for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
+  for (int c = blockIdx.x * kWaves + wv; c < S.nchunks; c += gridDim.x * kWaves) {
+    const int len = S.clen[c];
+    const int base = S.coff[c] + lane;
+    double sum = 0.0;
+    for (int k = 0; k < len; k += kU) {
+      int col[kU];
+      double a[kU], g[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k + u < len) {
+          col[u] = sci[base + (k + u) * 64];
+          a[u] = (double)vals[base + (k + u) * 64];
+        }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k + u < len) {
+          if (HOT && col[u] < hot) g[u] = xs[col[u]];
+          else op.gather(col[u], &g[u]);
+        }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k + u < len) sum += a[u] * g[u];
+    }
+    const int r = c * 64 + lane;
+    if (r < M.nrows) op.epi(r, &sum, acc);
+  }
+  if constexpr (Op::NACC > 0) {
+    block_sum<Op::NACC, kWaves>(acc, red);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int k = 0; k < Op::NACC; ++k) Op::part(p)[Op::NACC * blockIdx.x + k] = acc[k];
@@ -524,6 +602,16 @@ static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
   hipLaunchKernelGGL((k_stage_rows<Op, VT>), dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), 0, s, p);
 }
 
+// A step pass in the SELL-64 layout (sel.cfg selects the workgroup size and
+// whether the leading gathered entries are staged in LDS).
+template <class Op, typename VT>
+static void launch_sell(const Params& p, const DevCsr& M, hipStream_t s) {
+  const SellCsr& S = M.sel;
+  if (S.cfg == 0) hipLaunchKernelGGL((k_sell<Op, VT, 1024, true>), dim3(S.grid), dim3(1024), 0, s, p);
+  else if (S.cfg == 1) hipLaunchKernelGGL((k_sell<Op, VT, 512, true>), dim3(S.grid), dim3(512), 0, s, p);
+  else hipLaunchKernelGGL((k_sell<Op, VT, 256, false>), dim3(S.grid), dim3(256), 0, s, p);
+}
+
 // A step pass over a step view: the view replaces the matrix in the kernels'
 // parameters, and its tiling picks the kernels.
 template <class Op, int WHICH>
@@ -534,6 +622,9 @@ static void launch_view(const Params& p, hipStream_t s) {
   if (M.layout == 3) {
     if (q.use_f32) launch_staged<Op, float>(q, M, s);
     else launch_staged<Op, double>(q, M, s);
+  } else if (M.layout == 4) {
+    if (q.use_f32) launch_sell<Op, float>(q, M, s);
+    else launch_sell<Op, double>(q, M, s);
   } else if (M.tile == kTileWide) {
     if (q.use_f32) launch_op<Op, float, kTileWide>(q, M, s);
     else launch_op<Op, double, kTileWide>(q, M, s);

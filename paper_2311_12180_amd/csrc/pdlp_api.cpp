@@ -211,9 +211,12 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
 // nonzeros -- are cut into panels of kStageWidth columns; each panel's
 // segments are sorted by length (longest first, then by row), numbered in
 // that order and grouped in chunks of kStageLanes, stored lane-interleaved
-// with zero padding up to the chunk's longest segment.  Each panel's chunks
-// are cut into `per_panel` work items of about equal entry counts.  The rows
-// [rlong, nrows) are cut into plain row blocks.
+// with zero padding up to the chunk's longest segment.  The panels' chunks
+// are cut into at most `items` work items (one per CU: a single wave), each
+// panel into runs of about equal entry counts, as many per panel as the
+// smallest item size allows -- so panels of unequal weight (columns of
+// unequal counts) still give items of about equal work.  The rows [rlong,
+// nrows) are cut into plain row blocks.
 struct HostStaged {
   int32_t rlong = 0, nseg = 0;
   int64_t nnz_long = 0, nent = 0;
@@ -224,13 +227,6 @@ struct HostStaged {
 
 constexpr int kStageMinLen = 128;   // nonzeros of a row summed through the staged panels
 
-// Work items per panel: one workgroup per CU of the chip's 256 in a single
-// wave when the panels are fewer than the CUs.
-int stage_items_per_panel(int ncols) {
-  const int np = (ncols + kStageWidth - 1) / kStageWidth;
-  return std::max(1, 256 / std::max(np, 1));
-}
-
 // Nonzeros of the leading rows with at least min_len nonzeros.
 int64_t leading_long_nnz(const int32_t* rp, int nrows, int min_len) {
   int r = 0;
@@ -238,7 +234,7 @@ int64_t leading_long_nnz(const int32_t* rp, int nrows, int min_len) {
   return (int64_t)rp[r] - rp[0];
 }
 
-HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int ncols, int min_len, int per_panel) {
+HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int ncols, int min_len, int items) {
   HostStaged H;
   int rl = 0;
   while (rl < nrows && rp[rl + 1] - rp[rl] >= min_len) ++rl;
@@ -313,14 +309,34 @@ HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int nco
       H.pci[(size_t)pos] = (uint16_t)(ci[e] - p * kStageWidth);
     }
   }
-  // work items: each panel's chunks cut into per_panel runs of about equal entries
+  // work items: the smallest item size T whose per-panel item counts
+  // ceil(entries / T) (at most one per chunk) add up to at most `items`;
+  // each panel's chunks are then cut into that many runs of about equal entries
+  std::vector<int64_t> ptot((size_t)np, 0);
+  for (int p = 0; p < np; ++p) {
+    const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
+    if (a < b) ptot[(size_t)p] = (b < (int32_t)H.coff.size() ? (int64_t)H.coff[(size_t)b] : ent) - H.coff[(size_t)a];
+  }
+  auto count_for = [&](int64_t T, int p) {
+    const int64_t nc = chunk0[(size_t)p + 1] - chunk0[(size_t)p];
+    return std::min<int64_t>(nc, (ptot[(size_t)p] + T - 1) / T);
+  };
+  int64_t lo = 1, hi = std::max<int64_t>(ent, 1);
+  while (lo < hi) {
+    const int64_t T = lo + (hi - lo) / 2;
+    int64_t tot_items = 0;
+    for (int p = 0; p < np; ++p) tot_items += count_for(T, p);
+    if (tot_items <= std::max(items, np)) hi = T;
+    else lo = T + 1;
+  }
   H.wchunk.push_back(0);
   for (int p = 0; p < np; ++p) {
     const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
     if (a == b) continue;
     const int64_t e0 = H.coff[(size_t)a];
-    const int64_t tot = (b < (int32_t)H.coff.size() ? (int64_t)H.coff[(size_t)b] : ent) - e0;
-    int k = 1;
+    const int64_t tot = ptot[(size_t)p];
+    const int64_t per_panel = std::max<int64_t>(1, count_for(lo, p));
+    int64_t k = 1;
     for (int32_t c = a; c < b; ++c) {
       const int64_t done = (int64_t)H.coff[(size_t)c] - e0 + (int64_t)kStageLanes * H.clen[(size_t)c];
       if (c + 1 == b || (k < per_panel && done * per_panel >= tot * k)) {
@@ -377,6 +393,8 @@ struct pdlp_handle {
   // the LDS-staged layouts of K and K' a step view may take
   StagedCsr stg[2] = {};
   bool has_stg[2] = {false, false};
+  SellCsr sel[2] = {};
+  bool has_sel[2] = {false, false};
   // device of the handle, and the sizes (doubles) of the reduction partials
   // that pdlp_solve_noalloc places in the static scratch
   int device = 0;
@@ -434,6 +452,10 @@ struct pdlp_handle {
   // rperm[r] of the LP given to the device (empty: the identity); rp_given and
   // rp_dev are K's row pointers in the two numberings
   std::vector<int32_t> rperm, rp_given, rp_dev;
+  // column renumbering (single-LP handles, row_order = 2, or 1 on large LPs):
+  // device column j is column cperm[j] of the LP given to the device (empty:
+  // the identity)
+  std::vector<int32_t> cperm;
 
   // device row order <-> the given order, for vectors over the rows
   void rows_to_given(const double* dev, double* given) const {
@@ -441,6 +463,13 @@ struct pdlp_handle {
   }
   void rows_to_dev(const double* given, double* dev) const {
     for (size_t r = 0; r < rperm.size(); ++r) dev[r] = given[rperm[r]];
+  }
+  // device column order <-> the given order, for vectors over the columns
+  void cols_to_given(const double* dev, double* given) const {
+    for (size_t j = 0; j < cperm.size(); ++j) given[cperm[j]] = dev[j];
+  }
+  void cols_to_dev(const double* given, double* dev) const {
+    for (size_t j = 0; j < cperm.size(); ++j) dev[j] = given[cperm[j]];
   }
 
   template <typename T>
@@ -538,17 +567,18 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.trace < 0) return why = "trace must be >= 0", -1;
   if (o.poll_every < 1) return why = "poll_every must be >= 1", -1;
   if (o.graph != 0 && o.graph != 1) return why = "graph must be 0 or 1", -1;
-  // -1; 0, 1, 2 plus 4 and/or 8; 3, 19, 35 (LDS-staged step passes, phase-1 workgroups of 256, 512, 1024)
+  // -1; 0, 1, 2 plus 4 and/or 8; 3, 19, 35 (LDS-staged step passes, phase-1 workgroups of 256, 512, 1024);
+  // 64, 80, 96 (SELL-64 step passes)
   auto bad_layout = [](int v) {
-    if (v == 3 || v == 19 || v == 35) return false;
+    if (v == 3 || v == 19 || v == 35 || v == 64 || v == 80 || v == 96) return false;
     return v < -1 || v > 14 || (v >= 0 && (v & 3) == 3);
   };
   if (bad_layout(o.spmv_layout))
     return why = "spmv_layout must be -1, or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), "
-                 "or 3, 19, 35 (LDS-staged step passes)", -1;
+                 "or 3, 19, 35 (LDS-staged step passes), or 64, 80, 96 (SELL-64 step passes)", -1;
   if (o.spmv_layout_kt != -2 && bad_layout(o.spmv_layout_kt))
     return why = "spmv_layout_kt must be -2, -1, or 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), "
-                 "or 3, 19, 35 (LDS-staged step passes)", -1;
+                 "or 3, 19, 35 (LDS-staged step passes), or 64, 80, 96 (SELL-64 step passes)", -1;
   if (o.batch_lanes < -1 || o.batch_lanes > 64 || (o.batch_lanes > 0 && (o.batch_lanes & (o.batch_lanes - 1))))
     return why = "batch_lanes must be -1, 0 or a power of two up to 64", -1;
   if (o.batch_grid < 0) return why = "batch_grid must be >= 0", -1;
@@ -559,7 +589,7 @@ static int check_options(const pdlp_options& o, std::string& why) {
   if (o.infeas_every < 1) return why = "infeas_every must be >= 1", -1;
   if (o.presolve != 0 && o.presolve != 1) return why = "presolve must be 0 or 1", -1;
   if (o.restart_metric != 0 && o.restart_metric != 1) return why = "restart_metric must be 0 or 1", -1;
-  if (o.row_order != 0 && o.row_order != 1) return why = "row_order must be 0 or 1", -1;
+  if (o.row_order < 0 || o.row_order > 2) return why = "row_order must be 0, 1 or 2", -1;
   return 0;
 }
 
@@ -644,6 +674,91 @@ static int elem_grid(int n) {
   int g = (n + kBlock - 1) / kBlock;
   if (g > kElemBlocks) g = kElemBlocks;
   return g < 1 ? 1 : g;
+}
+
+// SELL-64 layout (see SellCsr), built on the host from the structure: chunk c
+// holds rows [64c, 64c + 64) lane-interleaved, zero-padded to its longest
+// row.  perm holds CSR indices (-1 on padding).  nent = -1: the entries would
+// not fit 32-bit offsets.
+struct HostSell {
+  int64_t nent = 0;
+  std::vector<int32_t> coff, clen, perm, sci;
+};
+
+HostSell build_sell(const int32_t* rp, const int32_t* ci, int nrows) {
+  HostSell H;
+  const int nch = (nrows + 63) / 64;
+  H.coff.resize((size_t)nch);
+  H.clen.resize((size_t)nch);
+  int64_t ent = 0;
+  for (int c = 0; c < nch; ++c) {
+    int32_t len = 0;
+    for (int r = 64 * c; r < std::min(nrows, 64 * c + 64); ++r) len = std::max(len, rp[r + 1] - rp[r]);
+    H.coff[(size_t)c] = (int32_t)std::min<int64_t>(ent, INT32_MAX);
+    H.clen[(size_t)c] = len;
+    ent += (int64_t)64 * len;
+  }
+  if (ent >= ((int64_t)1 << 31)) {
+    H.nent = -1;
+    return H;
+  }
+  H.nent = ent;
+  H.perm.assign((size_t)std::max<int64_t>(ent, 1), -1);
+  H.sci.assign((size_t)std::max<int64_t>(ent, 1), 0);
+  for (int r = 0; r < nrows; ++r) {
+    const int64_t at = H.coff[(size_t)(r / 64)] + (r % 64);
+    for (int32_t k = 0; k < rp[r + 1] - rp[r]; ++k) {
+      H.perm[(size_t)(at + 64 * k)] = rp[r] + k;
+      H.sci[(size_t)(at + 64 * k)] = ci[rp[r] + k];
+    }
+  }
+  return H;
+}
+
+// Device copy of a SELL-64 layout for the step view of matrix `which`, whose
+// step pass gathers a vector of `ngathered` entries (kept in h->sel until the
+// chooser or the option selects it).
+static void upload_sell(pdlp_handle* h, int which, const HostSell& H, int ngathered, const double* v,
+                        const float* vf) {
+  hipStream_t s = h->stream;
+  const hipMemcpyKind kind = hipMemcpyHostToDevice;
+  SellCsr& S = h->sel[which];
+  S = SellCsr{};
+  S.nchunks = (int32_t)H.coff.size();
+  S.hot = std::min(kSellHot, ngathered);
+  int32_t* coff = h->dalloc<int32_t>(H.coff.size());
+  int32_t* clen = h->dalloc<int32_t>(H.clen.size());
+  const int64_t ne = std::max<int64_t>(H.nent, 1);
+  int32_t* sci = h->dalloc<int32_t>((size_t)ne);
+  int32_t* perm = h->dalloc<int32_t>((size_t)ne);
+  double* sv = h->dalloc<double>((size_t)ne);
+  float* svf = vf ? h->dalloc<float>((size_t)ne) : nullptr;
+  if (!H.coff.empty()) {
+    check(hipMemcpyAsync(coff, H.coff.data(), H.coff.size() * 4, kind, s), "upload sell");
+    check(hipMemcpyAsync(clen, H.clen.data(), H.clen.size() * 4, kind, s), "upload sell");
+  }
+  if (H.nent > 0) {
+    check(hipMemcpyAsync(sci, H.sci.data(), (size_t)H.nent * 4, kind, s), "upload sell");
+    check(hipMemcpyAsync(perm, H.perm.data(), (size_t)H.nent * 4, kind, s), "upload sell");
+    check(setup_permute_values(H.nent, perm, v, vf, sv, svf, s), "permute sell");
+  }
+  check(hipStreamSynchronize(s), "sell sync");
+  S.coff = coff;
+  S.clen = clen;
+  S.sci = sci;
+  S.sv = sv;
+  S.svf = svf;
+  h->has_sel[which] = S.nchunks > 0;
+}
+
+// Workgroups of the SELL-64 launch for workgroup configuration cfg: two per
+// CU with the 64 KB LDS slice at 1024 threads, four at 512 threads (two
+// resident), sixteen per CU without it, and no more than the chunks need.
+static int sell_grid(const pdlp_handle* h, int cfg, int nchunks) {
+  const int cus = std::max(1, h->persist_grid / 8);
+  const int waves = cfg == 0 ? 16 : (cfg == 1 ? 8 : 4);
+  const int cap = cus * (cfg == 0 ? 2 : (cfg == 1 ? 4 : 16));
+  return std::max(1, std::min(cap, (nchunks + waves - 1) / waves));
 }
 
 // Device copy of a column-panel layout; the matrix keeps layout 0 until chosen.
@@ -825,11 +940,28 @@ static void choose_layouts(pdlp_handle* h) {
       V.stg.cfg = cfg;
       V.nred = V.stg.nlong_groups + V.stg.nrblocks;
     };
+    // the step view in the SELL-64 layout (workgroup configuration `cfg`),
+    // the evaluation view as for the staged layout
+    auto set_sell = [&](int cfg) {
+      set(has_pan ? 1 : 0, 0, 1, kTile);
+      V = M;
+      V.layout = 4;
+      V.tile = kTile;
+      V.remap = 0;
+      V.grid = 0;
+      V.sel = h->sel[which];
+      V.sel.cfg = cfg;
+      V.sel.grid = sell_grid(h, cfg, V.sel.nchunks);
+      V.nred = V.sel.grid;
+    };
     if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid, bit 3 the wide step tiles;
                        // 3 + 16 cfg: staged step view, column panels (else row blocks) on a persistent grid
-                       // for the evaluations
+                       // for the evaluations; 64 + 16 cfg: SELL-64 step view, the evaluations as for 3
       const int g = (mode & 4) ? 1 : 0, t = (mode & 8) ? kTileWide : kTile;
-      if ((mode & 3) == 0) set(0, 0, g, t);
+      if (mode & 64) {
+        if (h->has_sel[which]) set_sell((mode >> 4) & 3);
+        else set(has_pan ? 1 : 0, 0, 1, kTile);
+      } else if ((mode & 3) == 0) set(0, 0, g, t);
       else if ((mode & 3) == 2) set(0, 1, g, t);
       else if ((mode & 3) == 1) set(has_pan ? 1 : 0, 0, g, t);
       else if (h->has_stg[which]) set_staged((mode >> 4) & 3);
@@ -877,6 +1009,22 @@ static void choose_layouts(pdlp_handle* h) {
       }
       set(best_l, best_r, best_g, best_t);
       if (best_c >= 0) set_staged(best_c);
+    }
+    if (h->has_sel[which]) {
+      // (the current view is the best so far; keep a copy to come back to)
+      const DevCsr bm = M, bv = V;
+      int best_c = -1;
+      for (int cfg = 0; cfg < 3; ++cfg) {
+        set_sell(cfg);
+        const double t = time_probe(h, which, 6);
+        if (t < 0.98 * best) {
+          best = t;
+          best_c = cfg;
+        }
+      }
+      M = bm;
+      V = bv;
+      if (best_c >= 0) set_sell(best_c);
     }
     h->probe_ms[which] = best;
   }
@@ -1022,6 +1170,97 @@ static void scale_problem(pdlp_handle* h) {
     check(setup_to_f32(nnz, h->val, h->valf, s), "fp32 K");
     check(setup_to_f32(nnz, h->valT, h->valTf, s), "fp32 K'");
   }
+}
+
+// Column renumbering (row_order = 2, or 1 on LPs with 2^20 nonzeros or more):
+// the columns sorted by descending number of nonzeros (equal counts in the
+// given order) are cut into groups of 64, and the groups are dealt out over
+// the column range in kStageWidth-wide strides (group i of G goes to the
+// (i mod P)-th run, P = the number of kStageWidth-column panels).  Each run
+// of 64 columns then has (nearly) equal counts -- the SELL-64 chunks of K~'
+// need little padding -- while every wide column range still holds columns
+// of every count, as in the given order, so column panels keep balanced
+// entry counts.  Done after the scaling and before the row renumbering: K~'s
+// entries keep their place with new column indices, the rows of K~' move
+// whole, and c, l, u and D2 follow.  H.ci gets the new indices.
+static void renumber_cols(pdlp_handle* h, HostLP& H) {
+  const int32_t n = h->n;
+  const int64_t nnz = h->nnz;
+  const int ro = h->opt.row_order;
+  if (!(ro == 2 || (ro == 1 && nnz >= (1 << 20))) || n < 2) return;
+  std::vector<int32_t> cnt((size_t)n, 0);
+  for (int64_t e = 0; e < nnz; ++e) cnt[(size_t)H.ci[(size_t)e]]++;
+  std::vector<int32_t> perm((size_t)n);
+  for (int32_t j = 0; j < n; ++j) perm[(size_t)j] = j;
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int32_t a, int32_t b) { return cnt[(size_t)a] > cnt[(size_t)b]; });
+  {
+    // full groups of 64 dealt out over the panels; a last partial group stays last
+    const int32_t G = n / 64, P = std::max(1, (n + kStageWidth - 1) / kStageWidth);
+    std::vector<int32_t> dealt;
+    dealt.reserve((size_t)n);
+    for (int32_t r = 0; r < P; ++r)
+      for (int32_t i = r; i < G; i += P)
+        for (int l = 0; l < 64; ++l) dealt.push_back(perm[(size_t)i * 64 + l]);
+    for (int32_t j = G * 64; j < n; ++j) dealt.push_back(perm[(size_t)j]);
+    perm.swap(dealt);
+  }
+  bool ident = true;
+  for (int32_t j = 0; j < n && ident; ++j) ident = perm[(size_t)j] == j;
+  if (ident) return;
+  std::vector<int32_t> inv((size_t)n);
+  for (int32_t j = 0; j < n; ++j) inv[(size_t)perm[(size_t)j]] = j;
+  hipStream_t s = h->stream;
+  std::vector<int32_t> rpT((size_t)n + 1), rpT2((size_t)n + 1, 0), src((size_t)std::max<int64_t>(nnz, 1));
+  check(hipMemcpy(rpT.data(), h->rpT, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost), "read rowptr of K'");
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t o = perm[(size_t)j], b = rpT[(size_t)o], L = rpT[(size_t)o + 1] - b;
+    rpT2[(size_t)j + 1] = rpT2[(size_t)j] + L;
+    for (int32_t k = 0; k < L; ++k) src[(size_t)rpT2[(size_t)j] + k] = b + k;
+  }
+  const hipMemcpyKind kind = hipMemcpyHostToDevice, d2d = hipMemcpyDeviceToDevice;
+  // scratch of the move, freed before returning
+  std::vector<void*> tmp;
+  auto talloc = [&](size_t bytes) {
+    void* p = nullptr;
+    check(hipMalloc(&p, std::max<size_t>(bytes, 1)), "hipMalloc");
+    tmp.push_back(p);
+    return p;
+  };
+  try {
+    int32_t* d_src = static_cast<int32_t*>(talloc((size_t)nnz * 4));
+    int32_t* d_perm = static_cast<int32_t*>(talloc((size_t)n * 4));
+    int32_t* d_inv = static_cast<int32_t*>(talloc((size_t)n * 4));
+    int32_t* t_ci = static_cast<int32_t*>(talloc((size_t)nnz * 4));
+    double* t_v = static_cast<double*>(talloc((size_t)nnz * 8));
+    float* t_vf = h->valTf ? static_cast<float*>(talloc((size_t)nnz * 4)) : nullptr;
+    double* t_col = static_cast<double*>(talloc((size_t)n * 8));
+    if (nnz) check(hipMemcpyAsync(d_src, src.data(), (size_t)nnz * 4, kind, s), "upload renumbering");
+    check(hipMemcpyAsync(d_perm, perm.data(), (size_t)n * 4, kind, s), "upload renumbering");
+    check(hipMemcpyAsync(d_inv, inv.data(), (size_t)n * 4, kind, s), "upload renumbering");
+    // K~': rows moved whole
+    check(setup_permute(nnz, d_src, h->ciT, h->valT, h->valTf, t_ci, t_v, t_vf, s), "renumber K'");
+    if (nnz) {
+      check(hipMemcpyAsync(h->ciT, t_ci, (size_t)nnz * 4, d2d, s), "renumber K'");
+      check(hipMemcpyAsync(h->valT, t_v, (size_t)nnz * 8, d2d, s), "renumber K'");
+      if (h->valTf) check(hipMemcpyAsync(h->valTf, t_vf, (size_t)nnz * 4, d2d, s), "renumber K'");
+    }
+    check(hipMemcpyAsync(h->rpT, rpT2.data(), ((size_t)n + 1) * 4, kind, s), "renumber K'");
+    // K~: new column indices in place
+    check(setup_rename(nnz, d_inv, h->ci, s), "renumber K");
+    // column vectors
+    for (double* v : {h->c, h->l, h->u, h->D2}) {
+      check(setup_gather_rows(n, d_perm, v, t_col, s), "renumber columns");
+      check(hipMemcpyAsync(v, t_col, (size_t)n * 8, d2d, s), "renumber columns");
+    }
+    check(hipStreamSynchronize(s), "renumber sync");
+  } catch (const HipFail&) {
+    for (void* p : tmp) (void)hipFree(p);
+    throw;
+  }
+  for (void* p : tmp) (void)hipFree(p);
+  for (int64_t e = 0; e < nnz; ++e) H.ci[(size_t)e] = inv[(size_t)H.ci[(size_t)e]];
+  h->cperm = std::move(perm);
 }
 
 // Row renumbering for the locality of the gathers: rows by descending length,
@@ -1238,6 +1477,14 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
   }
   try {
     check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    {
+      hipDeviceProp_t prop;
+      int dev = 0;
+      check(hipGetDevice(&dev), "hipGetDevice");
+      check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+      h->persist_grid = std::max(8, prop.multiProcessorCount * 8);
+      h->device = dev;
+    }
     hipStream_t s = h->stream;
     const hipMemcpyKind kind = hipMemcpyHostToDevice;
     upload_normalize_transpose(h, H);
@@ -1259,6 +1506,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     double kmax;
     std::memcpy(&kmax, &hred[4], sizeof kmax);
     h->eta0 = kmax > 0.0 ? 1.0 / kmax : 1.0;
+    renumber_cols(h, H);
     renumber_rows(h, H);
     // --- row-block partitions and (optionally) the column-panel layouts
     std::vector<int32_t> hrpT((size_t)n + 1);
@@ -1285,12 +1533,13 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     // a panel layout pays when the gathered vector does not fit one XCD's L2;
     // spmv_layout = 1 builds it for any size (tests)
     const int mode_k = opt.spmv_layout, mode_kt = opt.spmv_layout_kt != -2 ? opt.spmv_layout_kt : opt.spmv_layout;
-    // (a staged code builds it under the size rule of the automatic choice,
-    // so that its evaluation passes take the same layout either way)
-    const bool want_k = (mode_k >= 0 && (mode_k & 3) == 1) ||
-                        ((mode_k == -1 || (mode_k & 3) == 3) && nnz >= (1 << 20) && n >= (1 << 18));
-    const bool want_kt = (mode_kt >= 0 && (mode_kt & 3) == 1) ||
-                         ((mode_kt == -1 || (mode_kt & 3) == 3) && nnz >= (1 << 20) && m >= (1 << 18));
+    // (a staged or SELL code builds it under the size rule of the automatic
+    // choice, so that its evaluation passes take the same layout either way)
+    auto step_code = [](int mode) { return mode == -1 || (mode & 3) == 3 || mode >= 64; };
+    const bool want_k = (mode_k >= 0 && mode_k < 64 && (mode_k & 3) == 1) ||
+                        (step_code(mode_k) && nnz >= (1 << 20) && n >= (1 << 18));
+    const bool want_kt = (mode_kt >= 0 && mode_kt < 64 && (mode_kt & 3) == 1) ||
+                         (step_code(mode_kt) && nnz >= (1 << 20) && m >= (1 << 18));
     {
       std::vector<int32_t> hciT;
       if (want_k) {
@@ -1314,7 +1563,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
       if (force_k || auto_k) {
         const int64_t nl = leading_long_nnz(H.rp.data(), m, kStageMinLen);
         if (force_k || 2 * nl >= nnz) {
-          HostStaged HS = build_staged(H.rp.data(), H.ci.data(), m, n, kStageMinLen, stage_items_per_panel(n));
+          HostStaged HS = build_staged(H.rp.data(), H.ci.data(), m, n, kStageMinLen, h->persist_grid / 8);
           upload_staged(h, 0, HS, n, h->val, h->valf);
         }
       }
@@ -1323,9 +1572,26 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
         if (force_kt || 2 * nl >= nnz) {
           std::vector<int32_t> hciT((size_t)std::max<int64_t>(nnz, 1));
           if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
-          HostStaged HS = build_staged(hrpT.data(), hciT.data(), n, m, kStageMinLen, stage_items_per_panel(m));
+          HostStaged HS = build_staged(hrpT.data(), hciT.data(), n, m, kStageMinLen, h->persist_grid / 8);
           upload_staged(h, 1, HS, m, h->valT, h->valTf);
         }
+      }
+    }
+    // the SELL-64 step layouts: when a matrix's rows, in their device
+    // numbering, fill chunks of 64 rows with at most 1/8 padding (under the
+    // size rule of the automatic choice), or for any size when forced
+    {
+      const bool force_k = mode_k >= 64, force_kt = mode_kt >= 64;
+      const bool auto_k = mode_k == -1 && nnz >= (1 << 20), auto_kt = mode_kt == -1 && nnz >= (1 << 20);
+      if (force_k || auto_k) {
+        HostSell HS = build_sell(H.rp.data(), H.ci.data(), m);
+        if (HS.nent >= 0 && (force_k || HS.nent * 8 <= nnz * 9)) upload_sell(h, 0, HS, n, h->val, h->valf);
+      }
+      if (force_kt || auto_kt) {
+        std::vector<int32_t> hciT((size_t)std::max<int64_t>(nnz, 1));
+        if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
+        HostSell HS = build_sell(hrpT.data(), hciT.data(), n);
+        if (HS.nent >= 0 && (force_kt || HS.nent * 8 <= nnz * 9)) upload_sell(h, 1, HS, m, h->valT, h->valTf);
       }
     }
     P.Ks = P.K;
@@ -1336,8 +1602,16 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     auto stg_red = [&](int w) {
       return h->has_stg[w] ? (size_t)(h->stg[w].nlong_groups + h->stg[w].nrblocks) : (size_t)0;
     };
-    const size_t redk = std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid, stg_red(0)});
-    const size_t redt = std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid, stg_red(1)});
+    auto sel_red = [&](int w) {
+      size_t g = 0;
+      if (h->has_sel[w])
+        for (int cfg = 0; cfg < 3; ++cfg) g = std::max(g, (size_t)sell_grid(h, cfg, h->sel[w].nchunks));
+      return g;
+    };
+    const size_t redk =
+        std::max({bk.size(), (size_t)h->wide_nblocks[0], (size_t)P.K.rows_grid, stg_red(0), sel_red(0)});
+    const size_t redt =
+        std::max({bt.size(), (size_t)h->wide_nblocks[1], (size_t)P.KT.rows_grid, stg_red(1), sel_red(1)});
     h->red_k = redk;
     h->red_t = redt;
     P.partA = h->dalloc<double>(redt);
@@ -1362,14 +1636,6 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     }
     check(hipStreamSynchronize(s), "setup sync");
     check(hipGetLastError(), "setup kernels");
-    {
-      hipDeviceProp_t prop;
-      int dev = 0;
-      check(hipGetDevice(&dev), "hipGetDevice");
-      check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-      h->persist_grid = std::max(8, prop.multiProcessorCount * 8);
-      h->device = dev;
-    }
     choose_layouts(h);
   } catch (const HipFail& f) {
     return create_failed(h, f);
@@ -1431,6 +1697,10 @@ extern "C" int pdlp_set_warm_start(pdlp_handle* h, const double* x0, const doubl
       h->rows_to_dev(y0, zy.data());
       y0 = zy.data();
     }
+    if (x0 && !h->cperm.empty()) {
+      h->cols_to_dev(x0, zx.data());
+      x0 = zx.data();
+    }
     check(hipMemcpy(h->wx, x0 ? x0 : zx.data(), (size_t)h->n * 8, hipMemcpyHostToDevice), "upload x0");
     if (h->m) check(hipMemcpy(h->wy, y0 ? y0 : zy.data(), (size_t)h->m * 8, hipMemcpyHostToDevice), "upload y0");
   } catch (const HipFail& f) {
@@ -1488,6 +1758,7 @@ static void finish_solve(pdlp_handle* h, double t0) {
   I.solve_s = now_s() - t0;
   auto code = [](const DevCsr& M, const DevCsr& V) {
     if (V.layout == 3) return 3 + 16 * V.stg.cfg;
+    if (V.layout == 4) return 64 + 16 * V.sel.cfg;
     return (M.layout == 1 ? 1 : (M.remap ? 2 : 0)) + (M.grid > 0 ? 4 : 0) + (V.tile == kTileWide ? 8 : 0);
   };
   I.layout_k = code(h->P.K, h->P.Ks);
@@ -1709,6 +1980,17 @@ static void download_rows(const pdlp_handle* h, double* dst, const double* dev, 
   h->rows_to_given(t.data(), dst);
 }
 
+// A device vector over the columns, in the given column order.
+static void download_cols(const pdlp_handle* h, double* dst, const double* dev, const char* what) {
+  if (h->cperm.empty()) {
+    check(hipMemcpy(dst, dev, (size_t)h->n * 8, hipMemcpyDeviceToHost), what);
+    return;
+  }
+  std::vector<double> t((size_t)h->n);
+  check(hipMemcpy(t.data(), dev, (size_t)h->n * 8, hipMemcpyDeviceToHost), what);
+  h->cols_to_given(t.data(), dst);
+}
+
 extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* rc, pdlp_info* info) {
   if (!h) return PDLP_ERR_ARG;
   if (h->count) return fail(h, PDLP_ERR_STATE, "pdlp_get_solution on a batch handle (use the _batch entry points)");
@@ -1719,9 +2001,9 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
     std::vector<double> xr((size_t)h->n), yr((size_t)std::max(h->m, 1)), lr((size_t)h->n);
     std::vector<double> xo((size_t)O.n), yo((size_t)std::max(O.m, 1)), lo((size_t)O.n);
     try {
-      check(hipMemcpy(xr.data(), h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
+      download_cols(h, xr.data(), h->xo, "download x");
       if (h->m) check(hipMemcpy(yr.data(), h->yo, (size_t)h->m * 8, hipMemcpyDeviceToHost), "download y");
-      check(hipMemcpy(lr.data(), h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
+      download_cols(h, lr.data(), h->rco, "download reduced costs");
     } catch (const HipFail& f) {
       return fail(h, PDLP_ERR_HIP, hip_msg(f));
     }
@@ -1762,9 +2044,9 @@ extern "C" int pdlp_get_solution(pdlp_handle* h, double* x, double* y, double* r
     return PDLP_OK;
   }
   try {
-    if (x) check(hipMemcpy(x, h->xo, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x");
+    if (x) download_cols(h, x, h->xo, "download x");
     if (y && h->m) download_rows(h, y, h->yo, "download y");
-    if (rc) check(hipMemcpy(rc, h->rco, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download reduced costs");
+    if (rc) download_cols(h, rc, h->rco, "download reduced costs");
   } catch (const HipFail& f) {
     return fail(h, PDLP_ERR_HIP, hip_msg(f));
   }
@@ -1780,7 +2062,7 @@ extern "C" int pdlp_get_iterate(pdlp_handle* h, double* x_hat, double* y_hat, pd
   try {
     DevState f;
     check(hipMemcpy(&f, h->st, sizeof f, hipMemcpyDeviceToHost), "read state");
-    if (x_hat) check(hipMemcpy(x_hat, h->P.x[f.cur], (size_t)h->n * 8, hipMemcpyDeviceToHost), "download x~");
+    if (x_hat) download_cols(h, x_hat, h->P.x[f.cur], "download x~");
     if (y_hat && h->m) download_rows(h, y_hat, h->P.y[f.cur], "download y~");
     if (st) {
       st->iterations = f.k;
@@ -1803,7 +2085,7 @@ extern "C" int pdlp_get_scaling(pdlp_handle* h, double* D1, double* D2, double* 
   if (h->presolved) return fail(h, PDLP_ERR_UNSUPPORTED, "pdlp_get_scaling on a presolved handle (the scaling is the reduced LP's)");
   try {
     if (D1 && h->m) download_rows(h, D1, h->D1, "download D1");
-    if (D2) check(hipMemcpy(D2, h->D2, (size_t)h->n * 8, hipMemcpyDeviceToHost), "download D2");
+    if (D2) download_cols(h, D2, h->D2, "download D2");
     if (val_scaled && h->nnz) {
       if (h->rperm.empty()) {
         check(hipMemcpy(val_scaled, h->val, (size_t)h->nnz * 8, hipMemcpyDeviceToHost), "download K~");

@@ -91,6 +91,30 @@ struct StagedCsr {
   const RowBlock* rblocks;  // [nrblocks] row blocks of the short rows [rlong, nrows)
 };
 
+// SELL-64 layout of a step view (layout 4): the rows are cut into chunks of
+// 64 consecutive rows, stored lane-interleaved (entry k of the chunk's row l
+// at coff + 64 k + l) and zero-padded to the chunk's longest row.  With the
+// rows numbered by descending length (columns renumbered for K~', rows for
+// K~) a chunk's rows have nearly equal lengths, so the padding is small.  A
+// wavefront sums a chunk, one row per lane, with coalesced loads and no
+// cross-lane reduction; each workgroup first copies the leading `hot` entries
+// of the gathered vector into LDS (the rows of the other matrix numbered
+// first are the longest, so their entries are gathered most often) and reads
+// them there.
+constexpr int kSellHot = 8192;   // leading gathered entries staged in LDS: 64 KB of FP64
+struct SellCsr {
+  int32_t nchunks;
+  int32_t hot;              // entries of the gathered vector staged in LDS (cfg 0, 1): min(kSellHot, its length)
+  int32_t cfg;              // 0: 1024-thread workgroups with the LDS slice; 1: 512 threads with it;
+                            // 2: 256 threads without it
+  int32_t grid;             // workgroups of the persistent launch (one reduction partial each)
+  const int32_t* coff;      // [nchunks] first entry of each chunk
+  const int32_t* clen;      // [nchunks] entries per lane (the chunk's longest row)
+  const int32_t* sci;       // column indices (0 on padding)
+  const double* sv;         // FP64 values (0 on padding)
+  const float* svf;         // FP32 values (nullptr unless FP32 steps)
+};
+
 struct DevCsr {
   const int32_t* rp;
   const int32_t* ci;
@@ -99,7 +123,8 @@ struct DevCsr {
   const RowBlock* blocks; // long rows first, then runs of short rows
   int32_t nblocks;
   int32_t nrows;
-  int32_t layout;         // 0: fused row blocks; 1: column panels (two phases); 3: LDS-staged panels (stg)
+  int32_t layout;         // 0: fused row blocks; 1: column panels (two phases); 3: LDS-staged panels (stg);
+                          // 4: SELL-64 chunks (sel)
   int32_t remap;          // fused layout: contiguous block ranges per XCD
   int32_t nred;           // reduction partials of a pass over this matrix
   int32_t rows_grid;      // grid of the phase-2 (row-wise) kernels
@@ -108,6 +133,7 @@ struct DevCsr {
   PanelCsr pan;
   int32_t tile;           // nonzeros per block of `blocks` and `pan.sblocks`: 0 = kTile, or kTileWide
   StagedCsr stg;          // layout 3 (step views only): LDS-staged panels of the long rows
+  SellCsr sel;            // layout 4 (step views only): SELL-64 chunks
 };
 
 // Solver state in device memory.  The first 16 bytes are the status word the

@@ -119,11 +119,14 @@ def test_rejects_bad_sizes_and_options(P):
     _bad(p, P, P.PDLP_ERR_ARG, "max_iter", max_iter=-1)
     _bad(p, P, P.PDLP_ERR_ARG, "kkt_omega_power", kkt_omega_power=3)
     # layouts: 0, 1, 2 plus 4 (persistent grid) and/or 8 (wide step tiles), or
-    # 3 + 16 cfg (LDS-staged step passes, cfg 0..2) with no other bit
-    for bad in (-2, 7, 11, 15, 16, 23, 27, 51, 67):
+    # 3 + 16 cfg (LDS-staged step passes, cfg 0..2) with no other bit, or
+    # 64 + 16 cfg (SELL-64 step passes, cfg 0..2) with no other bit
+    for bad in (-2, 7, 11, 15, 16, 23, 27, 51, 65, 67, 68, 72, 112, 128):
         _bad(p, P, P.PDLP_ERR_ARG, "spmv_layout must be", spmv_layout=bad)
-    for bad in (-3, 15, 16, 39, 51):
+    for bad in (-3, 15, 16, 39, 51, 66, 76, 112):
         _bad(p, P, P.PDLP_ERR_ARG, "spmv_layout_kt must be", spmv_layout_kt=bad)
+    for bad in (-1, 3):
+        _bad(p, P, P.PDLP_ERR_ARG, "row_order must be", row_order=bad)
 
 
 def test_batch_rejects_bad_members_and_options(P):
@@ -141,7 +144,7 @@ def test_batch_rejects_bad_members_and_options(P):
                                     ([good], P.PDLP_ERR_ARG, "infeas_every", {"infeas_every": 0}),
                                     ([good], P.PDLP_ERR_ARG, "presolve", {"presolve": 2}),
                                     ([good], P.PDLP_ERR_ARG, "restart_metric", {"restart_metric": 2}),
-                                    ([good], P.PDLP_ERR_ARG, "row_order", {"row_order": 2}),
+                                    ([good], P.PDLP_ERR_ARG, "row_order", {"row_order": 3}),
                                     ([good], P.PDLP_ERR_UNSUPPORTED, "batch handles", {"presolve": 1}),
                                     ([], P.PDLP_ERR_ARG, "count", {})]:
         with pytest.raises(P.PdlpError) as e:

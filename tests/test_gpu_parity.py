@@ -151,22 +151,32 @@ LAYOUT_CASES = [(name, layout) for name in ("random_1000x2000", "skewed_3000x600
 # threads) on the LPs with long rows, one of them over three column panels
 LAYOUT_CASES += [(name, layout) for name in ("skewed_3000x6000", "long_rows", "skewed_20000x40000")
                  for layout in (3, 19, 35)]
+# SELL-64 step passes of K and K' (workgroups of 1024 and 512 threads with
+# the leading 8192 gathered entries in LDS, of 256 threads without), rows and
+# columns renumbered by length; on the 20000 x 40000 LP the gathered vectors
+# are longer than the LDS slice, so both paths of the gather run
+LAYOUT_CASES += [(name, layout) for name in ("random_1000x2000", "skewed_3000x6000", "long_rows",
+                                              "transport_30x40", "skewed_20000x40000")
+                 for layout in (64, 80, 96)]
 
 
 @pytest.mark.parametrize("name,layout", LAYOUT_CASES)
 def test_layouts_match_oracle(P, orc, name, layout):
     """Column panels (1), XCD-contiguous row blocks (2), their persistent-grid
-    forms (4, 5, 6), the step passes on 6144-nonzero blocks (8, 9, 13) and
-    the LDS-staged step passes (3, 19, 35) follow the oracle's trajectory
-    like the default layout: same decisions, iterates within the
-    rounding-order bar, over 100 accepted steps."""
+    forms (4, 5, 6), the step passes on 6144-nonzero blocks (8, 9, 13), the
+    LDS-staged step passes (3, 19, 35) and the SELL-64 step passes (64, 80,
+    96, with rows and columns renumbered) follow the oracle's trajectory like
+    the default layout: same decisions, iterates within the rounding-order
+    bar, over 100 accepted steps."""
     p = PROBLEMS[name]()
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64)
-    h = P.pdlp_create(p, time_limit_s=60.0, trace=4096, spmv_layout=layout, **opts)
+    order = 2 if layout & 64 else 1
+    h = P.pdlp_create(p, time_limit_s=60.0, trace=4096, spmv_layout=layout, row_order=order, **opts)
     P.pdlp_solve(h)
     xh, yh, st = P.pdlp_get_iterate(h)
     tr = P.pdlp_get_trace(h, 4096)
     info = P.pdlp_get_solution(h)[3]
+    P.pdlp_destroy(h)
     if (layout & 3) == 3:   # LDS-staged step view of K; K' has no long rows here and keeps panels
         assert info["layout_k"] == layout
     else:
@@ -181,7 +191,7 @@ def test_layouts_match_oracle(P, orc, name, layout):
     np.testing.assert_array_equal(tr["ev_cand"], r.trace["ev_cand"])
     assert st["attempts"] == r.info["attempts"] and st["restarts"] == r.info["restarts"]
     assert ex <= tol_x and ey <= tol_x
-    res = P.solve(p, eps_rel=1e-6, time_limit_s=60.0, max_iter=200000, spmv_layout=layout)
+    res = P.solve(p, eps_rel=1e-6, time_limit_s=60.0, max_iter=200000, spmv_layout=layout, row_order=order)
     ro = orc.solve(p, eps_rel=1e-6, max_iter=200000)
     assert res.status == "OPTIMAL"
     assert abs(res.info["primal_obj"] - ro.info["primal_obj"]) <= 1e-6 * (1 + abs(ro.info["primal_obj"]))
@@ -217,22 +227,29 @@ def test_other_families_end_to_end(P, orc, name):
     assert orc.evaluate(p, res.x, res.y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
 
 
-def test_fp32_matrix_mode(P, orc):
-    """FP32-rounded scaled matrix in the steps: trajectory parity with the
-    oracle's FP32 mode, and rel KKT 1e-4 on the true (FP64) LP.  The
+@pytest.mark.parametrize("layout", [-1, 80])
+def test_fp32_matrix_mode(P, orc, layout):
+    """FP32-rounded scaled matrix in the steps (in the default layout, and in
+    the SELL-64 layout with rows and columns renumbered): trajectory parity
+    with the oracle's FP32 mode, and rel KKT 1e-4 on the true (FP64) LP.  The
     objective at 1e-4 lies within 1e-6 of the oracle's FP32-mode objective
     when the two took the same path (else 2 eps), and within 2 eps of the
     FP64 oracle's: two points that both meet rel KKT eps can differ by about
     that much in objective, whatever the matrix precision."""
     p = lpgen.config0(2)
+    lay = dict(spmv_layout=layout, row_order=2 if layout == 80 else 1)
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64, a_precision=1)
-    h = P.pdlp_create(p, time_limit_s=60.0, **opts)
+    h = P.pdlp_create(p, time_limit_s=60.0, **lay, **opts)
     P.pdlp_solve(h)
     xh, yh, st = P.pdlp_get_iterate(h)
+    if layout == 80:
+        I = P.pdlp_get_solution(h)[3]
+        assert (I["layout_k"], I["layout_kt"]) == (80, 80)
+    P.pdlp_destroy(h)
     r = orc.solve(p, **opts)
     assert st["attempts"] == r.info["attempts"] and st["restarts"] == r.info["restarts"]
     assert _rel_inf(xh, r.x_hat) <= 1e-10 and _rel_inf(yh, r.y_hat) <= 1e-10
-    res = P.solve(p, eps_rel=1e-4, a_precision=1, time_limit_s=60.0)
+    res = P.solve(p, eps_rel=1e-4, a_precision=1, time_limit_s=60.0, **lay)
     assert res.status == "OPTIMAL"
     e = orc.evaluate(p, res.x, res.y)
     assert e["rel_kkt"] <= 1e-4 * (1 + 1e-6)
