@@ -207,15 +207,16 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
   }
 }
 
-// LDS-staged panels, phase 2: workgroups [0, nrblocks) sweep one block of
-// short rows each, gathering from global memory; the last nlong_groups give
-// each long row a wavefront (its lanes add the row's segment sums
-// lane-strided in panel order, then a shuffle tree), dispatched after the
-// short blocks so that their dependent loads overlap the tail of the sweep.
-// Every row runs the epilogue.  One reduction partial per workgroup.
+// LDS-staged panels, phase 2: workgroups [0, nrblocks) take the short rows,
+// a thread per row adding the row's sums from the step view's column panels
+// in panel order (a row of one nonzero takes its product directly: equal
+// lengths are numbered by first column, so these gathers run in address
+// order); the last nlong_groups give each long row a wavefront (its
+// lanes add the row's segment sums lane-strided in panel order, then a
+// shuffle tree).  Every row runs the epilogue.  One reduction partial per
+// workgroup.
 template <class Op, typename VT>
 __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
-  __shared__ double lds[Op::NV * kTile];
   __shared__ double red[AccSize<Op>::RED];
   if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
@@ -236,9 +237,22 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
       if (lane == 0) op.epi(r, &sum, acc);
     }
   } else {
-    spmv_block<Op::NV, VT, kBlock, kTile>(
-        M.rp, M.ci, pick<VT>(M.v, M.vf), S.rblocks[blockIdx.x], lds, red,
-        [&](int c, double* g) { op.gather(c, g); }, [&](int r, const double* s) { op.epi(r, s, acc); });
+    const PanelCsr& Q = M.pan;
+    const VT* __restrict__ vals = pick<VT>(M.v, M.vf);
+    for (int r = S.rlong + blockIdx.x * kBlock + (int)threadIdx.x; r < M.nrows; r += nrb * kBlock) {
+      const int b = M.rp[r], e = M.rp[r + 1];
+      double sum = 0.0;
+      if (e - b <= 1) {
+        if (e > b) {
+          double g;
+          op.gather(M.ci[b], &g);
+          sum = (double)vals[b] * g;
+        }
+      } else {
+        for (int q = Q.row_seg[r]; q < Q.row_seg[r + 1]; ++q) sum += Q.part[Q.slot_seg[q]];
+      }
+      op.epi(r, &sum, acc);
+    }
   }
   if constexpr (Op::NACC > 0) {
     block_sum<Op::NACC>(acc, red);
@@ -590,7 +604,9 @@ static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
 }
 
 // A step pass in the LDS-staged layout: the long rows' staged panels
-// (stg.cfg selects the workgroup size), then the row pass.
+// (stg.cfg selects the workgroup size), the short rows' column panels (one
+// workgroup per phase-1 block, so that workgroup i serves panel i % 8 on XCD
+// i % 8), then the row pass.
 template <class Op, typename VT>
 static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
   const StagedCsr& S = M.stg;
@@ -599,6 +615,8 @@ static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
     else if (S.cfg == 1) hipLaunchKernelGGL((k_stage<Op, VT, 512>), dim3(S.nwork), dim3(512), 0, s, p);
     else hipLaunchKernelGGL((k_stage<Op, VT, 256>), dim3(S.nwork), dim3(256), 0, s, p);
   }
+  if (M.pan.nsblocks > 0)
+    hipLaunchKernelGGL((k_seg<Op, VT, kTile>), dim3(M.pan.nsblocks), dim3(kBlock), 0, s, p);
   hipLaunchKernelGGL((k_stage_rows<Op, VT>), dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), 0, s, p);
 }
 

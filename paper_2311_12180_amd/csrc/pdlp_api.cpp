@@ -123,19 +123,25 @@ struct HostPanels {
   std::vector<RowBlock> sblocks, sblocks_wide;   // phase-1 blocks of kTile and of kTileWide nonzeros
 };
 
-// Rows [r0, nrows) only (the rows before r0 get no segments); seg_ptr
-// offsets count from the first nonzero of row r0, perm holds CSR indices.
+// Rows [r0, nrows) with at least min_len nonzeros only (the others get no
+// segments); seg_ptr offsets count over those rows' nonzeros, perm holds CSR
+// indices.
 HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int ncols, const int32_t* col_ptr,
-                        int r0 = 0) {
+                        int r0 = 0, int min_len = 0) {
   HostPanels H;
-  const int64_t nnz = (int64_t)rp[nrows] - rp[r0];
+  auto in = [&](int r) { return rp[r + 1] - rp[r] >= min_len; };
+  int64_t nnz = 0;
+  for (int r = r0; r < nrows; ++r)
+    if (in(r)) nnz += rp[r + 1] - rp[r];
   // panel boundaries: about nnz / kPanels nonzeros of these rows each
   // (col_ptr = row pointer of the transpose when the range is every row;
   // otherwise the range's own column counts)
   std::vector<int32_t> own;
-  if (r0 > 0) {
+  if (r0 > 0 || min_len > 0 || !col_ptr) {
     own.assign((size_t)ncols + 1, 0);
-    for (int32_t e = rp[r0]; e < rp[nrows]; ++e) own[(size_t)ci[e] + 1]++;
+    for (int r = r0; r < nrows; ++r)
+      if (in(r))
+        for (int32_t e = rp[r]; e < rp[r + 1]; ++e) own[(size_t)ci[e] + 1]++;
     for (int j = 0; j < ncols; ++j) own[(size_t)j + 1] += own[(size_t)j];
     col_ptr = own.data();
   }
@@ -152,6 +158,7 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
   std::vector<uint8_t> mask((size_t)nrows, 0);
   std::vector<int64_t> pnnz(kPanels, 0), pseg(kPanels, 0);
   for (int r = r0; r < nrows; ++r) {
+    if (!in(r)) continue;
     for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
       const int p = colpan[(size_t)ci[e]];
       mask[(size_t)r] |= (uint8_t)(1u << p);
@@ -176,6 +183,7 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
   H.perm.assign((size_t)nnz, 0);
   std::vector<int32_t> last(kPanels, -1);
   for (int r = r0; r < nrows; ++r) {
+    if (!in(r)) continue;
     for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
       const int p = colpan[(size_t)ci[e]];
       if (last[p] != r) {
@@ -216,13 +224,12 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
 // panel into runs of about equal entry counts, as many per panel as the
 // smallest item size allows -- so panels of unequal weight (columns of
 // unequal counts) still give items of about equal work.  The rows [rlong,
-// nrows) are cut into plain row blocks.
+// nrows) go through column panels of their own (build_panels from rlong).
 struct HostStaged {
   int32_t rlong = 0, nseg = 0;
   int64_t nnz_long = 0, nent = 0;
   std::vector<int32_t> wpanel, wchunk, coff, clen, cseg, perm, row_seg, slot_seg;
   std::vector<uint16_t> pci;   // column relative to the panel (kStageWidth <= 65536)
-  std::vector<RowBlock> rblocks;
 };
 
 constexpr int kStageMinLen = 128;   // nonzeros of a row summed through the staged panels
@@ -346,10 +353,6 @@ HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int nco
       }
     }
   }
-  // short rows: at most one row per thread of a block, so that no thread
-  // runs two row epilogues one after the other
-  H.rblocks = partition_rows(rp, rl, nrows, kTile, kBlock);
-  if (H.rblocks.empty()) H.rblocks.push_back(RowBlock{rl, rl});
   return H;
 }
 
@@ -392,6 +395,7 @@ struct pdlp_handle {
   int32_t wide_nsblocks[2] = {0, 0};
   // the LDS-staged layouts of K and K' a step view may take
   StagedCsr stg[2] = {};
+  PanelCsr stg_pan[2] = {};   // the staged step views' column panels of the short rows
   bool has_stg[2] = {false, false};
   SellCsr sel[2] = {};
   bool has_sel[2] = {false, false};
@@ -802,8 +806,8 @@ static void upload_panels(pdlp_handle* h, int which, DevCsr& M, const HostPanels
 
 // Device copy of an LDS-staged layout for the step view of matrix `which`
 // (kept in h->stg until the chooser or the option selects it).
-static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, int ncols, const double* v,
-                          const float* vf) {
+static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, const int32_t* rp, const int32_t* ci,
+                          int nrows, int ncols, const int32_t* ci_dev, const double* v, const float* vf) {
   hipStream_t s = h->stream;
   const hipMemcpyKind kind = hipMemcpyHostToDevice;
   auto up = [&](const auto& vec, const char* what) {
@@ -818,10 +822,9 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, int nc
   S.ncols = ncols;
   S.nseg = H.nseg;
   S.rlong = H.rlong;
-  // the row pass: a wavefront per long row (four per workgroup), then one
-  // workgroup per block of short rows
+  // the row pass: a wavefront per long row (four per workgroup), a thread per short row
   S.nlong_groups = std::min(kElemBlocks, (H.rlong + kBlock / 64 - 1) / (kBlock / 64));
-  S.nrblocks = (int32_t)H.rblocks.size();
+  S.nrblocks = std::min(kElemBlocks, (nrows - H.rlong + kBlock - 1) / kBlock);
   S.wpanel = up(H.wpanel, "upload staged panels");
   S.wchunk = up(H.wchunk, "upload staged panels");
   S.coff = up(H.coff, "upload staged panels");
@@ -829,7 +832,6 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, int nc
   S.cseg = up(H.cseg, "upload staged panels");
   S.row_seg = up(H.row_seg, "upload staged panels");
   S.slot_seg = up(H.slot_seg, "upload staged panels");
-  S.rblocks = up(H.rblocks, "upload staged panels");
   S.pci = up(H.pci, "upload staged panels");
   const int64_t ne = std::max<int64_t>(H.nent, 1);
   int32_t* perm = h->dalloc<int32_t>((size_t)ne);
@@ -842,6 +844,29 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, int nc
   S.pv = pv;
   S.pvf = pvf;
   S.part = h->dalloc<double>((size_t)H.nseg + 1);
+  // the short rows' column panels (phase-1 blocks of kTile nonzeros)
+  PanelCsr& Q = h->stg_pan[which];
+  Q = PanelCsr{};
+  if (H.rlong < nrows) {
+    // (rows with one nonzero or none are summed directly in the row pass)
+    const HostPanels HP = build_panels(rp, ci, nrows, ncols, nullptr, H.rlong, 2);
+    const int64_t nz = (int64_t)HP.perm.size();
+    Q.nseg = (int32_t)HP.slot_seg.size();
+    Q.nsblocks = (int32_t)HP.sblocks.size();
+    Q.seg_ptr = up(HP.seg_ptr, "upload short-row panels");
+    Q.slot_seg = up(HP.slot_seg, "upload short-row panels");
+    Q.row_seg = up(HP.row_seg, "upload short-row panels");
+    Q.sblocks = up(HP.sblocks, "upload short-row panels");
+    int32_t* qperm = up(HP.perm, "upload short-row panels");
+    int32_t* qci = h->dalloc<int32_t>((size_t)std::max<int64_t>(nz, 1));
+    double* qv = h->dalloc<double>((size_t)std::max<int64_t>(nz, 1));
+    float* qvf = vf ? h->dalloc<float>((size_t)std::max<int64_t>(nz, 1)) : nullptr;
+    check(setup_permute(nz, qperm, ci_dev, v, vf, qci, qv, qvf, s), "permute short-row panels");
+    Q.pci = qci;
+    Q.pv = qv;
+    Q.pvf = qvf;
+    Q.part = h->dalloc<double>((size_t)std::max(Q.nseg, 1));
+  }
   check(hipStreamSynchronize(s), "staged panels sync");
   h->has_stg[which] = H.nseg > 0;
 }
@@ -938,6 +963,7 @@ static void choose_layouts(pdlp_handle* h) {
       V.grid = 0;
       V.stg = h->stg[which];
       V.stg.cfg = cfg;
+      V.pan = h->stg_pan[which];
       V.nred = V.stg.nlong_groups + V.stg.nrblocks;
     };
     // the step view in the SELL-64 layout (workgroup configuration `cfg`),
@@ -1564,7 +1590,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
         const int64_t nl = leading_long_nnz(H.rp.data(), m, kStageMinLen);
         if (force_k || 2 * nl >= nnz) {
           HostStaged HS = build_staged(H.rp.data(), H.ci.data(), m, n, kStageMinLen, h->persist_grid / 8);
-          upload_staged(h, 0, HS, n, h->val, h->valf);
+          upload_staged(h, 0, HS, H.rp.data(), H.ci.data(), m, n, h->ci, h->val, h->valf);
         }
       }
       if (force_kt || auto_kt) {
@@ -1573,7 +1599,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
           std::vector<int32_t> hciT((size_t)std::max<int64_t>(nnz, 1));
           if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
           HostStaged HS = build_staged(hrpT.data(), hciT.data(), n, m, kStageMinLen, h->persist_grid / 8);
-          upload_staged(h, 1, HS, m, h->valT, h->valTf);
+          upload_staged(h, 1, HS, hrpT.data(), hciT.data(), n, m, h->ciT, h->valT, h->valTf);
         }
       }
     }
@@ -1937,8 +1963,11 @@ extern "C" int pdlp_solve_noalloc(pdlp_handle* h) {
     DevCsr& M = w ? Q.KT : Q.K;     // evaluation view
     DevCsr& V = w ? Q.KTs : Q.Ks;   // step view (its panel sums are the same buffer as M's)
     if ((M.layout == 1 || V.layout == 1) && M.pan.part)
-      add(&M.pan.part, 2 * (size_t)std::max(M.pan.nseg, 1), &V.pan.part);
-    if (V.layout == 3) add(&V.stg.part, (size_t)V.stg.nseg + 1);
+      add(&M.pan.part, 2 * (size_t)std::max(M.pan.nseg, 1), V.layout == 1 ? &V.pan.part : nullptr);
+    if (V.layout == 3) {
+      add(&V.stg.part, (size_t)V.stg.nseg + 1);
+      if (V.pan.part) add(&V.pan.part, (size_t)std::max(V.pan.nseg, 1));   // the short rows' panel sums
+    }
   }
   size_t need = 0;
   for (int i = 0; i < np; ++i) need = (need + 255) / 256 * 256 + parts[i].count * sizeof(double);

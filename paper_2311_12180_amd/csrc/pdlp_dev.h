@@ -61,11 +61,15 @@ struct PanelCsr {
 // panel (16 bits).  Phase 1 (k_stage): a work item (one workgroup) is a run of one
 // panel's chunks; it copies the panel's slice of the gathered vector into LDS
 // once, then each wavefront sums whole chunks (coalesced loads, every gather
-// an LDS read, no barrier) and stores one sum per segment.  Phase 2
-// (k_stage_rows): the short rows are swept as plain row blocks of at most one
-// row per thread (equal lengths are numbered by first column, so their
-// gathers run in address order), then a wavefront per long row adds its
-// segment sums in panel order; every row runs the epilogue.
+// an LDS read, no barrier) and stores one sum per segment.  The short rows
+// take column panels of their own, one per XCD (the step view's PanelCsr,
+// summed by k_seg): each XCD then gathers from one eighth of the vector, which
+// stays in its L2, where random gathers from the whole vector would pull a
+// cache line from memory for nearly every nonzero; rows of one nonzero (their
+// gathers run in address order) are left out.  Phase 2 (k_stage_rows): a
+// thread per short row adds its panel sums in panel order (or takes its one
+// product), a wavefront per long row adds its segment sums in panel order;
+// every row runs the epilogue.
 constexpr int kStageWidth = 16384;   // columns per panel: 128 KB of FP64 in LDS (at most 65536: 16-bit indices)
 constexpr int kStageLanes = 64;      // segments per chunk
 struct StagedCsr {
@@ -75,7 +79,7 @@ struct StagedCsr {
   int32_t cfg;              // phase-1 workgroup size: 0: 256, 1: 512, 2: 1024 threads
   int32_t rlong;            // rows [0, rlong) are the long rows
   int32_t nlong_groups;     // phase-2 workgroups of the long rows
-  int32_t nrblocks;         // phase-2 row blocks of the short rows (at most kBlock rows each)
+  int32_t nrblocks;         // phase-2 workgroups of the short rows (one row per thread)
   int32_t pad;
   const int32_t* wpanel;    // [nwork] panel of each work item
   const int32_t* wchunk;    // [nwork+1] chunk range of each work item
@@ -88,7 +92,6 @@ struct StagedCsr {
   const int32_t* row_seg;   // [rlong+1] long row r's segments: slot_seg[row_seg[r] .. row_seg[r+1]), in panel order
   const int32_t* slot_seg;
   double* part;             // [nseg] segment sums
-  const RowBlock* rblocks;  // [nrblocks] row blocks of the short rows [rlong, nrows)
 };
 
 // SELL-64 layout of a step view (layout 4): the rows are cut into chunks of
