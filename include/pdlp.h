@@ -101,11 +101,13 @@ typedef struct {
                                  per 8 waves of every CU, looping over the row blocks); plus 8:
                                  the step passes take blocks of 6144 nonzeros instead of 3072
                                  (the evaluation passes keep 3072); or 3, 19, 35: the step pass
-                                 runs on LDS-staged column panels -- the rows with at least 128
+                                 runs on LDS-staged column panels -- the rows with at least 256
                                  nonzeros (numbered first by row_order) are cut into panels of
                                  16,384 columns whose slice of the gathered vector a workgroup of
                                  256, 512 or 1024 threads copies into LDS once, the other rows
-                                 are swept directly -- with column panels on a persistent grid
+                                 with two nonzeros or more take eight column panels (one per
+                                 XCD), rows of one nonzero are summed directly -- with column
+                                 panels on a persistent grid
                                  for the evaluation passes; or 64, 80, 96: the step pass runs
                                  on SELL-64 chunks -- 64 consecutive rows stored
                                  lane-interleaved, one row per lane, zero-padded to the chunk's
@@ -114,7 +116,8 @@ typedef struct {
                                  in workgroups of 1024 or 512 threads that first copy the
                                  leading 8192 entries of the gathered vector into LDS (64, 80),
                                  or of 256 threads without that copy (96); the evaluation passes
-                                 as for 3.  The timing at create tries every
+                                 over that matrix run on the same chunks (their two gathered
+                                 vectors share the LDS copy).  The timing at create tries every
                                  combination on matrices with 2^20 nonzeros or more.  The
                                  layout changes the order of floating-point sums; fix it for
                                  bitwise reproducibility across handles.  This field applies to

@@ -263,36 +263,41 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
   }
 }
 
-// SELL-64 step pass (layout 4) on a persistent grid: wavefront w of the grid
+// SELL-64 pass (layout 4) on a persistent grid: wavefront w of the grid
 // takes chunks w, w + (waves of the grid), ...; each lane sums its row's
 // entries in stored order (coalesced loads of the lane-interleaved entries,
 // kU of them in flight) and runs the epilogue.  With HOT, the workgroup first
-// copies the leading S.hot entries of the gathered vector into LDS, and
-// gathers below S.hot read that copy.  One reduction partial per workgroup.
+// copies the leading entries of the NV gathered vectors into LDS (kSellHot / NV
+// of each, at most S.hot), and gathers below that read the copy.  One
+// reduction partial per workgroup.
 template <class Op, typename VT, int BS, bool HOT>
 __global__ __launch_bounds__(BS) void k_sell(Params p) {
-  static_assert(Op::NV == 1, "the SELL step view gathers one vector");
+  constexpr int NV = Op::NV;
   constexpr int kWaves = BS / 64;
   constexpr int kU = 8;
+  constexpr int kHot = kSellHot / NV;
   __shared__ double xs[HOT ? kSellHot : 1];
   __shared__ double red[AccSize<Op>::N * kWaves];
   if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
   const DevCsr& M = Op::mat(p);
   const SellCsr& S = M.sel;
-  const int hot = HOT ? S.hot : 0;
+  const int hot = HOT ? min(S.hot, kHot) : 0;
   if (HOT) {
     for (int j0 = 0; j0 < hot; j0 += kU * BS) {
-      double g[kU];
+      double g[kU][NV];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int j = j0 + u * BS + (int)threadIdx.x;
-        op.gather(j < hot ? j : hot - 1, &g[u]);
+        op.gather(j < hot ? j : hot - 1, g[u]);
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int j = j0 + u * BS + (int)threadIdx.x;
-        if (j < hot) xs[j] = g[u];
+        if (j < hot) {
+#pragma unroll
+          for (int k = 0; k < NV; ++k) xs[k * kHot + j] = g[u][k];
+        }
       }
     }
     __syncthreads();
@@ -307,28 +312,37 @@ __global__ __launch_bounds__(BS) void k_sell(Params p) {
   for (int c = blockIdx.x * kWaves + wv; c < S.nchunks; c += gridDim.x * kWaves) {
     const int len = S.clen[c];
     const int base = S.coff[c] + lane;
-    double sum = 0.0;
-    for (int k = 0; k < len; k += kU) {
+    double sum[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sum[k] = 0.0;
+    for (int k0 = 0; k0 < len; k0 += kU) {
       int col[kU];
-      double a[kU], g[kU];
+      double a[kU], g[kU][NV];
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (k + u < len) {
-          col[u] = sci[base + (k + u) * 64];
-          a[u] = (double)vals[base + (k + u) * 64];
+        if (k0 + u < len) {
+          col[u] = sci[base + (k0 + u) * 64];
+          a[u] = (double)vals[base + (k0 + u) * 64];
         }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (k + u < len) {
-          if (HOT && col[u] < hot) g[u] = xs[col[u]];
-          else op.gather(col[u], &g[u]);
+        if (k0 + u < len) {
+          if (HOT && col[u] < hot) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) g[u][k] = xs[k * kHot + col[u]];
+          } else {
+            op.gather(col[u], g[u]);
+          }
         }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (k + u < len) sum += a[u] * g[u];
+        if (k0 + u < len) {
+#pragma unroll
+          for (int k = 0; k < NV; ++k) sum[k] += a[u] * g[u][k];
+        }
     }
     const int r = c * 64 + lane;
-    if (r < M.nrows) op.epi(r, &sum, acc);
+    if (r < M.nrows) op.epi(r, sum, acc);
   }
   if constexpr (Op::NACC > 0) {
     block_sum<Op::NACC, kWaves>(acc, red);
@@ -589,11 +603,23 @@ static inline int elem_grid(int n) {
   return g < 1 ? 1 : g;
 }
 
+// A pass in the SELL-64 layout (sel.cfg selects the workgroup size and
+// whether the leading gathered entries are staged in LDS).
+template <class Op, typename VT>
+static void launch_sell(const Params& p, const DevCsr& M, hipStream_t s) {
+  const SellCsr& S = M.sel;
+  if (S.cfg == 0) hipLaunchKernelGGL((k_sell<Op, VT, 1024, true>), dim3(S.grid), dim3(1024), 0, s, p);
+  else if (S.cfg == 1) hipLaunchKernelGGL((k_sell<Op, VT, 512, true>), dim3(S.grid), dim3(512), 0, s, p);
+  else hipLaunchKernelGGL((k_sell<Op, VT, 256, false>), dim3(S.grid), dim3(256), 0, s, p);
+}
+
 // One pass of `Op` over its matrix in the matrix's layout, with the
 // kernels built for the tiling of M's blocks.
 template <class Op, typename VT, int TILE = kTile>
 static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
-  if (M.layout == 0) {
+  if (M.layout == 4) {
+    launch_sell<Op, VT>(p, M, s);
+  } else if (M.layout == 0) {
     const int g = M.grid > 0 && M.grid < M.nblocks ? M.grid : M.nblocks;
     hipLaunchKernelGGL((k_fused<Op, VT, TILE>), dim3(g), dim3(kBlock), 0, s, p);
   } else {
@@ -618,16 +644,6 @@ static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
   if (M.pan.nsblocks > 0)
     hipLaunchKernelGGL((k_seg<Op, VT, kTile>), dim3(M.pan.nsblocks), dim3(kBlock), 0, s, p);
   hipLaunchKernelGGL((k_stage_rows<Op, VT>), dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), 0, s, p);
-}
-
-// A step pass in the SELL-64 layout (sel.cfg selects the workgroup size and
-// whether the leading gathered entries are staged in LDS).
-template <class Op, typename VT>
-static void launch_sell(const Params& p, const DevCsr& M, hipStream_t s) {
-  const SellCsr& S = M.sel;
-  if (S.cfg == 0) hipLaunchKernelGGL((k_sell<Op, VT, 1024, true>), dim3(S.grid), dim3(1024), 0, s, p);
-  else if (S.cfg == 1) hipLaunchKernelGGL((k_sell<Op, VT, 512, true>), dim3(S.grid), dim3(512), 0, s, p);
-  else hipLaunchKernelGGL((k_sell<Op, VT, 256, false>), dim3(S.grid), dim3(256), 0, s, p);
 }
 
 // A step pass over a step view: the view replaces the matrix in the kernels'

@@ -232,7 +232,7 @@ struct HostStaged {
   std::vector<uint16_t> pci;   // column relative to the panel (kStageWidth <= 65536)
 };
 
-constexpr int kStageMinLen = 128;   // nonzeros of a row summed through the staged panels
+constexpr int kStageMinLen = 256;   // nonzeros of a row summed through the staged panels
 
 // Nonzeros of the leading rows with at least min_len nonzeros.
 int64_t leading_long_nnz(const int32_t* rp, int nrows, int min_len) {
@@ -966,23 +966,21 @@ static void choose_layouts(pdlp_handle* h) {
       V.pan = h->stg_pan[which];
       V.nred = V.stg.nlong_groups + V.stg.nrblocks;
     };
-    // the step view in the SELL-64 layout (workgroup configuration `cfg`),
-    // the evaluation view as for the staged layout
+    // both views in the SELL-64 layout (workgroup configuration `cfg`)
     auto set_sell = [&](int cfg) {
-      set(has_pan ? 1 : 0, 0, 1, kTile);
+      set(0, 0, 0, kTile);
+      M.layout = 4;
+      M.remap = 0;
+      M.grid = 0;
+      M.sel = h->sel[which];
+      M.sel.cfg = cfg;
+      M.sel.grid = sell_grid(h, cfg, M.sel.nchunks);
+      M.nred = M.sel.grid;
       V = M;
-      V.layout = 4;
-      V.tile = kTile;
-      V.remap = 0;
-      V.grid = 0;
-      V.sel = h->sel[which];
-      V.sel.cfg = cfg;
-      V.sel.grid = sell_grid(h, cfg, V.sel.nchunks);
-      V.nred = V.sel.grid;
     };
     if (mode >= 0) {   // forced: bits 0-1 the layout, bit 2 the persistent grid, bit 3 the wide step tiles;
                        // 3 + 16 cfg: staged step view, column panels (else row blocks) on a persistent grid
-                       // for the evaluations; 64 + 16 cfg: SELL-64 step view, the evaluations as for 3
+                       // for the evaluations; 64 + 16 cfg: SELL-64 for the step and evaluation passes
       const int g = (mode & 4) ? 1 : 0, t = (mode & 8) ? kTileWide : kTile;
       if (mode & 64) {
         if (h->has_sel[which]) set_sell((mode >> 4) & 3);

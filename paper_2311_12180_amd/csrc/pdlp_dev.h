@@ -51,7 +51,7 @@ struct PanelCsr {
 };
 
 // LDS-staged panel layout of a CSR matrix for a step pass (one gathered
-// vector).  The long rows (at least 128 nonzeros; the descending-length row
+// vector).  The long rows (at least 256 nonzeros; the descending-length row
 // order numbers them first) are cut by columns into panels of kStageWidth
 // columns; the nonzeros of long row r in panel p form segment (r, p).  Inside
 // a panel the segments are sorted by length (longest first) and grouped in

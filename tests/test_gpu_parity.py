@@ -232,10 +232,12 @@ def test_fp32_matrix_mode(P, orc, layout):
     """FP32-rounded scaled matrix in the steps (in the default layout, and in
     the SELL-64 layout with rows and columns renumbered): trajectory parity
     with the oracle's FP32 mode, and rel KKT 1e-4 on the true (FP64) LP.  The
-    objective at 1e-4 lies within 1e-6 of the oracle's FP32-mode objective
-    when the two took the same path (else 2 eps), and within 2 eps of the
-    FP64 oracle's: two points that both meet rel KKT eps can differ by about
-    that much in objective, whatever the matrix precision."""
+    objective at 1e-4 lies within max(1e-10, 10 x) the oracle's own
+    objective spread under renumbering (copies that took the oracle's path)
+    of the oracle's FP32-mode objective when the two took the same path (else
+    2 eps), and within 2 eps of the FP64 oracle's: two points that both meet
+    rel KKT eps can differ by about that much in objective, whatever the
+    matrix precision."""
     p = lpgen.config0(2)
     lay = dict(spmv_layout=layout, row_order=2 if layout == 80 else 1)
     opts = dict(eps_rel=0.0, max_iter=100, eval_period=64, a_precision=1)
@@ -259,8 +261,18 @@ def test_fp32_matrix_mode(P, orc, layout):
     e64 = abs(obj - r64.info["primal_obj"]) / (1 + abs(r64.info["primal_obj"]))
     e32 = abs(obj - r32.info["primal_obj"]) / (1 + abs(r32.info["primal_obj"]))
     same = res.info["iterations"] == r32.info["iterations"] and res.info["attempts"] == r32.info["attempts"]
-    print(f"fp32 objective error vs the FP64 oracle {e64:.1e}, vs the oracle's FP32 mode {e32:.1e} (same path {same})")
-    assert e32 <= (1e-6 if same else 2e-4)
+    spread, copies = 0.0, 0
+    for k in range(3):
+        rng = np.random.default_rng(70 + k)
+        rp, cp = rng.permutation(p.m), rng.permutation(p.n)
+        q = orc.solve(lpgen.permute(p, rp, cp), eps_rel=1e-4, a_precision=1)
+        if q.info["iterations"] == r32.info["iterations"] and q.info["attempts"] == r32.info["attempts"]:
+            spread = max(spread, abs(q.info["primal_obj"] - r32.info["primal_obj"]) / (1 + abs(r32.info["primal_obj"])))
+            copies += 1
+    bar = bars.bar(spread) if (same and copies) else 2e-4
+    print(f"fp32 objective error vs the FP64 oracle {e64:.1e}, vs the oracle's FP32 mode {e32:.1e} (same path {same}; "
+          f"oracle spread {spread:.1e} over {copies} copies on its path, bar {bar:.1e})")
+    assert e32 <= bar
     assert e64 <= 2e-4
 
 
