@@ -27,6 +27,7 @@
 //                             Section 4.1 termination, Section 2.2 infeasibility
 //                             certificates, Section 3.4 restart decision
 //   restart ops             : apply the restart (new z^{n+1,0}, K~x)
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "pdlp_ops.h"
@@ -133,13 +134,23 @@ __global__ __launch_bounds__(kBlock) void k_rows(Params p) {
 // the lane-interleaved entries, every gather an LDS read, no barrier), and
 // stores the segment sums.  A chunk's descriptor is read while the previous
 // chunk is summed.
+//
+// After its work items, each workgroup sums blocks of the short rows' column
+// panels (the step view's PanelCsr): workgroup w takes blocks w, w + grid,
+// ..., with a grid that is a multiple of 8, so block j (which serves panel
+// j % 8) stays on XCD j % 8, whose L2 holds that panel's slice of the vector.
+// Work items finish at different times, so this latency-bound work overlaps
+// other workgroups' streaming instead of following it in a launch of its own.
 template <class Op, typename VT, int BS>
 __global__ __launch_bounds__(BS) void k_stage(Params p) {
   static_assert(Op::NV == 1, "staged panels hold one gathered vector");
+  static_assert(kTile <= kStageWidth, "a short-row block's products fit the LDS slice");
   __shared__ double xs[kStageWidth];
+  __shared__ double red[BS / 64];
   if (Op::idle(p, p.st)) return;
   const Op op(p, p.st);
-  const StagedCsr& S = Op::mat(p).stg;
+  const DevCsr& M = Op::mat(p);
+  const StagedCsr& S = M.stg;
   double* __restrict__ part = S.part;
   const VT* __restrict__ vals = pick<VT>(S.pv, S.pvf);
   const uint16_t* __restrict__ pci = S.pci;
@@ -205,16 +216,23 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
     }
     __syncthreads();   // the next work item rewrites xs
   }
+  // the short rows' panel blocks (products staged in xs, as in k_seg)
+  const PanelCsr& Q = M.pan;
+  for (int i = blockIdx.x; i < Q.nsblocks; i += gridDim.x) {
+    spmv_block<1, VT, BS, kTile>(
+        Q.seg_ptr, Q.pci, pick<VT>(Q.pv, Q.pvf), Q.sblocks[i], xs, red,
+        [&](int col, double* g) { op.gather(col, g); }, [&](int sg, const double* sums) { Q.part[sg] = sums[0]; });
+    __syncthreads();   // the next block reuses xs
+  }
 }
 
 // LDS-staged panels, phase 2: workgroups [0, nrblocks) take the short rows,
 // a thread per row adding the row's sums from the step view's column panels
 // in panel order (a row of one nonzero takes its product directly: equal
 // lengths are numbered by first column, so these gathers run in address
-// order); the last nlong_groups give each long row a wavefront (its
-// lanes add the row's segment sums lane-strided in panel order, then a
-// shuffle tree).  Every row runs the epilogue.  One reduction partial per
-// workgroup.
+// order); the last nlong_groups give each long row a wavefront (its lanes add
+// the row's segment sums lane-strided in panel order, then a shuffle tree).
+// Every row runs the epilogue.  One reduction partial per workgroup.
 template <class Op, typename VT>
 __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
   __shared__ double red[AccSize<Op>::RED];
@@ -597,6 +615,25 @@ __global__ void k_set_limit(DevState* st, int status) {
 
 // ---------------------------------------------------------------------------- launchers
 
+// Kernel timing (pdlp_profile_attempts): while set, the first kernel of a
+// step pass records t0 at its own start and the last records t1 at its own
+// end (hipExtLaunchKernelGGL: the runtime takes both at the kernel's
+// boundaries, so the interval holds the pass's kernels and the gaps between
+// them, not the event packets around them).
+static thread_local hipEvent_t g_t0 = nullptr, g_t1 = nullptr;
+
+void set_pass_events(hipEvent_t t0, hipEvent_t t1) {
+  g_t0 = t0;
+  g_t1 = t1;
+}
+
+template <typename F>
+static void go(F kernel, dim3 grid, dim3 block, hipStream_t s, const Params& p, bool first, bool last) {
+  hipEvent_t a = first ? g_t0 : nullptr, b = last ? g_t1 : nullptr;
+  if (a || b) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, p);
+  else hipLaunchKernelGGL(kernel, grid, block, 0, s, p);
+}
+
 static inline int elem_grid(int n) {
   int g = (n + kBlock - 1) / kBlock;
   if (g > kElemBlocks) g = kElemBlocks;
@@ -608,9 +645,9 @@ static inline int elem_grid(int n) {
 template <class Op, typename VT>
 static void launch_sell(const Params& p, const DevCsr& M, hipStream_t s) {
   const SellCsr& S = M.sel;
-  if (S.cfg == 0) hipLaunchKernelGGL((k_sell<Op, VT, 1024, true>), dim3(S.grid), dim3(1024), 0, s, p);
-  else if (S.cfg == 1) hipLaunchKernelGGL((k_sell<Op, VT, 512, true>), dim3(S.grid), dim3(512), 0, s, p);
-  else hipLaunchKernelGGL((k_sell<Op, VT, 256, false>), dim3(S.grid), dim3(256), 0, s, p);
+  if (S.cfg == 0) go(k_sell<Op, VT, 1024, true>, dim3(S.grid), dim3(1024), s, p, true, true);
+  else if (S.cfg == 1) go(k_sell<Op, VT, 512, true>, dim3(S.grid), dim3(512), s, p, true, true);
+  else go(k_sell<Op, VT, 256, false>, dim3(S.grid), dim3(256), s, p, true, true);
 }
 
 // One pass of `Op` over its matrix in the matrix's layout, with the
@@ -621,29 +658,27 @@ static void launch_op(const Params& p, const DevCsr& M, hipStream_t s) {
     launch_sell<Op, VT>(p, M, s);
   } else if (M.layout == 0) {
     const int g = M.grid > 0 && M.grid < M.nblocks ? M.grid : M.nblocks;
-    hipLaunchKernelGGL((k_fused<Op, VT, TILE>), dim3(g), dim3(kBlock), 0, s, p);
+    go(k_fused<Op, VT, TILE>, dim3(g), dim3(kBlock), s, p, true, true);
   } else {
     const int g = M.grid > 0 && M.grid < M.pan.nsblocks ? M.grid : M.pan.nsblocks;
-    hipLaunchKernelGGL((k_seg<Op, VT, TILE>), dim3(g), dim3(kBlock), 0, s, p);
-    hipLaunchKernelGGL((k_rows<Op>), dim3(M.rows_grid), dim3(kBlock), 0, s, p);
+    go(k_seg<Op, VT, TILE>, dim3(g), dim3(kBlock), s, p, true, false);
+    go(k_rows<Op>, dim3(M.rows_grid), dim3(kBlock), s, p, false, true);
   }
 }
 
-// A step pass in the LDS-staged layout: the long rows' staged panels
-// (stg.cfg selects the workgroup size), the short rows' column panels (one
-// workgroup per phase-1 block, so that workgroup i serves panel i % 8 on XCD
-// i % 8), then the row pass.
+// A step pass in the LDS-staged layout: the long rows' staged panels and
+// then, in the same workgroups, the short rows' column panels (stg.cfg
+// selects the workgroup size); then the row pass.
 template <class Op, typename VT>
 static void launch_staged(const Params& p, const DevCsr& M, hipStream_t s) {
   const StagedCsr& S = M.stg;
-  if (S.nwork > 0) {
-    if (S.cfg == 2) hipLaunchKernelGGL((k_stage<Op, VT, 1024>), dim3(S.nwork), dim3(1024), 0, s, p);
-    else if (S.cfg == 1) hipLaunchKernelGGL((k_stage<Op, VT, 512>), dim3(S.nwork), dim3(512), 0, s, p);
-    else hipLaunchKernelGGL((k_stage<Op, VT, 256>), dim3(S.nwork), dim3(256), 0, s, p);
-  }
-  if (M.pan.nsblocks > 0)
-    hipLaunchKernelGGL((k_seg<Op, VT, kTile>), dim3(M.pan.nsblocks), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL((k_stage_rows<Op, VT>), dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), 0, s, p);
+  // the grid: every work item, a multiple of 8 (XCD affinity of the short
+  // rows' panel blocks)
+  const int g = S.sgrid;
+  if (S.cfg == 2) go(k_stage<Op, VT, 1024>, dim3(g), dim3(1024), s, p, true, false);
+  else if (S.cfg == 1) go(k_stage<Op, VT, 512>, dim3(g), dim3(512), s, p, true, false);
+  else go(k_stage<Op, VT, 256>, dim3(g), dim3(256), s, p, true, false);
+  go(k_stage_rows<Op, VT>, dim3(S.nlong_groups + S.nrblocks), dim3(kBlock), s, p, false, true);
 }
 
 // A step pass over a step view: the view replaces the matrix in the kernels'

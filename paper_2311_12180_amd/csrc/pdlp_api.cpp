@@ -31,6 +31,7 @@ void launch_eval(const Params& p, hipStream_t s);
 void launch_init(const Params& p, const double* xs, const double* ys, hipStream_t s);
 void launch_output(const Params& p, hipStream_t s);
 void launch_set_limit(DevState* st, int status, hipStream_t s);
+void set_pass_events(hipEvent_t t0, hipEvent_t t1);
 void launch_batch(const Params& p, const BatchParams& bp, int grid, hipStream_t s);
 int batch_occupancy(size_t lds_bytes);
 size_t batch_lds_bytes(const BatchParams& bp);
@@ -825,6 +826,7 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, const 
   // the row pass: a wavefront per long row (four per workgroup), a thread per short row
   S.nlong_groups = std::min(kElemBlocks, (H.rlong + kBlock / 64 - 1) / (kBlock / 64));
   S.nrblocks = std::min(kElemBlocks, (nrows - H.rlong + kBlock - 1) / kBlock);
+  S.sgrid = std::max(8, ((int)H.wpanel.size() + 7) / 8 * 8);
   S.wpanel = up(H.wpanel, "upload staged panels");
   S.wchunk = up(H.wchunk, "upload staged panels");
   S.coff = up(H.coff, "upload staged panels");
@@ -2183,12 +2185,11 @@ extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* m
       if (f.done) break;
       const int64_t a0 = f.attempts;
       for (int k = 0; k < S; ++k) {
-        check(hipEventRecord(ev[4 * k], s), "event");
+        set_pass_events(ev[4 * k], ev[4 * k + 1]);
         launch_primal(h->P, s);
-        check(hipEventRecord(ev[4 * k + 1], s), "event");
-        check(hipEventRecord(ev[4 * k + 2], s), "event");
+        set_pass_events(ev[4 * k + 2], ev[4 * k + 3]);
         launch_dual(h->P, s);
-        check(hipEventRecord(ev[4 * k + 3], s), "event");
+        set_pass_events(nullptr, nullptr);
         launch_decide(h->P, s);
       }
       launch_eval(h->P, s);
@@ -2207,10 +2208,12 @@ extern "C" int pdlp_profile_attempts(pdlp_handle* h, int32_t attempts, double* m
       if (active == 0) break;
     }
   } catch (const HipFail& f) {
+    set_pass_events(nullptr, nullptr);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     return fail(h, PDLP_ERR_HIP, hip_msg(f));
   }
+  set_pass_events(nullptr, nullptr);
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   if (timed == 0) return fail(h, PDLP_ERR_STATE, "the solve finished before any attempt could be timed");

@@ -80,7 +80,7 @@ struct StagedCsr {
   int32_t rlong;            // rows [0, rlong) are the long rows
   int32_t nlong_groups;     // phase-2 workgroups of the long rows
   int32_t nrblocks;         // phase-2 workgroups of the short rows (one row per thread)
-  int32_t pad;
+  int32_t sgrid;            // k_stage's workgroups (every work item, a multiple of 8)
   const int32_t* wpanel;    // [nwork] panel of each work item
   const int32_t* wchunk;    // [nwork+1] chunk range of each work item
   const int32_t* coff;      // [nchunk] first entry of each chunk
