@@ -158,7 +158,9 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
   constexpr int kWaves = BS / 64;
   constexpr int kU = 8;   // loads in flight per lane
   for (int w = blockIdx.x; w < S.nwork; w += gridDim.x) {
-    const int c0 = S.wpanel[w] * kStageWidth;
+    if (S.wchunk[2 * w] == S.wchunk[2 * w + 1]) continue;   // a pad slot
+    const int pan = S.wpanel[w];
+    const int c0 = pan * kStageWidth;
     const int nc = min(kStageWidth, S.ncols - c0);
     for (int j0 = 0; j0 < nc; j0 += kU * BS) {
       double g[kU];
@@ -174,8 +176,8 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
       }
     }
     __syncthreads();
-    const int ch1 = S.wchunk[w + 1];
-    int c = S.wchunk[w] + wv;
+    const int ch1 = S.wchunk[2 * w + 1];
+    int c = S.wchunk[2 * w] + wv;
     int len = 0, off = 0, s0 = 0, s1 = 0;
     if (c < ch1) {
       len = S.clen[c];
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
         for (int u = 0; u < kU; ++u)
           if (k + u < len) acc += a[u] * xs[col[u]];
       }
-      if (s0 + lane < s1) part[s0 + lane] = acc;
+      if (s0 + lane < s1) part[(size_t)pan * S.rlong + S.srow[s0 + lane]] = acc;
       c = cn;
       len = nlen;
       off = noff;
@@ -230,9 +232,10 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
 // a thread per row adding the row's sums from the step view's column panels
 // in panel order (a row of one nonzero takes its product directly: equal
 // lengths are numbered by first column, so these gathers run in address
-// order); the last nlong_groups give each long row a wavefront (its lanes add
-// the row's segment sums lane-strided in panel order, then a shuffle tree).
-// Every row runs the epilogue.  One reduction partial per workgroup.
+// order); the last nlong_groups take 64 long rows at a time, each row's
+// segment sums added in four interleaved panel groups and then in group order
+// (consecutive lanes read consecutive entries).  Every row runs the epilogue.
+// One reduction partial per workgroup.
 template <class Op, typename VT>
 __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
   __shared__ double red[AccSize<Op>::RED];
@@ -245,14 +248,36 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
   for (int k = 0; k < AccSize<Op>::N; ++k) acc[k] = 0.0;
   const int nlg = S.nlong_groups, nrb = S.nrblocks;
   if ((int)blockIdx.x >= nrb) {
-    constexpr int kWaves = kBlock / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int r = (blockIdx.x - nrb) * kWaves + wv; r < S.rlong; r += nlg * kWaves) {
+    // 64 long rows per workgroup: wavefront g sums panels g, g + 4, ... of
+    // lane l's row (eight loads in flight), then the four sums are added in
+    // wavefront order
+    __shared__ double lred[kBlock / 64][64];
+    constexpr int kG = kBlock / 64;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    for (int r0 = (blockIdx.x - nrb) * 64; r0 < S.rlong; r0 += nlg * 64) {
+      const int r = r0 + lane;
       double sum = 0.0;
-      const int q1 = S.row_seg[r + 1];
-      for (int q = S.row_seg[r] + lane; q < q1; q += 64) sum += S.part[S.slot_seg[q]];
-      sum = wave_sum(sum);
-      if (lane == 0) op.epi(r, &sum, acc);
+      if (r < S.rlong) {
+        const double* __restrict__ col = S.part + r;
+        int q = grp;
+        for (; q + 7 * kG < S.npan; q += 8 * kG) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(q + u * kG) * S.rlong];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; q < S.npan; q += kG) sum += col[(size_t)q * S.rlong];
+      }
+      lred[grp][lane] = sum;
+      __syncthreads();
+      if (grp == 0 && r < S.rlong) {
+        double t = lred[0][lane];
+#pragma unroll
+        for (int g2 = 1; g2 < kG; ++g2) t += lred[g2][lane];
+        op.epi(r, &t, acc);
+      }
+      __syncthreads();
     }
   } else {
     const PanelCsr& Q = M.pan;

@@ -229,7 +229,8 @@ HostPanels build_panels(const int32_t* rp, const int32_t* ci, int nrows, int nco
 struct HostStaged {
   int32_t rlong = 0, nseg = 0;
   int64_t nnz_long = 0, nent = 0;
-  std::vector<int32_t> wpanel, wchunk, coff, clen, cseg, perm, row_seg, slot_seg;
+  int32_t npan = 0;
+  std::vector<int32_t> wpanel, wchunk, coff, clen, cseg, perm, srow;
   std::vector<uint16_t> pci;   // column relative to the panel (kStageWidth <= 65536)
 };
 
@@ -293,22 +294,24 @@ HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int nco
   chunk0[(size_t)np] = (int32_t)H.coff.size();
   H.cseg.push_back(H.nseg);
   H.nent = ent;
-  // every long row's segment ids in panel order (its slots), then its entries in place
+  // each segment's row; every long row's entries in place (segments in panel order)
+  H.npan = np;
+  H.srow.assign((size_t)std::max(H.nseg, 1), 0);
   std::vector<std::vector<int32_t>> rowsegs((size_t)rl);
   for (int p = 0; p < np; ++p)
-    for (size_t i = 0; i < ps[(size_t)p].size(); ++i)
-      rowsegs[(size_t)ps[(size_t)p][i].row].push_back((int32_t)(sbase[(size_t)p] + (int64_t)i));
+    for (size_t i = 0; i < ps[(size_t)p].size(); ++i) {
+      const int32_t sid = (int32_t)(sbase[(size_t)p] + (int64_t)i);
+      rowsegs[(size_t)ps[(size_t)p][i].row].push_back(sid);
+      H.srow[(size_t)sid] = ps[(size_t)p][i].row;
+    }
   H.perm.assign((size_t)std::max<int64_t>(ent, 1), -1);
   H.pci.assign((size_t)std::max<int64_t>(ent, 1), 0);
-  H.row_seg.assign((size_t)rl + 1, 0);
   std::vector<int64_t> at((size_t)np);
   for (int r = 0; r < rl; ++r) {
     for (int32_t sid : rowsegs[(size_t)r]) {
       const int p = (int)(std::upper_bound(sbase.begin(), sbase.end(), (int64_t)sid) - sbase.begin()) - 1;
       at[(size_t)p] = seg_at[(size_t)sid];
-      H.slot_seg.push_back(sid);
     }
-    H.row_seg[(size_t)r + 1] = (int32_t)H.slot_seg.size();
     for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
       const int p = ci[e] / kStageWidth;
       const int64_t pos = at[(size_t)p];
@@ -318,8 +321,8 @@ HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int nco
     }
   }
   // work items: the smallest item size T whose per-panel item counts
-  // ceil(entries / T) (at most one per chunk) add up to at most `items`;
-  // each panel's chunks are then cut into that many runs of about equal entries
+  // ceil(entries / T) (at most one per chunk) add up to at most `cap`; each
+  // panel's chunks are then cut into that many runs of about equal entries
   std::vector<int64_t> ptot((size_t)np, 0);
   for (int p = 0; p < np; ++p) {
     const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
@@ -329,31 +332,71 @@ HostStaged build_staged(const int32_t* rp, const int32_t* ci, int nrows, int nco
     const int64_t nc = chunk0[(size_t)p + 1] - chunk0[(size_t)p];
     return std::min<int64_t>(nc, (ptot[(size_t)p] + T - 1) / T);
   };
-  int64_t lo = 1, hi = std::max<int64_t>(ent, 1);
-  while (lo < hi) {
-    const int64_t T = lo + (hi - lo) / 2;
-    int64_t tot_items = 0;
-    for (int p = 0; p < np; ++p) tot_items += count_for(T, p);
-    if (tot_items <= std::max(items, np)) hi = T;
-    else lo = T + 1;
-  }
-  H.wchunk.push_back(0);
-  for (int p = 0; p < np; ++p) {
-    const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
-    if (a == b) continue;
-    const int64_t e0 = H.coff[(size_t)a];
-    const int64_t tot = ptot[(size_t)p];
-    const int64_t per_panel = std::max<int64_t>(1, count_for(lo, p));
-    int64_t k = 1;
-    for (int32_t c = a; c < b; ++c) {
-      const int64_t done = (int64_t)H.coff[(size_t)c] - e0 + (int64_t)kStageLanes * H.clen[(size_t)c];
-      if (c + 1 == b || (k < per_panel && done * per_panel >= tot * k)) {
-        H.wpanel.push_back(p);
-        H.wchunk.push_back(c + 1);
-        ++k;
+  struct Item {
+    int32_t p, a, b;   // panel, chunk range
+  };
+  auto cut = [&](int cap) {
+    int64_t lo = 1, hi = std::max<int64_t>(ent, 1);
+    while (lo < hi) {
+      const int64_t T = lo + (hi - lo) / 2;
+      int64_t tot_items = 0;
+      for (int p = 0; p < np; ++p) tot_items += count_for(T, p);
+      if (tot_items <= std::max(cap, np)) hi = T;
+      else lo = T + 1;
+    }
+    std::vector<Item> it;
+    for (int p = 0; p < np; ++p) {
+      const int32_t a = chunk0[(size_t)p], b = chunk0[(size_t)p + 1];
+      if (a == b) continue;
+      const int64_t e0 = H.coff[(size_t)a];
+      const int64_t tot = ptot[(size_t)p];
+      const int64_t per_panel = std::max<int64_t>(1, count_for(lo, p));
+      int64_t k = 1;
+      int32_t start = a;
+      for (int32_t c = a; c < b; ++c) {
+        const int64_t done = (int64_t)H.coff[(size_t)c] - e0 + (int64_t)kStageLanes * H.clen[(size_t)c];
+        if (c + 1 == b || (k < per_panel && done * per_panel >= tot * k)) {
+          it.push_back(Item{p, start, c + 1});
+          start = c + 1;
+          ++k;
+        }
       }
     }
+    return it;
+  };
+  // workgroups are dispatched round-robin over the 8 XCDs (workgroup i on
+  // XCD i % 8): all items of a panel go to one XCD, whose L2 then gathers
+  // that panel's segment-sum stores (the panels dealt to the XCDs by item
+  // count, largest first); slot 8k + x holds XCD x's k-th item, empty
+  // slots pad the shorter queues, at most `items` slots in all
+  std::vector<std::vector<Item>> q(8);
+  for (int cap = std::max(items, 8);; cap -= 8) {
+    const std::vector<Item> it = cut(cap);
+    std::vector<int> cnt_p((size_t)np, 0), order;
+    for (const Item& x : it) cnt_p[(size_t)x.p]++;
+    for (int p = 0; p < np; ++p)
+      if (cnt_p[(size_t)p]) order.push_back(p);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt_p[(size_t)a] > cnt_p[(size_t)b]; });
+    std::vector<int> bin((size_t)np, 0), load(8, 0);
+    for (int p : order) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      bin[(size_t)p] = x;
+      load[(size_t)x] += cnt_p[(size_t)p];
+    }
+    for (auto& v : q) v.clear();
+    for (const Item& x : it) q[(size_t)bin[(size_t)x.p]].push_back(x);
+    const int mx = *std::max_element(load.begin(), load.end());
+    if (8 * mx <= std::max(items, 8) || cap <= 8) break;
   }
+  size_t depth = 0;
+  for (const auto& v : q) depth = std::max(depth, v.size());
+  for (size_t k = 0; k < depth; ++k)
+    for (int x = 0; x < 8; ++x) {
+      const Item e = k < q[(size_t)x].size() ? q[(size_t)x][k] : Item{0, 0, 0};
+      H.wpanel.push_back(e.p);
+      H.wchunk.push_back(e.a);
+      H.wchunk.push_back(e.b);
+    }
   return H;
 }
 
@@ -823,17 +866,17 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, const 
   S.ncols = ncols;
   S.nseg = H.nseg;
   S.rlong = H.rlong;
-  // the row pass: a wavefront per long row (four per workgroup), a thread per short row
-  S.nlong_groups = std::min(kElemBlocks, (H.rlong + kBlock / 64 - 1) / (kBlock / 64));
+  // the row pass: 64 long rows per workgroup, a thread per short row
+  S.nlong_groups = std::min(kElemBlocks, (H.rlong + 63) / 64);
+  S.npan = H.npan;
   S.nrblocks = std::min(kElemBlocks, (nrows - H.rlong + kBlock - 1) / kBlock);
-  S.sgrid = std::max(8, ((int)H.wpanel.size() + 7) / 8 * 8);
+  S.sgrid = std::max(8, ((int)H.wpanel.size() + 7) / 8 * 8);   // (a multiple of 8 already)
   S.wpanel = up(H.wpanel, "upload staged panels");
   S.wchunk = up(H.wchunk, "upload staged panels");
   S.coff = up(H.coff, "upload staged panels");
   S.clen = up(H.clen, "upload staged panels");
   S.cseg = up(H.cseg, "upload staged panels");
-  S.row_seg = up(H.row_seg, "upload staged panels");
-  S.slot_seg = up(H.slot_seg, "upload staged panels");
+  S.srow = up(H.srow, "upload staged panels");
   S.pci = up(H.pci, "upload staged panels");
   const int64_t ne = std::max<int64_t>(H.nent, 1);
   int32_t* perm = h->dalloc<int32_t>((size_t)ne);
@@ -845,7 +888,10 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, const 
   }
   S.pv = pv;
   S.pvf = pvf;
-  S.part = h->dalloc<double>((size_t)H.nseg + 1);
+  // the dense segment sums: zero once here; a (row, panel) without nonzeros is never written
+  const size_t dense = std::max<size_t>((size_t)H.npan * (size_t)H.rlong, 1);
+  S.part = h->dalloc<double>(dense);
+  check(hipMemsetAsync(S.part, 0, dense * sizeof(double), s), "clear staged segment sums");
   // the short rows' column panels (phase-1 blocks of kTile nonzeros)
   PanelCsr& Q = h->stg_pan[which];
   Q = PanelCsr{};
@@ -871,6 +917,13 @@ static void upload_staged(pdlp_handle* h, int which, const HostStaged& H, const 
   }
   check(hipStreamSynchronize(s), "staged panels sync");
   h->has_stg[which] = H.nseg > 0;
+}
+
+// The staged layout keeps its segment sums dense (panels x long rows); it
+// is built only where most (long row, panel) pairs hold nonzeros, as on
+// power-law LPs whose few long rows span every panel.
+static bool staged_dense_ok(const HostStaged& H) {
+  return (int64_t)H.npan * H.rlong <= 4 * (int64_t)H.nseg + (1 << 20);
 }
 
 // Mean duration (ms) of the step pass over K (which = 0, the dual step) or K'
@@ -1590,7 +1643,7 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
         const int64_t nl = leading_long_nnz(H.rp.data(), m, kStageMinLen);
         if (force_k || 2 * nl >= nnz) {
           HostStaged HS = build_staged(H.rp.data(), H.ci.data(), m, n, kStageMinLen, h->persist_grid / 8);
-          upload_staged(h, 0, HS, H.rp.data(), H.ci.data(), m, n, h->ci, h->val, h->valf);
+          if (staged_dense_ok(HS)) upload_staged(h, 0, HS, H.rp.data(), H.ci.data(), m, n, h->ci, h->val, h->valf);
         }
       }
       if (force_kt || auto_kt) {
@@ -1599,7 +1652,8 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
           std::vector<int32_t> hciT((size_t)std::max<int64_t>(nnz, 1));
           if (nnz) check(hipMemcpy(hciT.data(), h->ciT, (size_t)nnz * 4, hipMemcpyDeviceToHost), "read K' columns");
           HostStaged HS = build_staged(hrpT.data(), hciT.data(), n, m, kStageMinLen, h->persist_grid / 8);
-          upload_staged(h, 1, HS, hrpT.data(), hciT.data(), n, m, h->ciT, h->valT, h->valTf);
+          if (staged_dense_ok(HS))
+            upload_staged(h, 1, HS, hrpT.data(), hciT.data(), n, m, h->ciT, h->valT, h->valTf);
         }
       }
     }
@@ -1965,7 +2019,7 @@ extern "C" int pdlp_solve_noalloc(pdlp_handle* h) {
     if ((M.layout == 1 || V.layout == 1) && M.pan.part)
       add(&M.pan.part, 2 * (size_t)std::max(M.pan.nseg, 1), V.layout == 1 ? &V.pan.part : nullptr);
     if (V.layout == 3) {
-      add(&V.stg.part, (size_t)V.stg.nseg + 1);
+      add(&V.stg.part, std::max<size_t>((size_t)V.stg.npan * (size_t)V.stg.rlong, 1));
       if (V.pan.part) add(&V.pan.part, (size_t)std::max(V.pan.nseg, 1));   // the short rows' panel sums
     }
   }

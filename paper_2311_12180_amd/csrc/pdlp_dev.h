@@ -68,8 +68,9 @@ struct PanelCsr {
 // cache line from memory for nearly every nonzero; rows of one nonzero (their
 // gathers run in address order) are left out.  Phase 2 (k_stage_rows): a
 // thread per short row adds its panel sums in panel order (or takes its one
-// product), a wavefront per long row adds its segment sums in panel order;
-// every row runs the epilogue.
+// product), a thread per long row adds its segment sums in panel order (the
+// sums sit panel-major and by row, so consecutive threads read consecutive
+// entries); every row runs the epilogue.
 constexpr int kStageWidth = 16384;   // columns per panel: 128 KB of FP64 in LDS (at most 65536: 16-bit indices)
 constexpr int kStageLanes = 64;      // segments per chunk
 struct StagedCsr {
@@ -82,16 +83,18 @@ struct StagedCsr {
   int32_t nrblocks;         // phase-2 workgroups of the short rows (one row per thread)
   int32_t sgrid;            // k_stage's workgroups (every work item, a multiple of 8)
   const int32_t* wpanel;    // [nwork] panel of each work item
-  const int32_t* wchunk;    // [nwork+1] chunk range of each work item
+  const int32_t* wchunk;    // [2 nwork] chunk range [wchunk[2w], wchunk[2w+1]) of work item w (empty: a pad)
   const int32_t* coff;      // [nchunk] first entry of each chunk
   const int32_t* clen;      // [nchunk] entries per lane (the chunk's longest segment)
   const int32_t* cseg;      // [nchunk+1] first segment of each chunk
   const uint16_t* pci;      // column index relative to the panel (0 on padding)
   const double* pv;         // FP64 values (0 on padding)
   const float* pvf;         // FP32 values (nullptr unless FP32 steps)
-  const int32_t* row_seg;   // [rlong+1] long row r's segments: slot_seg[row_seg[r] .. row_seg[r+1]), in panel order
-  const int32_t* slot_seg;
-  double* part;             // [nseg] segment sums
+  int32_t npan;             // panels
+  int32_t pad2;
+  const int32_t* srow;      // [nseg] the long row of each segment
+  double* part;             // [npan * rlong] segment sums, panel-major and by row inside a panel
+                            // (zero where a row has no nonzero in a panel: never written)
 };
 
 // SELL-64 layout of a step view (layout 4): the rows are cut into chunks of
