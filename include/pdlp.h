@@ -176,15 +176,18 @@ typedef struct {
                                  descending number of nonzeros, equal counts by first column
                                  (after the scaling, so D1, D2 and K~ are unchanged): on LPs with
                                  skewed row lengths the gathers of y and of x then hit the caches
-                                 far more often.  On LPs with 2^20 nonzeros or more it first
-                                 renumbers the columns: sorted by descending number of nonzeros,
-                                 cut into groups of 64, the groups dealt out over the column
-                                 range (16,384-column strides), so that the rows of K' fill
-                                 SELL-64 chunks with little padding while every wide column range
-                                 keeps columns of every count.  2 = rows and columns at any size.  Only the order of floating-point sums
-                                 changes; every vector crossing this interface (x, y, reduced
-                                 costs, D1, D2, K~, warm starts) stays in the caller's order.
-                                 0 = the given order.  Batch handles keep the given order */
+                                 far more often.  On LPs with 2^20 nonzeros or more whose
+                                 columns in the given order would fill 64-column chunks with
+                                 more than 1/8 padding, it first renumbers the columns: sorted
+                                 by descending number of nonzeros, cut into groups of 64, the
+                                 groups dealt out over the column range (16,384-column
+                                 strides), so that the rows of K' fill SELL-64 chunks with
+                                 little padding while every wide column range keeps columns of
+                                 every count.  2 = the same at any size.  Only the order of
+                                 floating-point sums changes; every vector crossing this
+                                 interface (x, y, reduced costs, D1, D2, K~, warm starts) stays
+                                 in the caller's order.  0 = the given order.  Batch handles
+                                 keep the given order */
 } pdlp_options;
 
 typedef struct {

@@ -1251,9 +1251,10 @@ static void scale_problem(pdlp_handle* h) {
   }
 }
 
-// Column renumbering (row_order = 2, or 1 on LPs with 2^20 nonzeros or more):
-// the columns sorted by descending number of nonzeros (equal counts in the
-// given order) are cut into groups of 64, and the groups are dealt out over
+// Column renumbering (row_order = 2, or 1 on LPs with 2^20 nonzeros or more,
+// unless the given order already fills 64-column chunks with at most 1/8
+// padding): the columns sorted by descending number of nonzeros (equal
+// counts in the given order) are cut into groups of 64, and the groups are dealt out over
 // the column range in kStageWidth-wide strides (group i of G goes to the
 // (i mod P)-th run, P = the number of kStageWidth-column panels).  Each run
 // of 64 columns then has (nearly) equal counts -- the SELL-64 chunks of K~'
@@ -1269,6 +1270,17 @@ static void renumber_cols(pdlp_handle* h, HostLP& H) {
   if (!(ro == 2 || (ro == 1 && nnz >= (1 << 20))) || n < 2) return;
   std::vector<int32_t> cnt((size_t)n, 0);
   for (int64_t e = 0; e < nnz; ++e) cnt[(size_t)H.ci[(size_t)e]]++;
+  {
+    // the given order already fills 64-column chunks with at most 1/8
+    // padding (e.g. equal counts): keep it
+    int64_t padded = 0;
+    for (int32_t j0 = 0; j0 < n; j0 += 64) {
+      int32_t mx = 0;
+      for (int32_t j = j0; j < std::min(n, j0 + 64); ++j) mx = std::max(mx, cnt[(size_t)j]);
+      padded += (int64_t)64 * mx;
+    }
+    if (padded * 8 <= nnz * 9) return;
+  }
   std::vector<int32_t> perm((size_t)n);
   for (int32_t j = 0; j < n; ++j) perm[(size_t)j] = j;
   std::stable_sort(perm.begin(), perm.end(),
