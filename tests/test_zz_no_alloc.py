@@ -5,9 +5,10 @@ Both run the same kernels in the same order on the same data, so the bar is
 bitwise: x, y, reduced costs and the counters.  Two calls of the new entry
 point in a row, the second on a smaller LP (the scratch keeps the first
 call's contents, which the second must not see): a 20,000 x 40,000 skewed LP
-with LDS-staged step passes of K and column panels for K', then a 40 x 60
-LP with every bound and row type on column panels with the normalized-gap
-restarts (its partial sums too).  Infeasibility detection is on in both (its
+with the headline LP's layouts (LDS-staged step passes of K, their dense
+segment sums and the short rows' panel sums; SELL-64 passes of K'), then a
+40 x 60 LP with every bound and row type on column panels with the
+normalized-gap restarts (its partial sums too).  Infeasibility detection is on in both (its
 partials as well)."""
 import numpy as np
 import pytest
@@ -29,7 +30,7 @@ def P():
 def test_noalloc_matches_solve_on_two_calls_in_a_row(P):
     cases = [
         (lpgen.skewed_lp(3, m=20000, n=40000, nnz_target=400000, cap=8000),
-         dict(eps_rel=1e-6, spmv_layout=35, spmv_layout_kt=5)),
+         dict(eps_rel=1e-6, spmv_layout=35, spmv_layout_kt=64)),
         (lpgen.mixed_lp(1), dict(eps_rel=1e-6, spmv_layout=1, restart_metric=1)),
     ]
     handles, ref = [], []
@@ -40,7 +41,7 @@ def test_noalloc_matches_solve_on_two_calls_in_a_row(P):
             P.pdlp_solve(h)
             ref.append(P.pdlp_get_solution(h))
         info = P.pdlp_get_solution(handles[0])[3]
-        assert (info["layout_k"], info["layout_kt"]) == (35, 5)
+        assert (info["layout_k"], info["layout_kt"]) == (35, 64)
         for k, (p, _) in enumerate(cases):
             P.pdlp_solve_noalloc(handles[k])
             x, y, rc, I = P.pdlp_get_solution(handles[k])
