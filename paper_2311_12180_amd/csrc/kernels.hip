@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
       if (e - b <= 1) {
         if (e > b) {
           double g;
-          op.gather(M.ci[b], &g);
-          sum = (double)vals[b] * g;
+          op.gather(__builtin_nontemporal_load(M.ci + b), &g);
+          sum = (double)__builtin_nontemporal_load(vals + b) * g;
         }
       } else {
         for (int q = Q.row_seg[r]; q < Q.row_seg[r + 1]; ++q) sum += Q.part[Q.slot_seg[q]];
@@ -309,7 +309,9 @@ __global__ __launch_bounds__(kBlock) void k_stage_rows(Params p) {
 // SELL-64 pass (layout 4) on a persistent grid: wavefront w of the grid
 // takes chunks w, w + (waves of the grid), ...; each lane sums its row's
 // entries in stored order (coalesced loads of the lane-interleaved entries,
-// kU of them in flight) and runs the epilogue.  With HOT, the workgroup first
+// kU of them in flight, nontemporal: the matrix is read once per pass, and
+// kept out of the caches it leaves them to the vectors) and runs the
+// epilogue.  With HOT, the workgroup first
 // copies the leading entries of the NV gathered vectors into LDS (kSellHot / NV
 // of each, at most S.hot), and gathers below that read the copy.  One
 // reduction partial per workgroup.
@@ -364,8 +366,8 @@ __global__ __launch_bounds__(BS) void k_sell(Params p) {
 #pragma unroll
       for (int u = 0; u < kU; ++u)
         if (k0 + u < len) {
-          col[u] = sci[base + (k0 + u) * 64];
-          a[u] = (double)vals[base + (k0 + u) * 64];
+          col[u] = __builtin_nontemporal_load(sci + base + (k0 + u) * 64);
+          a[u] = (double)__builtin_nontemporal_load(vals + base + (k0 + u) * 64);
         }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
