@@ -154,7 +154,8 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
   double* __restrict__ part = S.part;
   const VT* __restrict__ vals = pick<VT>(S.pv, S.pvf);
   const uint16_t* __restrict__ pci = S.pci;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform: scalar chunk loop
   constexpr int kWaves = BS / 64;
   constexpr int kU = 8;   // loads in flight per lane
   for (int w = blockIdx.x; w < S.nwork; w += gridDim.x) {
@@ -178,43 +179,47 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
     __syncthreads();
     const int ch1 = S.wchunk[2 * w + 1];
     int c = S.wchunk[2 * w] + wv;
-    int len = 0, off = 0, s0 = 0, s1 = 0;
+    int len = 0, off = 0, s0 = 0, s1 = 0, row = 0;
     if (c < ch1) {
       len = S.clen[c];
       off = S.coff[c];
       s0 = S.cseg[c];
       s1 = S.cseg[c + 1];
+      if (s0 + lane < s1) row = S.srow[s0 + lane];
     }
     while (c < ch1) {
       const int cn = c + kWaves;
-      int nlen = 0, noff = 0, ns0 = 0, ns1 = 0;
+      int nlen = 0, noff = 0, ns0 = 0, ns1 = 0, nrow = 0;
       if (cn < ch1) {
         nlen = S.clen[cn];
         noff = S.coff[cn];
         ns0 = S.cseg[cn];
         ns1 = S.cseg[cn + 1];
+        if (ns0 + lane < ns1) nrow = S.srow[ns0 + lane];
       }
       const int base = off + lane;
       double acc = 0.0;
       for (int k = 0; k < len; k += kU) {
+        // (len is wave-uniform: the guards are scalar branches, no load past the end)
         int col[kU];
         double a[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int kk = k + u < len ? k + u : len - 1;   // past the end: the last entry again (in bounds)
-          col[u] = __builtin_nontemporal_load(pci + base + kk * kStageLanes);
-          a[u] = (double)__builtin_nontemporal_load(vals + base + kk * kStageLanes);
-        }
+        for (int u = 0; u < kU; ++u)
+          if (k + u < len) {
+            col[u] = __builtin_nontemporal_load(pci + base + (k + u) * kStageLanes);
+            a[u] = (double)__builtin_nontemporal_load(vals + base + (k + u) * kStageLanes);
+          }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
           if (k + u < len) acc += a[u] * xs[col[u]];
       }
-      if (s0 + lane < s1) part[(size_t)pan * S.rlong + S.srow[s0 + lane]] = acc;
+      if (s0 + lane < s1) part[(size_t)pan * S.rlong + row] = acc;
       c = cn;
       len = nlen;
       off = noff;
       s0 = ns0;
       s1 = ns1;
+      row = nrow;
     }
     __syncthreads();   // the next work item rewrites xs
   }
