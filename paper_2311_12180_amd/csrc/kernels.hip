@@ -201,17 +201,19 @@ __global__ __launch_bounds__(BS) void k_stage(Params p) {
       double acc = 0.0;
       for (int k = 0; k < len; k += kU) {
         // (len is wave-uniform: the guards are scalar branches, no load past the end)
+        // (values kept as loaded and widened in the sum: a conversion next to
+        // its load would make each guarded load wait for itself)
         int col[kU];
-        double a[kU];
+        VT a[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u)
           if (k + u < len) {
             col[u] = __builtin_nontemporal_load(pci + base + (k + u) * kStageLanes);
-            a[u] = (double)__builtin_nontemporal_load(vals + base + (k + u) * kStageLanes);
+            a[u] = __builtin_nontemporal_load(vals + base + (k + u) * kStageLanes);
           }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
-          if (k + u < len) acc += a[u] * xs[col[u]];
+          if (k + u < len) acc += (double)a[u] * xs[col[u]];
       }
       if (s0 + lane < s1) part[(size_t)pan * S.rlong + row] = acc;
       c = cn;
@@ -367,12 +369,13 @@ __global__ __launch_bounds__(BS) void k_sell(Params p) {
     for (int k = 0; k < NV; ++k) sum[k] = 0.0;
     for (int k0 = 0; k0 < len; k0 += kU) {
       int col[kU];
-      double a[kU], g[kU][NV];
+      VT a[kU];   // widened in the sum (see k_stage)
+      double g[kU][NV];
 #pragma unroll
       for (int u = 0; u < kU; ++u)
         if (k0 + u < len) {
           col[u] = __builtin_nontemporal_load(sci + base + (k0 + u) * 64);
-          a[u] = (double)__builtin_nontemporal_load(vals + base + (k0 + u) * 64);
+          a[u] = __builtin_nontemporal_load(vals + base + (k0 + u) * 64);
         }
 #pragma unroll
       for (int u = 0; u < kU; ++u)
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(BS) void k_sell(Params p) {
       for (int u = 0; u < kU; ++u)
         if (k0 + u < len) {
 #pragma unroll
-          for (int k = 0; k < NV; ++k) sum[k] += a[u] * g[u][k];
+          for (int k = 0; k < NV; ++k) sum[k] += (double)a[u] * g[u][k];
         }
     }
     const int r = c * 64 + lane;
