@@ -112,7 +112,9 @@ typedef struct {
                                  on SELL-64 chunks -- 64 consecutive rows stored
                                  lane-interleaved, one row per lane, zero-padded to the chunk's
                                  longest row (built automatically when the padding stays within
-                                 1/8; with row_order the rows of K' come by descending length) --
+                                 1/8, the matrix gives at least four chunks per CU and no row is
+                                 longer than 16 times the mean plus 64; with row_order the rows
+                                 of K' come by descending length) --
                                  in workgroups of 1024 or 512 threads that first copy the
                                  leading 8192 entries of the gathered vector into LDS (64, 80),
                                  or of 256 threads without that copy (96); the evaluation passes

@@ -1670,11 +1670,21 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
       }
     }
     // the SELL-64 step layouts: when a matrix's rows, in their device
-    // numbering, fill chunks of 64 rows with at most 1/8 padding (under the
-    // size rule of the automatic choice), or for any size when forced
+    // numbering, fill chunks of 64 rows with at most 1/8 padding, give at
+    // least four chunks per CU, and none is longer than 16 times the mean
+    // (plus 64: one lane sums a whole row, so a long row would hold its
+    // chunk's wavefront long after the others), under the size rule of the
+    // automatic choice, or for any size when forced
+    auto balanced = [&](const int32_t* rp, int nrows) {
+      if ((int64_t)nrows < (int64_t)64 * 4 * std::max(1, h->persist_grid / 8)) return false;
+      int32_t mx = 0;
+      for (int r = 0; r < nrows; ++r) mx = std::max(mx, rp[r + 1] - rp[r]);
+      return (int64_t)mx <= 16 * (nnz / std::max(nrows, 1)) + 64;
+    };
     {
       const bool force_k = mode_k >= 64, force_kt = mode_kt >= 64;
-      const bool auto_k = mode_k == -1 && nnz >= (1 << 20), auto_kt = mode_kt == -1 && nnz >= (1 << 20);
+      const bool auto_k = mode_k == -1 && nnz >= (1 << 20) && balanced(H.rp.data(), m);
+      const bool auto_kt = mode_kt == -1 && nnz >= (1 << 20) && balanced(hrpT.data(), n);
       if (force_k || auto_k) {
         HostSell HS = build_sell(H.rp.data(), H.ci.data(), m);
         if (HS.nent >= 0 && (force_k || HS.nent * 8 <= nnz * 9)) upload_sell(h, 0, HS, n, h->val, h->valf);
