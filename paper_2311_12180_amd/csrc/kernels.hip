@@ -764,8 +764,9 @@ void launch_eval(const Params& p, hipStream_t s) {
     }
   }
   hipLaunchKernelGGL(k_restart_x, dim3(ge), dim3(kBlock), 0, s, p);
-  if (p.use_f32) launch_op<RestartYOp, float>(p, p.K, s);
-  else launch_op<RestartYOp, double>(p, p.K, s);
+  // K~x of the restart point: one gathered vector, like the dual step, so it
+  // takes the dual step's view (and its matrix precision)
+  launch_view<RestartYOp, 0>(p, s);
 }
 
 void launch_init(const Params& p, const double* xs, const double* ys, hipStream_t s) {
