@@ -45,13 +45,22 @@ def log(*a):
 STEP_SOURCES = ("pdlp_dev.h", "pdlp_ops.h", "kernels.hip", "setup.hip", "pdlp_api.cpp")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank lines (string literals here
+    hold no comment markers), so that a comment edit keeps the hash."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def step_kernels_hash() -> str:
-    """sha256 prefix over the sources the single-LP step kernels and their
-    matrix layout are built from."""
+    """sha256 prefix over the code (comments dropped) of the sources the
+    single-LP step kernels and their matrix layout are built from."""
     import hashlib
     h = hashlib.sha256()
     for name in STEP_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2311_12180_amd", "csrc", name), "rb").read())
+        h.update(_code_only(open(os.path.join(ROOT, "paper_2311_12180_amd", "csrc", name)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -4,8 +4,8 @@
 // (no atomics on values, so results are bitwise reproducible run to run).
 // Each pass over a matrix is an "op": what is gathered per nonzero, and what
 // the row epilogue does with the row sums (the PDHG updates of eq. (pdhg),
-// the eq. (kkt) residuals, the restart, the output).  An op runs in one of two
-// layouts, chosen per matrix by timing at create:
+// the eq. (kkt) residuals, the restart, the output).  An op runs in the
+// layout chosen per matrix by timing at create; the general two:
 //   fused  : row blocks -- runs of short rows whose nonzeros (at most kTile)
 //            are streamed once, coalesced, into LDS as products and summed per
 //            row by a power-of-two group of lanes, or one long row swept by
@@ -14,8 +14,9 @@
 //            serving panel i % 8 only (one XCD per panel, so the gathered
 //            slice of the vector stays in that XCD's L2), phase 2 adds each
 //            row's segment sums in panel order and runs the epilogue.
-// The step passes may also take an LDS-staged panel layout (long rows) or a
-// SELL-64 layout (one row per lane), both described at their kernels.
+// The step passes may also take an LDS-staged panel layout (long rows), and
+// the passes over a matrix a SELL-64 layout (one row per lane), both
+// described at their kernels.
 // No workgroup reads another workgroup's results inside a launch: reductions
 // leave one partial per workgroup and a single-workgroup kernel after the
 // launch adds them in a fixed order.

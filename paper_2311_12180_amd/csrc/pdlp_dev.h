@@ -61,16 +61,17 @@ struct PanelCsr {
 // panel (16 bits).  Phase 1 (k_stage): a work item (one workgroup) is a run of one
 // panel's chunks; it copies the panel's slice of the gathered vector into LDS
 // once, then each wavefront sums whole chunks (coalesced loads, every gather
-// an LDS read, no barrier) and stores one sum per segment.  The short rows
-// take column panels of their own, one per XCD (the step view's PanelCsr,
-// summed by k_seg): each XCD then gathers from one eighth of the vector, which
-// stays in its L2, where random gathers from the whole vector would pull a
-// cache line from memory for nearly every nonzero; rows of one nonzero (their
-// gathers run in address order) are left out.  Phase 2 (k_stage_rows): a
-// thread per short row adds its panel sums in panel order (or takes its one
-// product), a thread per long row adds its segment sums in panel order (the
-// sums sit panel-major and by row, so consecutive threads read consecutive
-// entries); every row runs the epilogue.
+// an LDS read, no barrier) and stores one sum per segment, at [panel][row]
+// of a dense array (a panel's items run on one XCD, whose L2 merges those
+// stores).  The short rows take column panels of their own, one per XCD (the
+// step view's PanelCsr), summed by the same workgroups after their items:
+// each XCD then gathers from one eighth of the vector, which stays in its L2,
+// where random gathers from the whole vector would pull a cache line from
+// memory for nearly every nonzero; rows of one nonzero (their gathers run in
+// address order) are left out.  Phase 2 (k_stage_rows): a thread per short
+// row adds its panel sums in panel order (or takes its one product); 64 long
+// rows per workgroup add their dense segment sums (consecutive lanes read
+// consecutive entries); every row runs the epilogue.
 constexpr int kStageWidth = 16384;   // columns per panel: 128 KB of FP64 in LDS (at most 65536: 16-bit indices)
 constexpr int kStageLanes = 64;      // segments per chunk
 struct StagedCsr {
