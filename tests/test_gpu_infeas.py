@@ -140,15 +140,18 @@ def test_certificates_match_oracle(P, orc, kind, arg, every):
         assert d <= bars.bar(spread, 1e-8), (d, spread)
 
 
-@pytest.mark.parametrize("layout,prec", [(1, 0), (2, 0), (0, 1), (9, 1)])
+@pytest.mark.parametrize("layout,prec", [(1, 0), (2, 0), (0, 1), (9, 1), (64, 0), (80, 1), (96, 0)])
 def test_every_layout_and_fp32_matrix(P, orc, layout, prec):
-    """Column panels (two-phase kernels), XCD-remapped row blocks and the
-    FP32 matrix compute the same certificates."""
+    """Column panels (two-phase kernels), XCD-remapped row blocks, SELL-64
+    passes over both matrices (with rows and columns renumbered; their
+    evaluation passes, the certificate tests included, run on the same
+    chunks) and the FP32 matrix compute the same certificates."""
     for kind, arg in (("infeasible", 1), ("unbounded", 2)):
         p = _make(kind, arg)
         opts = dict(eps_rel=1e-8, max_iter=200000, a_precision=prec)
         r = orc.solve(p, **opts)
-        res = P.solve(p, time_limit_s=60.0, spmv_layout=layout, **opts)
+        order = 2 if layout & 64 else 1
+        res = P.solve(p, time_limit_s=60.0, spmv_layout=layout, row_order=order, **opts)
         assert res.status == r.status, (kind, layout, prec)
         _check(p, res.status, res.x, res.y, res.rc, res.info)
 
