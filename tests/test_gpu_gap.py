@@ -104,14 +104,18 @@ def test_gap_value_matches_exact_oracle(P, orc, k, warm):
     assert abs(float(tr["ev_kkt_avg"][0]) - rho) <= 1e-9 * rho
 
 
+@pytest.mark.parametrize("layout", [-1, 80])
 @pytest.mark.parametrize("k", range(len(FAMILIES)))
-def test_first_200_steps_match_oracle(P, orc, k):
+def test_first_200_steps_match_oracle(P, orc, k, layout):
+    """The default layouts, and SELL-64 passes over both matrices (rows and
+    columns renumbered) whose evaluation passes give the gap its products."""
     p = FAMILIES[k]()
     opts = dict(eps_rel=0.0, max_iter=200, restart_metric=1)
     r, sx, sg, stable = _spread(orc, p, opts)
     if not stable:
         pytest.skip("the oracle's own decisions change under renumbering (a near-tie)")
-    h = P.pdlp_create(p, trace=4096, time_limit_s=60.0, **opts)
+    lay = dict(spmv_layout=layout, row_order=2) if layout == 80 else {}
+    h = P.pdlp_create(p, trace=4096, time_limit_s=60.0, **lay, **opts)
     try:
         P.pdlp_solve(h)
         x, y, rc, I = P.pdlp_get_solution(h)
