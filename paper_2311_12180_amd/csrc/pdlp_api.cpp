@@ -427,6 +427,10 @@ struct pdlp_handle {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // the short graph for the end of a step budget: kTailSlots attempt slots
+  // and an evaluation, so that a solve with max_iter ends with few idle slots
+  hipGraph_t graph_tail = nullptr;
+  hipGraphExec_t gexec_tail = nullptr;
   int slots_per_round = 0, rounds = 0;
   double eta0 = 1.0, omega0 = 1.0;
   double probe_ms[2] = {0.0, 0.0};
@@ -535,8 +539,12 @@ struct pdlp_handle {
   void release() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (gexec_tail) (void)hipGraphExecDestroy(gexec_tail);
+    if (graph_tail) (void)hipGraphDestroy(graph_tail);
     gexec = nullptr;
     graph = nullptr;
+    gexec_tail = nullptr;
+    graph_tail = nullptr;
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e), e = nullptr;
     for (Lane& L : lanes_ho) {
@@ -701,6 +709,8 @@ static void fetch(std::vector<T>& dst, const T* src, size_t count, int mem) {
   else check(hipMemcpy(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost), "hipMemcpy(D2H) of the problem");
 }
 
+constexpr int kTailSlots = 8;   // attempt slots of the short graph
+
 static void build_graph(pdlp_handle* h) {
   const int P = h->opt.eval_period;
   h->slots_per_round = P + std::max(2, P / 8);
@@ -716,6 +726,15 @@ static void build_graph(pdlp_handle* h) {
   }
   check(hipStreamEndCapture(h->cap_stream, &h->graph), "hipStreamEndCapture");
   check(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  check(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  for (int s = 0; s < kTailSlots; ++s) {
+    launch_primal(h->P, h->cap_stream);
+    launch_dual(h->P, h->cap_stream);
+    launch_decide(h->P, h->cap_stream);
+  }
+  launch_eval(h->P, h->cap_stream);
+  check(hipStreamEndCapture(h->cap_stream, &h->graph_tail), "hipStreamEndCapture");
+  check(hipGraphInstantiate(&h->gexec_tail, h->graph_tail, nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
 static int elem_grid(int n) {
@@ -1900,26 +1919,37 @@ static int solve_single(pdlp_handle* h, bool use_graph) {
     // accepted steps one graph can take at most: an evaluation falls due after
     // every P accepted steps and the attempt slots idle until it has run
     const int64_t per_graph = (int64_t)h->opt.eval_period * h->rounds;
+    const int64_t per_tail = std::min<int64_t>(kTailSlots, h->opt.eval_period);
     // pipelined polling: launch batch b, then wait for the status copied after
-    // batch b-1.  A batch is left empty (a status read only) while the graphs
-    // in flight could already take the solve to max_iter, so a solve with a
-    // step budget ends with at most the idle slots of its last graph.
+    // batch b-1.  A batch holds up to poll_every graphs while the step budget
+    // left after the graphs in flight (each counted at the most steps it can
+    // take) is positive: the full graph while that budget reaches a full
+    // graph's steps, else the short one; so a solve with a step budget ends
+    // with at most the idle slots of one short graph.
     int pending = -1;  // index of the status buffer of the previous batch
-    int graphs_in[2] = {0, 0};   // graphs launched in the batch of each status buffer
+    int graphs_in[2] = {0, 0};     // graphs launched in the batch of each status buffer
+    int64_t steps_in[2] = {0, 0};  // and the most steps they can take
     const bool done = h->st_host[0]->done != 0;
     int64_t k_seen = h->st_host[0]->k;
-    int64_t in_flight = 0;       // graphs launched after the status k_seen was read
+    int64_t in_flight = 0;       // steps the graphs launched after the status k_seen can take at most
     int cur = 0;
     int64_t last_k = -1;
     int stalls = 0;
     while (!done) {
-      const int nl = (h->opt.max_iter - k_seen <= in_flight * per_graph) ? 0 : per;
-      graphs_in[cur] = nl;
-      in_flight += nl;
-      for (int i = 0; i < nl; ++i) {
-        if (use_graph) {
+      int nl = 0;
+      int64_t steps = 0;
+      for (int i = 0; i < per; ++i) {
+        const int64_t left = h->opt.max_iter - k_seen - in_flight - steps;
+        if (left <= 0) break;
+        ++nl;
+        if (use_graph && left < per_graph) {
+          check(hipGraphLaunch(h->gexec_tail, s), "hipGraphLaunch");
+          steps += per_tail;
+        } else if (use_graph) {
           check(hipGraphLaunch(h->gexec, s), "hipGraphLaunch");
+          steps += per_graph;
         } else {
+          steps += per_graph;
           for (int r = 0; r < h->rounds; ++r) {
             for (int k = 0; k < h->slots_per_round; ++k) {
               launch_primal(h->P, s);
@@ -1931,13 +1961,16 @@ static int solve_single(pdlp_handle* h, bool use_graph) {
           check(hipGetLastError(), "eager launches");
         }
       }
+      graphs_in[cur] = nl;
+      steps_in[cur] = steps;
+      in_flight += steps;
       check(hipMemcpyAsync(h->st_host[cur], h->st, 16, hipMemcpyDeviceToHost, s), "read status");
       check(hipEventRecord(h->ev[cur], s), "hipEventRecord");
       if (pending >= 0) {
         check(hipEventSynchronize(h->ev[pending]), "hipEventSynchronize");
         if (h->st_host[pending]->done) break;
         k_seen = h->st_host[pending]->k;
-        in_flight -= graphs_in[pending];
+        in_flight -= steps_in[pending];
         // a healthy run accepts a step within a few attempts; a batch of graphs
         // without any accepted step means the state is broken
         if (graphs_in[pending] > 0) {
