@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_x(Params p) {
 
 // Single-workgroup reduction of every evaluation partial in a fixed order,
 // then the evaluation decision.
-__global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0_blocks) {
+__global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0_blocks, int n_e1) {
   __shared__ double red[22 * (kDecideBlock / 64)];
   __shared__ double E[42];
   DevState* st = p.st;
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(kDecideBlock) void k_eval_decide(Params p, int n_e0
 #pragma unroll
       for (int k = 0; k < 4; ++k) S[k] += p.partE0[4 * i + k];
     }
-    for (int i = threadIdx.x; i < p.K.nred; i += kDecideBlock) {
+    for (int i = threadIdx.x; i < n_e1; i += kDecideBlock) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) S[4 + k] += p.partE1[10 * i + k];
     }
@@ -750,13 +750,27 @@ void launch_decide(const Params& p, hipStream_t s) {
 void launch_eval(const Params& p, hipStream_t s) {
   const int ge = elem_grid(p.n);
   hipLaunchKernelGGL(k_eval_x, dim3(ge), dim3(kBlock), 0, s, p);
-  launch_op<EvalRowsOp, double>(p, p.K, s);
+  // the rows of K~: on an LDS-staged step view of the FP64 matrix, K~x_bar
+  // and then K~x with the epilogue, a staged pass each (together 0.6 of the
+  // time of one pass gathering both vectors over the evaluation view's column
+  // panels, on a skewed LP of 2e7 nonzeros); otherwise that one pass.  The
+  // partials come one per workgroup of the pass that ran.
+  int n_e1 = p.K.nred;
+  if (p.kxb && p.Ks.layout == 3 && !p.use_f32) {
+    Params q = p;
+    q.K = p.Ks;
+    launch_staged<EvalKxbOp, double>(q, q.K, s);
+    launch_staged<EvalRowsKxbOp, double>(q, q.K, s);
+    n_e1 = p.Ks.nred;
+  } else {
+    launch_op<EvalRowsOp, double>(p, p.K, s);
+  }
   launch_op<EvalColsOp, double>(p, p.KT, s);
   if (p.infeas) {
     launch_op<InfeasRowsOp, double>(p, p.K, s);
     launch_op<InfeasColsOp, double>(p, p.KT, s);
   }
-  hipLaunchKernelGGL(k_eval_decide, dim3(1), dim3(kDecideBlock), 0, s, p, ge);
+  hipLaunchKernelGGL(k_eval_decide, dim3(1), dim3(kDecideBlock), 0, s, p, ge, n_e1);
   if (p.gap) {
     const int gn = elem_grid(p.n), gm = elem_grid(p.m);
     for (int ph = 0; ph < kGapPasses + 2; ++ph) {

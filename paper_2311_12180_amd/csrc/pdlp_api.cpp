@@ -1718,6 +1718,8 @@ extern "C" int pdlp_create(const pdlp_problem* p, const pdlp_options* o, void* h
     P.Ks = P.K;
     P.KTs = P.KT;
     alloc_iterates(h);
+    // K~x_bar of the evaluations' split row pass (on an FP64 LDS-staged view of K~)
+    if (h->has_stg[0] && !P.use_f32) P.kxb = h->dalloc<double>((size_t)std::max(m, 1));
     // partials: one per block of either tiling, or per workgroup of the row pass
     // (and per workgroup of the staged layouts' row pass)
     auto stg_red = [&](int w) {

@@ -247,6 +247,9 @@ struct Params {
   double* kxe[2];
   double* ktye[2];
   double* partG;
+  // [m]: K~x_bar of an evaluation whose rows of K~ run as two one-vector
+  // passes on the LDS-staged step view (FP64 matrix); null otherwise
+  double* kxb;
 };
 
 constexpr int32_t kPaused = 16;  // internal status of a batched LP handed to the single-LP kernels

@@ -343,7 +343,9 @@ struct EvalRowsOp {
     g[0] = x[j];
     g[1] = xb[j];
   }
-  __device__ void epi(int i, const double* s, double* acc) const {
+  __device__ void epi(int i, const double* s, double* acc) const { rows(i, s[0], s[1], acc); }
+  // the epilogue of row i given (K~x)_i and (K~x_bar)_i
+  __device__ void rows(int i, double kx, double kxb, double* acc) const {
     const Params& p = *pp;
     const double yi = y[i];
     double yb = yi;
@@ -360,7 +362,7 @@ struct EvalRowsOp {
     const bool ie = p.ineq[i] != 0;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      const double kv = s[it];
+      const double kv = it ? kxb : kx;
       const double yv = it ? yb : yi;
       double r = kv - qi;
       if (ie) r = (qi - kv) > 0.0 ? (qi - kv) : 0.0;
@@ -374,10 +376,32 @@ struct EvalRowsOp {
       acc[8 + it] += gy * gy;
     }
     if (p.gap) {
-      p.kxe[0][i] = s[0];
-      p.kxe[1][i] = s[1];
+      p.kxe[0][i] = kx;
+      p.kxe[1][i] = kxb;
     }
   }
+};
+
+// The same rows of an evaluation in two passes of one gathered vector each,
+// for step views that hold one vector (the LDS-staged panels): first
+// K~x_bar into kxb, then K~x with the epilogue above.
+struct EvalKxbOp {
+  static constexpr int NV = 1, NACC = 0;
+  __device__ static bool idle(const Params&, const DevState* st) { return eval_idle(st); }
+  __device__ static const DevCsr& mat(const Params& p) { return p.K; }
+  __device__ static double* part(const Params&) { return nullptr; }
+  const double* __restrict__ xb;
+  double* __restrict__ kxb;
+  __device__ EvalKxbOp(const Params& p, const DevState*) : xb(p.xbar), kxb(p.kxb) {}
+  __device__ void gather(int j, double* g) const { g[0] = xb[j]; }
+  __device__ void epi(int i, const double* s, double*) const { kxb[i] = s[0]; }
+};
+
+struct EvalRowsKxbOp : EvalRowsOp {
+  static constexpr int NV = 1, NACC = 10;
+  __device__ EvalRowsKxbOp(const Params& p, const DevState* st) : EvalRowsOp(p, st) {}
+  __device__ void gather(int j, double* g) const { g[0] = x[j]; }
+  __device__ void epi(int i, const double* s, double* acc) const { rows(i, s[0], pp->kxb[i], acc); }
 };
 
 // Rows of K~' in an evaluation: K~'y and K~'y_bar (FP64 matrix), lambda =
