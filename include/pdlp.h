@@ -108,7 +108,10 @@ typedef struct {
                                  with two nonzeros or more take eight column panels (one per
                                  XCD), rows of one nonzero are summed directly -- with column
                                  panels on a persistent grid
-                                 for the evaluation passes; or 64, 80, 96: the step pass runs
+                                 for the evaluation passes (with the FP64 matrix, the
+                                 evaluation's rows of K run instead as two staged passes of
+                                 one gathered vector each: K x_bar, then K x with the
+                                 residuals); or 64, 80, 96: the step pass runs
                                  on SELL-64 chunks -- 64 consecutive rows stored
                                  lane-interleaved, one row per lane, zero-padded to the chunk's
                                  longest row (built automatically when the padding stays within
