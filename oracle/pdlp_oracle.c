@@ -818,7 +818,7 @@ int orc_solve(const orc_problem* p, const orc_options* opt, double* x_user, doub
   for (int32_t j = 0; j < n; ++j) x[j] = clampd(0.0, P.l[j], P.u[j]);
   memcpy(x0, x, sizeof(double) * (size_t)n);
 
-  /* Algorithm 1 line 1: step size 1/||K~||_inf, primal weight ||c~|| / ||q~|| */
+  /* Algorithm 1, initialization: step size 1/||K~||_inf, primal weight ||c~|| / ||q~|| */
   double kmax = 0.0;
   for (int64_t q = 0; q < Ks->nnz; ++q) kmax = fabs(Ks->v[q]) > kmax ? fabs(Ks->v[q]) : kmax;
   double eta_hat = kmax > 0.0 ? 1.0 / kmax : 1.0;
