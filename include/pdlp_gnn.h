@@ -6,7 +6,7 @@
  * / pdlp_set_warm_start_batch.  The network, its training and its inference run
  * in HIP kernels for gfx950: 64-wide CSR gathers for the messages and bfloat16
  * MFMA products with FP32 accumulation for the 128 x 64 transforms; FP32 master
- * weights updated by Adam.  The solver itself stays the judge of a prediction:
+ * weights updated by Adam.  The solver's own test decides on a prediction:
  * a warm start changes where Algorithm 1 starts, never its termination test.
  *
  * Network (width H = 64, R = 3 rounds):

@@ -6,7 +6,7 @@
      backward, Adam);
   3. predict (x0, y0, omega0) for held-out LPs and solve them from there; an
      LP whose warm solve does not end OPTIMAL is solved again cold (the cold
-     solver is the fallback and the judge of every prediction).
+     solver is the fallback, and its termination test decides every prediction).
 
 Only the C ABI is used; every numerical step runs in the HIP library."""
 from __future__ import annotations
