@@ -14,9 +14,10 @@
 //            serving panel i % 8 only (one XCD per panel, so the gathered
 //            slice of the vector stays in that XCD's L2), phase 2 adds each
 //            row's segment sums in panel order and runs the epilogue.
-// The step passes may also take an LDS-staged panel layout (long rows), and
-// the passes over a matrix a SELL-64 layout (one row per lane), both
-// described at their kernels.
+// The step passes may also take an LDS-staged panel layout (long rows; with
+// the FP64 matrix the evaluation's rows of K~ then run on it too, as two
+// passes of one gathered vector), and the passes over a matrix a SELL-64
+// layout (one row per lane), both described at their kernels.
 // No workgroup reads another workgroup's results inside a launch: reductions
 // leave one partial per workgroup and a single-workgroup kernel after the
 // launch adds them in a fixed order.
